@@ -1,0 +1,83 @@
+"""Hybrid-transparency composite (paper Sec. 3.3, Eq. pixel_color_computation
+and its helper equation).
+
+The core is the K front-most fragments whose alpha is at least tau_K (the
+second threshold of Sec. 4.2), alpha-blended in exact depth order; every other
+fragment forms the tail, blended without order:
+
+  C = sum_{i<=n} alpha_i T_i c_i + T_{n+1} ((1 - T_tail) c_tail + T_tail c_bg)
+  T_i = prod_{j<i} (1 - alpha_j)
+  c_tail = sum_tail alpha c / sum_tail alpha,  T_tail = prod_tail (1 - alpha)
+
+Readings where the paper is silent: n is the number of actual core members
+(n <= K) and T_{n+1} the transmittance after them; an empty tail contributes
+T_{n+1} c_bg; equal depths are ordered by ascending Gaussian index.
+"""
+from __future__ import annotations
+
+import torch
+
+F64 = torch.float64
+
+
+def composite_pixel(core_alpha, core_colour, tail_alpha, tail_colour, bg):
+    """One pixel, written out term by term. ``core_*`` are in depth order."""
+    C = torch.zeros(3, dtype=F64)
+    T = torch.ones((), dtype=F64)
+    for a, c in zip(core_alpha, core_colour):
+        C = C + a * T * c
+        T = T * (1.0 - a)
+    bg = torch.as_tensor(bg, dtype=F64)
+    A = torch.zeros((), dtype=F64)
+    S = torch.zeros(3, dtype=F64)
+    P = torch.ones((), dtype=F64)
+    for a, c in zip(tail_alpha, tail_colour):
+        A = A + a
+        S = S + a * c
+        P = P * (1.0 - a)
+    X = P * bg
+    if float(A) > 0.0:
+        X = X + (1.0 - P) * S / A
+    return C + T * X
+
+
+def hybrid(alpha, colour, depth, frag, K, tau_core, bg):
+    """Vectorised over pixels: alpha/depth/frag [P,G] (alpha = 0 off the
+    fragments), colour [G,3]. Returns C [P,3] and per-pixel core indices
+    (ordered, [P,min(K,G)], -1 past the n-th) for parity checks."""
+    Pn, G = alpha.shape
+    bg = torch.as_tensor(bg, dtype=F64)
+    eligible = frag & (alpha >= tau_core)
+    kk = min(int(K), G)
+    n = torch.clamp(eligible.sum(1), max=kk)
+    if kk > 0:
+        key = torch.where(eligible, depth.detach(), torch.full_like(depth.detach(), float('inf')))
+        order = torch.sort(key, dim=1, stable=True).indices[:, :kk]          # [P,kk]
+        valid = torch.arange(kk)[None, :] < n[:, None]
+        a_core = alpha.gather(1, order) * valid
+        c_core = colour[order]                                             # [P,kk,3]
+        one_minus = 1.0 - a_core
+        T_incl = torch.cumprod(one_minus, dim=1)
+        T_excl = torch.cat([torch.ones((Pn, 1), dtype=F64), T_incl[:, :-1]], dim=1)
+        core_sum = ((a_core * T_excl)[:, :, None] * c_core).sum(1)
+        T_n1 = T_incl[:, -1]
+        core_mask = torch.zeros((Pn, G), dtype=torch.bool)
+        core_mask.scatter_(1, order, valid)
+        core_ids = torch.where(valid, order, torch.full_like(order, -1))
+    else:
+        core_sum = torch.zeros((Pn, 3), dtype=F64)
+        T_n1 = torch.ones(Pn, dtype=F64)
+        core_mask = torch.zeros((Pn, G), dtype=torch.bool)
+        core_ids = torch.zeros((Pn, 0), dtype=torch.long)
+    tail = frag & ~core_mask
+    a_tail = torch.where(tail, alpha, torch.zeros_like(alpha))
+    A = a_tail.sum(1)
+    S = a_tail @ colour
+    P = torch.prod(torch.where(tail, 1.0 - alpha, torch.ones_like(alpha)), dim=1)
+    has_tail = A > 0
+    A_safe = torch.where(has_tail, A, torch.ones_like(A))
+    c_tail = S / A_safe[:, None]
+    X = torch.where(has_tail[:, None], (1.0 - P)[:, None] * c_tail,
+                    torch.zeros_like(c_tail)) + P[:, None] * bg[None, :]
+    C = core_sum + T_n1[:, None] * X
+    return C, core_ids
