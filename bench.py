@@ -1,0 +1,222 @@
+#!/usr/bin/env python3
+"""Benchmark of the hot path: one step = forward render + L1 loss gradient +
+backward, through the C ABI, on one MI355X.
+
+Default workload: 1M clustered Gaussians (SH degree 3), one 1920x1080
+camera, K = 8, 16x16 tiles, L1 loss against a seeded smooth target. Inputs
+are resident in HBM before timing. Prints ONE JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--workload 1080p|720p|small|stress]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Peaks (MI355X spec sheet): HBM3E 8 TB/s; FP32 vector FMA without packed
+# instructions: 256 CUs x 64 lanes x 2 flop x 2.4 GHz = 78.6 TFLOP/s.
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+
+# Algorithmic float32 flops of the rasterizer (FMA = 2):
+# a candidate pair (tile pixel x tile instance) evaluates d, m, |d|^2, |m|^2
+# and the cutoff test; a fragment adds alpha and its core/tail work.
+FLOPS_PAIR = 35
+FLOPS_FRAG_FWD = 15
+FLOPS_FRAG_BWD = 64
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def workload(name):
+    from paper_2410_08129_amd import scenes
+    if name == "1080p":
+        sc, cams, st = scenes.workload_1080p()
+        desc = "1M clustered Gaussians, SH3, 1920x1080, fov 50, K=8, 16x16 tiles, fwd+bwd (L1 to smooth target)"
+    elif name == "720p":
+        sc, cams, st = scenes.workload_720p()
+        desc = "1M clustered Gaussians, SH3, 1280x720, fov 50, K=8, 16x16 tiles, fwd+bwd (L1 to smooth target)"
+    elif name == "small":
+        sc, cams, st = scenes.workload_small()
+        desc = "4096 uniform Gaussians, SH0, 128x128, fov 60, K=4, 16x16 tiles, fwd+bwd"
+    elif name == "stress":
+        sc, cams, st = scenes.workload_stress()
+        st.tile_w = st.tile_h = 8
+        desc = "6M clustered Gaussians (10% zero-axis, 2% 1e-7-axis), SH3, 3840x2160, fov 70, K=16, 8x8 tiles, fwd+bwd"
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return sc, cams, st, desc
+
+
+def cpu_baseline(sc, cam, st, n_crops=4, size=64):
+    """The FP64 oracle on a bounded sample: forward + autograd backward of
+    seeded 64x64 crops; extrapolated to the full frame by pixel count."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2410_08129_amd import scenes
+    torch.set_num_threads(os.cpu_count() or 1)
+    crops = scenes.random_crops(cam, n_crops, size, seed=5)
+    target = scenes.smooth_target(cam.height, cam.width)
+    t0 = time.perf_counter()
+    for (x0, y0, c) in crops:
+        ps = [torch.tensor(a, dtype=torch.float64, requires_grad=True) for a in sc.arrays()]
+        img = oracle.render.render(*ps, sc.sh_degree, c, st)
+        tgt = torch.tensor(target[:, y0:y0 + size, x0:x0 + size], dtype=torch.float64)
+        loss = (img - tgt).abs().mean()
+        loss.backward()
+    dt = time.perf_counter() - t0
+    per_px = dt / (n_crops * size * size)
+    frame_ms = per_px * cam.width * cam.height * 1e3
+    return dict(value=frame_ms, unit="ms/frame (extrapolated)", cores=torch.get_num_threads(),
+                kind="oracle",
+                sample=f"{n_crops} seeded {size}x{size} crops, fwd + autograd bwd, {dt:.1f} s "
+                       f"total, extrapolated by pixel count to {cam.width}x{cam.height}")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="1080p")
+    ap.add_argument("--tile", type=int, default=0, help="override tile size (8 or 16)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--forward-only", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the renderer runs on a single MI355X).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2410_08129_amd import htgs, scenes
+
+    log(f"bench: workload {args.workload}, generating scene")
+    sc, cams, st, desc = workload(args.workload)
+    if args.tile:
+        st.tile_w = st.tile_h = args.tile
+        desc = desc.replace("16x16 tiles", f"{args.tile}x{args.tile} tiles")
+    cam = cams[0]
+    dev = torch.device("cuda:0")
+    params = [torch.tensor(a, device=dev) for a in sc.arrays()]
+    target = torch.tensor(scenes.smooth_target(cam.height, cam.width), device=dev)
+    n_inst = htgs.count_instances(params, sc.sh_degree, [cam], st)
+    ws = htgs.alloc_workspace(sc.n, [cam], st, n_inst, dev)
+    state = torch.empty(htgs.state_bytes([cam], st) // 4, dtype=torch.float32, device=dev)
+    img = torch.empty((3, cam.height, cam.width), dtype=torch.float32, device=dev)
+    gimg = torch.empty_like(img)
+    grads = [torch.zeros_like(p) for p in params]
+    inv_n = 1.0 / img.numel()
+    log(f"bench: {sc.n} Gaussians, {n_inst} instances, ws {ws.numel() / 2**20:.0f} MiB")
+
+    def step():
+        frame = htgs.forward(params, sc.sh_degree, [cam], st, ws=ws, state=state, images=[img])
+        if args.forward_only:
+            return
+        torch.sub(img, target, out=gimg)
+        gimg.sign_().mul_(inv_n)
+        for g in grads:
+            g.zero_()
+        htgs.backward(params, frame, [gimg], grads=grads)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    flags, n_inst2, n_frag = htgs.read_status(ws, fragments=True)
+    if flags:
+        raise SystemExit(f"status flags {flags} after warm-up")
+    log(f"bench: warm-up done, {n_frag} fragments")
+
+    htgs.profile_enable(True)
+    htgs.profile_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = htgs.profile_read()
+    htgs.profile_enable(False)
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    log(f"bench: {args.steps} steps, {ms_step:.3f} ms/step")
+
+    # Algorithmic work of the rasterizer.
+    keys, vals, _, _ = htgs.export_bins(params, sc.sh_degree, [cam], st, ws)
+    tiles_x = (cam.width + st.tile_w - 1) // st.tile_w
+    tiles_y = (cam.height + st.tile_h - 1) // st.tile_h
+    tx = np.arange(tiles_x)
+    ty = np.arange(tiles_y)
+    pw = np.minimum(st.tile_w, cam.width - tx * st.tile_w)
+    ph = np.minimum(st.tile_h, cam.height - ty * st.tile_h)
+    tile_px = (ph[:, None] * pw[None, :]).reshape(-1)
+    per_tile = np.bincount(keys.astype(np.int64), minlength=tiles_x * tiles_y)
+    pairs = int((per_tile * tile_px).sum())
+
+    stages = {k: dict(ms_per_launch=(v[0] / max(v[1], 1)), launches_per_step=v[1] / args.steps,
+                      ms_per_step=v[0] / args.steps) for k, v in prof.items() if v[1]}
+    work = {
+        "raster_fwd": (FLOPS_PAIR * pairs + FLOPS_FRAG_FWD * n_frag) / 1e12,
+        "raster_bwd": (FLOPS_PAIR * pairs + FLOPS_FRAG_BWD * n_frag) / 1e12,
+    }
+    dom = max(("raster_fwd", "raster_bwd") if not args.forward_only else ("raster_fwd",),
+              key=lambda k: stages.get(k, {}).get("ms_per_step", 0.0))
+    ach = work[dom] / (stages[dom]["ms_per_launch"] * 1e-3)
+    roofline = dict(kernel=dom, bound="alu", achieved=round(ach, 3), peak=round(FP32_PEAK_TFLOPS, 1),
+                    unit="TFLOP/s", frac=round(ach / FP32_PEAK_TFLOPS, 4), traffic=None)
+    # Binning: each radix pass reads and writes key + value once.
+    kb = 2 if (tiles_x * tiles_y) <= 65536 else 4
+    sort_bytes_launch = n_inst * (2 * kb + 8)
+    sort = stages.get("sort")
+    binning = None
+    if sort:
+        gbs = sort_bytes_launch / (sort["ms_per_launch"] * 1e-3) / 1e9
+        binning = dict(kernel="sort_pass", bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS,
+                       unit="GB/s", frac=round(gbs / HBM_PEAK_GBS, 4),
+                       bytes_per_launch=sort_bytes_launch)
+
+    out = {
+        "metric": "fwd+bwd ms/frame at 1080p & 1M Gaussians",
+        "value": round(ms_step, 4),
+        "unit": "ms/frame",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": desc, "gaussians": sc.n, "width": cam.width, "height": cam.height,
+                   "K": st.K, "tile": [st.tile_w, st.tile_h]},
+        "roofline": roofline,
+        "binning_roofline": binning,
+        "stages_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in stages.items()},
+        "instances": n_inst,
+        "fragments": n_frag,
+        "candidate_pairs": pairs,
+        "gaussian_pixels_per_s": sc.n * cam.width * cam.height / (ms_step * 1e-3),
+        "candidate_pairs_per_s": pairs / (ms_step * 1e-3),
+    }
+    if args.workload != "1080p" or args.forward_only:
+        out["metric"] = f"{'fwd' if args.forward_only else 'fwd+bwd'} ms/frame ({args.workload})"
+    if not args.no_cpu_baseline:
+        log("bench: timing the CPU oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(sc, cam, st)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,210 @@
+/*
+ * htgs.h - C ABI of the MI355X perspective-correct hybrid-transparency
+ * Gaussian-splatting renderer (Hahlbohm et al., arXiv 2410.08129).
+ *
+ * The library renders 3D Gaussians by evaluating each one exactly along every
+ * pixel ray (Sec. 3.2: Pluecker coordinates of the ray in normalised splat
+ * space, Eq. rho-pluecker, no matrix inversion) and blends the fragments of a
+ * pixel with hybrid transparency (Sec. 3.3, Eq. pixel_color_computation: the
+ * K front-most fragments with alpha >= tau_K in exact depth order, every other
+ * fragment in an order-independent tail). Tile lists use plain tile-id keys
+ * with no depth sort (Sec. 4.3). The backward pass gives the gradient with
+ * respect to every Gaussian parameter.
+ *
+ * Conventions shared by every entry point
+ *  - Every array argument is a DEVICE pointer to float32 (unless stated),
+ *    C-contiguous, owned by the caller. The library never allocates device
+ *    memory; the caller provides a workspace sized by htgs_workspace_bytes().
+ *  - All device work is enqueued on `stream` (a hipStream_t, NULL = the null
+ *    stream) and is asynchronous, except where a function says it
+ *    synchronises.
+ *  - Return value: HTGS_OK (0) or a negative HTGS_E_* code; argument checks
+ *    run before any device work, so an error return means nothing was
+ *    enqueued. No C++ exception crosses this boundary.
+ *  - Calls that share one workspace on one device must not overlap.
+ */
+#ifndef HTGS_H
+#define HTGS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  HTGS_OK = 0,
+  HTGS_E_INVAL = -1,      /* null pointer, bad size, K out of [0,32], bad tile shape */
+  HTGS_E_WORKSPACE = -2,  /* workspace smaller than htgs_workspace_bytes() with 0 instances */
+  HTGS_E_KEYWIDTH = -3,   /* total tile count exceeds the 32-bit key range */
+  HTGS_E_HIP = -4,        /* a HIP call or kernel launch failed */
+  HTGS_E_OVERFLOW = -5,   /* (status) more instances than the workspace holds */
+  HTGS_E_TOO_MANY_VIEWS = -6
+};
+
+/* Status flags reported by htgs_read_status(). */
+enum {
+  HTGS_STATUS_OVERFLOW = 1u,      /* instance count exceeded the capacity; outputs invalid */
+  HTGS_STATUS_SPIN_TIMEOUT = 2u   /* a cross-workgroup wait gave up; outputs invalid */
+};
+
+#define HTGS_MAX_VIEWS 16
+
+/* Gaussian parameters (Sec. 3.1). n may be 0.
+ *  means          [n,3]  world-space centres
+ *  log_scales     [n,3]  s = exp(log_scale); -INFINITY gives an exact zero axis
+ *  quats          [n,4]  (w,x,y,z), normalised internally, must be non-zero
+ *  opacity_logits [n]    o = sigmoid(logit)
+ *  sh             [n,(sh_degree+1)^2,3]  real SH coefficients, index l*l+l+m,
+ *                 orthonormal basis without the Condon-Shortley phase;
+ *                 colour = max(0, sum k_lm Y_lm(dir) + 0.5), dir = unit vector
+ *                 from the camera centre to the mean. */
+typedef struct htgs_gaussians {
+  int64_t n;
+  int32_t sh_degree; /* 0..3 */
+  int32_t reserved;
+  const float *means;
+  const float *log_scales;
+  const float *quats;
+  const float *opacity_logits;
+  const float *sh;
+} htgs_gaussians;
+
+/* Pinhole camera. world_to_cam is the row-major 3x4 [R|t] (host memory, part
+ * of this struct); camera axes x right, y down, z forward. A view point
+ * (X,Y,Z) lands at window x = fx X/Z + cx, y = fy Y/Z + cy; pixel (i,j) has
+ * its centre at (i+0.5, j+0.5). Gaussians whose view depth is <= z_near are
+ * culled. */
+typedef struct htgs_camera {
+  float world_to_cam[12];
+  float fx, fy, cx, cy;
+  int32_t width, height;
+  float z_near;
+  int32_t reserved;
+} htgs_camera;
+
+/* Renderer settings.
+ *  K          core size, 0..32 (Sec. 3.3; the paper uses 16)
+ *  tau_alpha  minimum alpha of a fragment; gives rho_c = 2 ln(o/tau_alpha) (Sec. 3.2)
+ *  tau_core   minimum alpha for core membership, tau_K (Sec. 4.2, 0.05)
+ *  alpha_max  alpha clamp, alpha = min(alpha_max, o exp(-rho^2/2)), in (0,1)
+ *  bg         background colour c_bg of Eq. pixel_color_computation
+ *  tile_w/h   8x8 or 16x16 pixels
+ *  lds_batch  records staged per batch in the forward; 0 = the tile's pixel count */
+typedef struct htgs_config {
+  int32_t K;
+  float tau_alpha;
+  float tau_core;
+  float alpha_max;
+  float bg[3];
+  int32_t tile_w;
+  int32_t tile_h;
+  int32_t lds_batch;
+  uint32_t flags; /* reserved, must be 0 */
+} htgs_config;
+
+/* Gradient outputs, same shapes as htgs_gaussians. The backward ADDS into
+ * them (+=); any pointer may be NULL to skip that parameter. */
+typedef struct htgs_grads {
+  float *means;
+  float *log_scales;
+  float *quats;
+  float *opacity_logits;
+  float *sh;
+} htgs_grads;
+
+/* Bytes of workspace for n Gaussians, the given views and settings, and room
+ * for max_instances (Gaussian, tile) instances. The workspace carries the
+ * per-splat records, tile lists and backward partials from a forward call to
+ * the matching backward call; its capacity is derived from the byte size
+ * passed to every call. */
+int htgs_workspace_bytes(int64_t n, const htgs_camera *cams, int32_t n_views,
+                         const htgs_config *cfg, int64_t max_instances,
+                         int64_t *bytes_out);
+
+/* Bytes of the per-pixel forward state of ALL views (caller-owned, kept from
+ * forward to backward): per pixel 8K+24 bytes laid out as float planes of
+ * W*H elements: K core ids (int32, -1 = empty, front to back), K core alphas,
+ * T_{n+1}, tail sum of alpha, tail sum of alpha*rgb (3 planes), tail product
+ * of (1-alpha). Views follow each other in order. */
+int htgs_state_bytes(const htgs_camera *cams, int32_t n_views, const htgs_config *cfg,
+                     int64_t *bytes_out);
+
+/* Runs the preprocessing of every view and returns the number of
+ * (Gaussian, tile) instances the forward will need. SYNCHRONISES the stream.
+ * ws may be sized for 0 instances. */
+int htgs_count_instances(const htgs_gaussians *g, const htgs_camera *cams, int32_t n_views,
+                         const htgs_config *cfg, void *ws, int64_t ws_bytes,
+                         int64_t *instances_out, void *stream);
+
+/* Forward render of one view (Sec. 3.2-3.3). out_rgb is [3,H,W]. state may be
+ * NULL (inference); otherwise it receives the per-pixel state described at
+ * htgs_state_bytes() that htgs_render_backward() needs. If more instances
+ * arise than the workspace holds, the status word reports
+ * HTGS_STATUS_OVERFLOW and the image is invalid. */
+int htgs_render_forward(const htgs_gaussians *g, const htgs_camera *cam,
+                        const htgs_config *cfg, void *ws, int64_t ws_bytes, void *state,
+                        float *out_rgb, void *stream);
+
+/* Backward of the last htgs_render_forward() on this workspace and state:
+ * grad_rgb is dL/dC [3,H,W]; gradients w.r.t. every parameter are ADDED to
+ * `grads`. Deterministic (no floating-point atomics). Same g, cam, cfg as the
+ * forward. */
+int htgs_render_backward(const htgs_gaussians *g, const htgs_camera *cam,
+                         const htgs_config *cfg, void *ws, int64_t ws_bytes,
+                         const void *state, const float *grad_rgb, const htgs_grads *grads,
+                         void *stream);
+
+/* Several views of one scene in one pass per stage (1 <= n_views <=
+ * HTGS_MAX_VIEWS). out_rgb[v] is [3,H_v,W_v]; state holds all views in order
+ * (htgs_state_bytes). The backward sums the gradients of all views. */
+int htgs_render_forward_batched(const htgs_gaussians *g, const htgs_camera *cams,
+                                int32_t n_views, const htgs_config *cfg, void *ws,
+                                int64_t ws_bytes, void *state, float *const *out_rgb,
+                                void *stream);
+int htgs_render_backward_batched(const htgs_gaussians *g, const htgs_camera *cams,
+                                 int32_t n_views, const htgs_config *cfg, void *ws,
+                                 int64_t ws_bytes, const void *state,
+                                 const float *const *grad_rgb, const htgs_grads *grads,
+                                 void *stream);
+
+/* Reads the status flags (HTGS_STATUS_*), the instance count and the number
+ * of fragments (pixel-Gaussian pairs with rho^2 <= rho_c) of the last call on
+ * ws; instances_out and fragments_out may be NULL. SYNCHRONISES the stream. */
+int htgs_read_status(const void *ws, int64_t ws_bytes, uint32_t *flags_out,
+                     int64_t *instances_out, int64_t *fragments_out, void *stream);
+
+/* Stage timing for benchmarking. While enabled, every later call records a
+ * pair of HIP events on its stream around each stage it launches;
+ * htgs_profile_read() waits for those events and returns, per stage, the
+ * summed milliseconds and the number of kernel launches, then clears them.
+ * Host-side state, not thread-safe; keep it disabled during graph capture. */
+enum {
+  HTGS_STAGE_FILL = 0, HTGS_STAGE_PREPROCESS = 1, HTGS_STAGE_SORT = 2, HTGS_STAGE_RANGES = 3,
+  HTGS_STAGE_RASTER_FWD = 4, HTGS_STAGE_RASTER_BWD = 5, HTGS_STAGE_PREPROCESS_BWD = 6,
+  HTGS_NUM_STAGES = 7
+};
+int htgs_profile_enable(int on);
+int htgs_profile_read(double *ms_out, int64_t *launches_out, int32_t n_stages);
+
+/* Copies the sorted tile lists of the last forward to HOST memory: keys
+ * (global tile id, converted to uint32) and values (Gaussian index), up to
+ * max_out entries each, plus the per-Gaussian tile rectangles of view 0
+ * (int32 [n,4]: tx0, ty0, tx1, ty1, empty when tx0 > tx1; rects_out may be
+ * NULL). Same n, cams, cfg as the forward. SYNCHRONISES the stream. */
+int htgs_debug_export_bins(const htgs_gaussians *g, const htgs_camera *cams, int32_t n_views,
+                           const htgs_config *cfg, const void *ws, int64_t ws_bytes,
+                           uint32_t *keys_out, uint32_t *values_out, int64_t max_out,
+                           int32_t *rects_out, int64_t *instances_out, void *stream);
+
+/* Static description of an error code. */
+const char *htgs_strerror(int code);
+
+/* ABI version, currently 1. */
+int htgs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HTGS_H */

@@ -1,0 +1,142 @@
+// Internal definitions shared by the HIP kernels and the C ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace htgs {
+
+constexpr int kMaxViews = 16;
+constexpr int kRecFloats = 32;      // per (view, Gaussian) raster record
+constexpr int kPartialFloats = 24;  // per-instance backward partials (22 used)
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortChunk = kSortThreads * kSortItems;
+constexpr int kPreThreads = 256;
+
+// Raster record of one Gaussian in one view (float32). The Pluecker
+// direction d and moment m of the ray through a pixel are affine in the
+// pixel's offset from a reference point (xc, yc) near the splat's
+// footprint: d = D0 + dx Du + dy Dv, m = M0 + dx Mu + dy Mv, dx, dy in
+// pixels. Centring keeps the float32 evaluation of m accurate where rho is
+// small. (xc, yc) = (ixc + 0.5 - hx, iyc + 0.5 - hy).
+enum RecField {
+  R_D0 = 0, R_DU = 3, R_DV = 6, R_M0 = 9, R_MU = 12, R_MV = 15,
+  R_R3 = 18,    // third view row of M T (scaled axes' z components)
+  R_MUZ = 21,   // view depth of the mean
+  R_O = 22,     // opacity
+  R_RC = 23,    // rho_c (squared cutoff radius)
+  R_RGB = 24,   // colour (3)
+  R_HX = 27, R_HY = 28,
+  R_IX = 29, R_IY = 30,  // int32 bit patterns
+  R_FLAGS = 31           // bit c set: colour channel c was clamped at 0
+};
+
+// Per-instance backward partials: sums over the tile's pixels of the
+// gradients w.r.t. d and m (plain, times the pixel's x offset and times its
+// y offset from the tile origin), of dL/do and of dL/drgb.
+enum PartialField {
+  P_D0 = 0, P_DX = 3, P_DY = 6, P_M0 = 9, P_MX = 12, P_MY = 15, P_O = 18, P_C = 19
+};
+
+// Staged record in the raster kernels: tile-centred coefficients (28 floats).
+enum StageField {
+  S_D0 = 0, S_DU = 3, S_DV = 6, S_M0 = 9, S_MU = 12, S_MV = 15, S_R3 = 18,
+  S_MUZ = 21, S_O = 22, S_RC = 23, S_RGB = 24, S_GID = 27, S_FLOATS = 28
+};
+
+struct ViewParams {
+  float w2c[12];        // row-major [R|t]
+  float fx, fy, cx, cy;
+  double cam_pos[3];    // camera centre -R^-1 t (computed on the host in float64)
+  int32_t width, height;
+  int32_t tiles_x, tiles_y;
+  int32_t tile_base;    // first global tile id of this view
+  float z_near;
+  int64_t state_off;    // float offset of this view's state block
+  float *out_rgb;       // [3,H,W]
+  const float *grad_rgb;
+};
+
+struct ViewSet {
+  int32_t n;
+  int32_t total_tiles;
+  ViewParams v[kMaxViews];
+};
+
+struct KCfg {
+  int64_t n;
+  int32_t K;
+  int32_t sh_degree;
+  float tau_alpha, tau_core, alpha_max;
+  float bg[3];
+  int32_t tile_w, tile_h;
+};
+
+struct GaussPtrs {
+  const float *means, *log_scales, *quats, *logits, *sh;
+};
+
+struct GradPtrs {
+  float *means, *log_scales, *quats, *logits, *sh;
+};
+
+// Device addresses inside the caller's workspace.
+struct Ws {
+  uint32_t *status;            // [0] flags, [1] preprocess ticket, [2..5] sort tickets
+  unsigned long long *total;   // instance count (64-bit)
+  unsigned long long *frags;   // fragments counted by the forward raster
+  unsigned long long *pp_look; // preprocess look-back words, one per block
+  uint32_t *hist;              // [4][256] digit histograms
+  uint32_t *sort_look;         // [passes][max_chunks][256]
+  uint2 *ranges;               // [total_tiles] (start, end)
+  float *records;              // [views][n][32]
+  int4 *rects;                 // [views][n] tile rect (tx0, ty0, tx1, ty1), empty if tx0 > tx1
+  uint32_t *offsets;           // [n] first instance slot of each Gaussian
+  void *keys[2];
+  uint32_t *vals[2];
+  float *partials;             // [capacity][24]
+  int64_t capacity;
+  int64_t max_chunks;
+  int32_t key_bits, passes, key16;
+  int32_t final_buf;           // which of keys/vals holds the sorted lists
+};
+
+// Look-back words: 2 flag bits on top of the value.
+constexpr uint32_t kFlagA32 = 1u << 30, kFlagP32 = 2u << 30, kMask32 = (1u << 30) - 1u;
+constexpr unsigned long long kFlagA64 = 1ull << 62, kFlagP64 = 2ull << 62,
+                             kMask64 = (1ull << 62) - 1ull;
+constexpr int kSpinLimit = 1 << 22;
+
+enum StatusBits : uint32_t { ST_OVERFLOW = 1u, ST_SPIN = 2u };
+
+__device__ __forceinline__ uint32_t ld_acq_u32(const uint32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_rel_u32(uint32_t *p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long ld_acq_u64(const unsigned long long *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_rel_u64(unsigned long long *p, unsigned long long v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Tile coverage rule shared by the forward and backward launchers: tile ids
+// are handed out so that consecutive workgroups on one XCD (workgroups are
+// dealt round-robin over the 8 XCDs) work on a contiguous band of tiles.
+__device__ __forceinline__ int xcd_tile(int block, int total_tiles) {
+  const int per = (total_tiles + 7) >> 3;
+  return (block & 7) * per + (block >> 3);
+}
+
+__device__ __forceinline__ int view_of_tile(const ViewSet &vs, int t) {
+  int v = 0;
+  for (int k = 1; k < vs.n; ++k) v = (t >= vs.v[k].tile_base) ? k : v;
+  return v;
+}
+
+}  // namespace htgs

@@ -1,0 +1,516 @@
+// Tile rasterizer, forward and backward (Sec. 3.2 and Sec. 3.3).
+//
+// Forward: one workgroup per tile, one lane per pixel. The tile's instances
+// are staged through LDS in batches of one record per lane; every lane then
+// walks the batch: Pluecker direction d and moment m of its pixel ray in
+// splat space (affine in the pixel offset, tile-centred), rho^2 = |m|^2/|d|^2
+// (Eq. rho-pluecker), alpha = min(alpha_max, o exp(-rho^2/2)), and for
+// fragments with alpha >= tau_K the view depth of the maximum-density point
+// z = (M T [(d x m)/|d|^2; 1])_z (Sec. 3.3). Those go through an unrolled
+// insertion network into a register core of K (depth, alpha, id, rgb)
+// entries; what falls off the end, and every other fragment, is added to
+// the order-independent tail (sum alpha, sum alpha rgb, prod (1 - alpha)).
+// The composite is Eq. pixel_color_computation.
+//
+// Backward: one workgroup per tile. First each pixel's adjoint factors are
+// built in LDS: the core terms T_i (c_i - B_i) . G and T_i by walking the
+// stored core back to front, and the tail factors shared by every tail
+// fragment of the pixel (Sec. 3.3, last paragraph). Then each wave takes 64
+// of the tile's instances, one per lane, and loops over the tile's pixels,
+// recomputing rho^2 and alpha exactly as the forward did and accumulating
+// the gradient of its splat's record in registers. Each lane writes one
+// partial per instance, so there are no floating-point atomics and the
+// result is deterministic.
+#include <float.h>
+
+#include "common.h"
+
+namespace htgs {
+
+constexpr float kNegHalfLog2e = -0.72134752044448170368f;  // -1 / (2 ln 2)
+
+__device__ __forceinline__ float exp2_fast(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float rcp_fast(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// Tile-centred staged record: d = D0t + lx Du + ly Dv with (lx, ly) the
+// pixel's integer offset from the tile's first pixel.
+__device__ __forceinline__ void stage_record(const float *__restrict__ rec, int px0, int py0,
+                                             uint32_t gid, float *st) {
+  const int ix = __float_as_int(rec[R_IX]);
+  const int iy = __float_as_int(rec[R_IY]);
+  const float dx0 = (float)(px0 - ix) + rec[R_HX];
+  const float dy0 = (float)(py0 - iy) + rec[R_HY];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    st[S_D0 + k] = fmaf(dy0, rec[R_DV + k], fmaf(dx0, rec[R_DU + k], rec[R_D0 + k]));
+    st[S_DU + k] = rec[R_DU + k];
+    st[S_DV + k] = rec[R_DV + k];
+    st[S_M0 + k] = fmaf(dy0, rec[R_MV + k], fmaf(dx0, rec[R_MU + k], rec[R_M0 + k]));
+    st[S_MU + k] = rec[R_MU + k];
+    st[S_MV + k] = rec[R_MV + k];
+    st[S_R3 + k] = rec[R_R3 + k];
+    st[S_RGB + k] = rec[R_RGB + k];
+  }
+  st[S_MUZ] = rec[R_MUZ];
+  st[S_O] = rec[R_O];
+  st[S_RC] = rec[R_RC];
+  st[S_GID] = __uint_as_float(gid);
+}
+
+__device__ __forceinline__ void eval_ray(const float *st, float lx, float ly, float d[3], float m[3],
+                                         float &dd, float &mm) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    d[k] = fmaf(ly, st[S_DV + k], fmaf(lx, st[S_DU + k], st[S_D0 + k]));
+    m[k] = fmaf(ly, st[S_MV + k], fmaf(lx, st[S_MU + k], st[S_M0 + k]));
+  }
+  dd = fmaf(d[2], d[2], fmaf(d[1], d[1], d[0] * d[0]));
+  mm = fmaf(m[2], m[2], fmaf(m[1], m[1], m[0] * m[0]));
+}
+
+__device__ __forceinline__ bool is_fragment(float dd, float mm, float rc) {
+  return (dd >= FLT_MIN) && (mm <= rc * dd);
+}
+
+__device__ __forceinline__ float max_point_depth(const float *st, const float d[3], const float m[3],
+                                                 float inv) {
+  const float c0 = fmaf(d[1], m[2], -d[2] * m[1]);
+  const float c1 = fmaf(d[2], m[0], -d[0] * m[2]);
+  const float c2 = fmaf(d[0], m[1], -d[1] * m[0]);
+  const float r = fmaf(st[S_R3 + 2], c2, fmaf(st[S_R3 + 1], c1, st[S_R3] * c0));
+  return fmaf(r, inv, st[S_MUZ]);
+}
+
+__device__ __forceinline__ void load_record(const float *__restrict__ recs, uint32_t gid, float *rec) {
+  const float4 *r4 = reinterpret_cast<const float4 *>(recs + (int64_t)gid * kRecFloats);
+#pragma unroll
+  for (int k = 0; k < kRecFloats / 4; ++k) {
+    const float4 t = r4[k];
+    rec[4 * k] = t.x; rec[4 * k + 1] = t.y; rec[4 * k + 2] = t.z; rec[4 * k + 3] = t.w;
+  }
+}
+
+struct TileInfo {
+  int t, v, tx, ty;
+};
+
+__device__ __forceinline__ bool tile_info(const ViewSet &vs, TileInfo &ti) {
+  ti.t = xcd_tile(blockIdx.x, vs.total_tiles);
+  if (ti.t >= vs.total_tiles) return false;
+  ti.v = view_of_tile(vs, ti.t);
+  const int lt = ti.t - vs.v[ti.v].tile_base;
+  ti.tx = lt % vs.v[ti.v].tiles_x;
+  ti.ty = lt / vs.v[ti.v].tiles_x;
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// Forward
+// ---------------------------------------------------------------------------
+template <int KMAX, int TW, int TH>
+__global__ void __launch_bounds__(TW *TH) k_raster_fwd(Ws w, ViewSet vs, KCfg cfg,
+                                                       float *__restrict__ state,
+                                                       const uint32_t *__restrict__ vals) {
+  constexpr int NT = TW * TH;
+  constexpr int SV = S_FLOATS / 4;
+  __shared__ float4 s_stage[NT * SV];
+  __shared__ uint32_t s_nfrag;
+
+  TileInfo ti;
+  if (!tile_info(vs, ti)) return;
+  const ViewParams &V = vs.v[ti.v];
+  const int tid = threadIdx.x;
+  const int lx = tid % TW, ly = tid / TW;
+  const int px0 = ti.tx * TW, py0 = ti.ty * TH;
+  const int px = px0 + lx, py = py0 + ly;
+  const bool inside = (px < V.width) && (py < V.height);
+  const uint2 rg = w.ranges[ti.t];
+  const float flx = (float)lx, fly = (float)ly;
+  const int K = cfg.K;
+  const float tau_core = cfg.tau_core, amax = cfg.alpha_max;
+  const float *recs = w.records + (int64_t)ti.v * cfg.n * kRecFloats;
+
+  float cz[KMAX], ca[KMAX], cr[KMAX], cg[KMAX], cb[KMAX];
+  int cid[KMAX];
+#pragma unroll
+  for (int i = 0; i < KMAX; ++i) {
+    cz[i] = INFINITY; ca[i] = 0.f; cr[i] = cg[i] = cb[i] = 0.f; cid[i] = -1;
+  }
+  float zlast = INFINITY;
+  float A = 0.f, S0 = 0.f, S1 = 0.f, S2 = 0.f, P = 1.f;
+  uint32_t nfrag = 0;
+  if (tid == 0) s_nfrag = 0u;
+
+  for (uint32_t base = rg.x; base < rg.y; base += NT) {
+    const int cnt = (int)min((uint32_t)NT, rg.y - base);
+    __syncthreads();
+    if (tid < cnt) {
+      const uint32_t gid = vals[base + tid];
+      float rec[kRecFloats];
+      load_record(recs, gid, rec);
+      float st[S_FLOATS];
+      stage_record(rec, px0, py0, gid, st);
+#pragma unroll
+      for (int k = 0; k < SV; ++k)
+        s_stage[tid * SV + k] = make_float4(st[4 * k], st[4 * k + 1], st[4 * k + 2], st[4 * k + 3]);
+    }
+    __syncthreads();
+    if (!inside) continue;
+    for (int j = 0; j < cnt; ++j) {
+      float st[S_FLOATS];
+#pragma unroll
+      for (int k = 0; k < SV; ++k) {
+        const float4 t = s_stage[j * SV + k];
+        st[4 * k] = t.x; st[4 * k + 1] = t.y; st[4 * k + 2] = t.z; st[4 * k + 3] = t.w;
+      }
+      float d[3], m[3], dd, mm;
+      eval_ray(st, flx, fly, d, m, dd, mm);
+      if (!is_fragment(dd, mm, st[S_RC])) continue;
+      ++nfrag;
+      const float inv = rcp_fast(dd);
+      const float r2 = mm * inv;
+      const float alpha = fminf(amax, st[S_O] * exp2_fast(r2 * kNegHalfLog2e));
+      float ta = alpha, tr = st[S_RGB], tg = st[S_RGB + 1], tb = st[S_RGB + 2];
+      bool to_tail = true;
+      if (alpha >= tau_core && K > 0) {
+        float z = max_point_depth(st, d, m, inv);
+        if (z < zlast) {
+          int id = (int)__float_as_uint(st[S_GID]);
+          float a = alpha;
+          float zl = zlast;
+#pragma unroll
+          for (int i = 0; i < KMAX; ++i) {
+            if (i < K) {
+              const bool sw = z < cz[i];
+              const float nz = sw ? z : cz[i]; z = sw ? cz[i] : z; cz[i] = nz;
+              const float na = sw ? a : ca[i]; a = sw ? ca[i] : a; ca[i] = na;
+              const int ni = sw ? id : cid[i]; id = sw ? cid[i] : id; cid[i] = ni;
+              const float nr = sw ? tr : cr[i]; tr = sw ? cr[i] : tr; cr[i] = nr;
+              const float ng = sw ? tg : cg[i]; tg = sw ? cg[i] : tg; cg[i] = ng;
+              const float nb = sw ? tb : cb[i]; tb = sw ? cb[i] : tb; cb[i] = nb;
+              if (i == K - 1) zl = cz[i];
+            }
+          }
+          zlast = zl;
+          ta = a;
+          to_tail = id >= 0;
+        }
+      }
+      if (to_tail) {
+        A += ta;
+        S0 = fmaf(ta, tr, S0);
+        S1 = fmaf(ta, tg, S1);
+        S2 = fmaf(ta, tb, S2);
+        P *= 1.f - ta;
+      }
+    }
+  }
+  __syncthreads();
+  if (nfrag) atomicAdd(&s_nfrag, nfrag);
+  __syncthreads();
+  if (tid == 0 && s_nfrag) atomicAdd(w.frags, (unsigned long long)s_nfrag);
+  if (!inside) return;
+
+  float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
+#pragma unroll
+  for (int i = 0; i < KMAX; ++i) {
+    if (i < K && cid[i] >= 0) {
+      const float wgt = ca[i] * T;
+      C0 = fmaf(wgt, cr[i], C0);
+      C1 = fmaf(wgt, cg[i], C1);
+      C2 = fmaf(wgt, cb[i], C2);
+      T *= 1.f - ca[i];
+    }
+  }
+  float X0 = P * cfg.bg[0], X1 = P * cfg.bg[1], X2 = P * cfg.bg[2];
+  if (A > 0.f) {
+    const float k = (1.f - P) / A;
+    X0 = fmaf(k, S0, X0);
+    X1 = fmaf(k, S1, X1);
+    X2 = fmaf(k, S2, X2);
+  }
+  const int64_t npix = (int64_t)V.width * V.height;
+  const int64_t pix = (int64_t)py * V.width + px;
+  V.out_rgb[pix] = fmaf(T, X0, C0);
+  V.out_rgb[npix + pix] = fmaf(T, X1, C1);
+  V.out_rgb[2 * npix + pix] = fmaf(T, X2, C2);
+  if (state) {
+    float *sp = state + V.state_off + pix;
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i) {
+      if (i < K) {
+        sp[(int64_t)i * npix] = __int_as_float(cid[i]);
+        sp[(int64_t)(K + i) * npix] = ca[i];
+      }
+    }
+    sp[(int64_t)(2 * K) * npix] = T;
+    sp[(int64_t)(2 * K + 1) * npix] = A;
+    sp[(int64_t)(2 * K + 2) * npix] = S0;
+    sp[(int64_t)(2 * K + 3) * npix] = S1;
+    sp[(int64_t)(2 * K + 4) * npix] = S2;
+    sp[(int64_t)(2 * K + 5) * npix] = P;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Backward
+// ---------------------------------------------------------------------------
+template <int KMAX>
+struct PixLayout {
+  // G(3), w1, q1, q2, pad(2), ids[KMAX], dL/dalpha_i[KMAX], T_i[KMAX]
+  static constexpr int kIds = 8;
+  static constexpr int kCoef = 8 + KMAX;
+  static constexpr int kT = 8 + 2 * KMAX;
+  static constexpr int kStride = ((8 + 3 * KMAX) + 3) / 4 * 4;
+};
+
+template <int KMAX, int TW, int TH>
+__global__ void __launch_bounds__(256) k_raster_bwd(Ws w, ViewSet vs, KCfg cfg,
+                                                    const float *__restrict__ state,
+                                                    const uint32_t *__restrict__ vals) {
+  constexpr int NT = TW * TH;
+  using L = PixLayout<KMAX>;
+  __shared__ float4 s_pix[NT * L::kStride / 4];
+
+  TileInfo ti;
+  if (!tile_info(vs, ti)) return;
+  const ViewParams &V = vs.v[ti.v];
+  const int tid = threadIdx.x;
+  const int px0 = ti.tx * TW, py0 = ti.ty * TH;
+  const int K = cfg.K;
+  const float *recs = w.records + (int64_t)ti.v * cfg.n * kRecFloats;
+  const int64_t npix = (int64_t)V.width * V.height;
+  float *sp_all = reinterpret_cast<float *>(s_pix);
+
+  // Per-pixel adjoint factors.
+  for (int p = tid; p < NT; p += 256) {
+    const int px = px0 + p % TW, py = py0 + p / TW;
+    float *Pp = sp_all + p * L::kStride;
+    float G[3] = {0.f, 0.f, 0.f}, w1 = 0.f, q1 = 0.f, q2 = 0.f;
+    int ids[KMAX];
+    float coef[KMAX], Ti[KMAX];
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i) { ids[i] = -1; coef[i] = 0.f; Ti[i] = 0.f; }
+    if (px < V.width && py < V.height) {
+      const int64_t pix = (int64_t)py * V.width + px;
+      for (int c = 0; c < 3; ++c) G[c] = V.grad_rgb[c * npix + pix];
+      const float *sp = state + V.state_off + pix;
+      float ca[KMAX], cc[KMAX][3];
+#pragma unroll
+      for (int i = 0; i < KMAX; ++i) {
+        ca[i] = 0.f; cc[i][0] = cc[i][1] = cc[i][2] = 0.f;
+        if (i < K) {
+          ids[i] = __float_as_int(sp[(int64_t)i * npix]);
+          ca[i] = sp[(int64_t)(K + i) * npix];
+          if (ids[i] >= 0) {
+            const float *r = recs + (int64_t)ids[i] * kRecFloats + R_RGB;
+            cc[i][0] = r[0]; cc[i][1] = r[1]; cc[i][2] = r[2];
+          }
+        }
+      }
+      const float A = sp[(int64_t)(2 * K + 1) * npix];
+      const float S[3] = {sp[(int64_t)(2 * K + 2) * npix], sp[(int64_t)(2 * K + 3) * npix],
+                          sp[(int64_t)(2 * K + 4) * npix]};
+      const float Pt = sp[(int64_t)(2 * K + 5) * npix];
+      float T = 1.f;
+#pragma unroll
+      for (int i = 0; i < KMAX; ++i) {
+        if (i < K && ids[i] >= 0) {
+          Ti[i] = T;
+          T *= 1.f - ca[i];
+        }
+      }
+      float X[3], ct[3] = {0.f, 0.f, 0.f};
+      const bool has_tail = A > 0.f;
+      for (int c = 0; c < 3; ++c) {
+        X[c] = Pt * cfg.bg[c];
+        if (has_tail) {
+          ct[c] = S[c] / A;
+          X[c] = fmaf(1.f - Pt, ct[c], X[c]);
+        }
+      }
+      float B[3] = {X[0], X[1], X[2]};
+#pragma unroll
+      for (int i = KMAX - 1; i >= 0; --i) {
+        if (i < K && ids[i] >= 0) {
+          coef[i] = Ti[i] * (G[0] * (cc[i][0] - B[0]) + G[1] * (cc[i][1] - B[1]) +
+                             G[2] * (cc[i][2] - B[2]));
+          for (int c = 0; c < 3; ++c) B[c] = fmaf(ca[i], cc[i][c] - B[c], B[c]);
+        }
+      }
+      if (has_tail) {
+        w1 = T * (1.f - Pt) / A;
+        q1 = w1 * (G[0] * ct[0] + G[1] * ct[1] + G[2] * ct[2]);
+        q2 = T * Pt *
+             (G[0] * (cfg.bg[0] - ct[0]) + G[1] * (cfg.bg[1] - ct[1]) + G[2] * (cfg.bg[2] - ct[2]));
+      }
+    }
+    Pp[0] = G[0]; Pp[1] = G[1]; Pp[2] = G[2];
+    Pp[3] = w1; Pp[4] = q1; Pp[5] = q2; Pp[6] = 0.f; Pp[7] = 0.f;
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i) {
+      Pp[L::kIds + i] = __int_as_float(ids[i]);
+      Pp[L::kCoef + i] = coef[i];
+      Pp[L::kT + i] = Ti[i];
+    }
+  }
+  __syncthreads();
+
+  const uint2 rg = w.ranges[ti.t];
+  const int wave = tid >> 6, lane = tid & 63;
+  const uint32_t count = rg.y - rg.x;
+  const uint32_t nch = (count + 63u) >> 6;
+  const float tau_core = cfg.tau_core, amax = cfg.alpha_max;
+  for (uint32_t c = wave; c < nch; c += 4) {
+    const uint32_t j = rg.x + c * 64u + lane;
+    const bool active = j < rg.y;
+    float st[S_FLOATS];
+#pragma unroll
+    for (int k = 0; k < S_FLOATS; ++k) st[k] = 0.f;
+    st[S_RC] = -1.f;
+    uint32_t gid = 0, slot = 0;
+    if (active) {
+      gid = vals[j];
+      float rec[kRecFloats];
+      load_record(recs, gid, rec);
+      stage_record(rec, px0, py0, gid, st);
+      uint32_t pre = 0;
+      for (int u = 0; u < ti.v; ++u) {
+        const int4 r = w.rects[(int64_t)u * cfg.n + gid];
+        if (r.x <= r.z) pre += (uint32_t)((r.z - r.x + 1) * (r.w - r.y + 1));
+      }
+      const int4 r = w.rects[(int64_t)ti.v * cfg.n + gid];
+      slot = w.offsets[gid] + pre + (uint32_t)((ti.ty - r.y) * (r.z - r.x + 1) + (ti.tx - r.x));
+    }
+    float acc[22];
+#pragma unroll
+    for (int k = 0; k < 22; ++k) acc[k] = 0.f;
+    for (int p = 0; p < NT; ++p) {
+      const float flx = (float)(p % TW), fly = (float)(p / TW);
+      float d[3], m[3], dd, mm;
+      eval_ray(st, flx, fly, d, m, dd, mm);
+      if (!(active && is_fragment(dd, mm, st[S_RC]))) continue;
+      const float *Pp = sp_all + p * L::kStride;
+      const float inv = rcp_fast(dd);
+      const float r2 = mm * inv;
+      const float e = exp2_fast(r2 * kNegHalfLog2e);
+      const float araw = st[S_O] * e;
+      const float alpha = fminf(amax, araw);
+      const float G0 = Pp[0], G1 = Pp[1], G2 = Pp[2];
+      bool core = false;
+      float dLda = 0.f, Tc = 0.f;
+      if (alpha >= tau_core) {
+#pragma unroll
+        for (int i = 0; i < KMAX; ++i) {
+          if (i < K && __float_as_uint(Pp[L::kIds + i]) == gid) {
+            core = true;
+            dLda = Pp[L::kCoef + i];
+            Tc = Pp[L::kT + i];
+          }
+        }
+      }
+      float wc;
+      if (core) {
+        wc = alpha * Tc;
+      } else {
+        const float w1 = Pp[3];
+        const float gdc = fmaf(G2, st[S_RGB + 2], fmaf(G1, st[S_RGB + 1], G0 * st[S_RGB]));
+        dLda = w1 * gdc - Pp[4] - Pp[5] / (1.f - alpha);
+        wc = w1 * alpha;
+      }
+      acc[P_C + 0] = fmaf(wc, G0, acc[P_C + 0]);
+      acc[P_C + 1] = fmaf(wc, G1, acc[P_C + 1]);
+      acc[P_C + 2] = fmaf(wc, G2, acc[P_C + 2]);
+      if (araw <= amax) {
+        acc[P_O] = fmaf(dLda, e, acc[P_O]);
+        const float s1 = -alpha * dLda * inv;   // 2 dL/drho^2 / |d|^2, dL/drho^2 = -alpha/2 dL/dalpha
+        const float s2 = -s1 * r2;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const float gm = s1 * m[k];
+          const float gd = s2 * d[k];
+          acc[P_M0 + k] += gm;
+          acc[P_MX + k] = fmaf(flx, gm, acc[P_MX + k]);
+          acc[P_MY + k] = fmaf(fly, gm, acc[P_MY + k]);
+          acc[P_D0 + k] += gd;
+          acc[P_DX + k] = fmaf(flx, gd, acc[P_DX + k]);
+          acc[P_DY + k] = fmaf(fly, gd, acc[P_DY + k]);
+        }
+      }
+    }
+    if (active && (uint64_t)slot < (uint64_t)w.capacity) {
+      float4 *dst = reinterpret_cast<float4 *>(w.partials + (int64_t)slot * kPartialFloats);
+      dst[0] = make_float4(acc[0], acc[1], acc[2], acc[3]);
+      dst[1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
+      dst[2] = make_float4(acc[8], acc[9], acc[10], acc[11]);
+      dst[3] = make_float4(acc[12], acc[13], acc[14], acc[15]);
+      dst[4] = make_float4(acc[16], acc[17], acc[18], acc[19]);
+      dst[5] = make_float4(acc[20], acc[21], 0.f, 0.f);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+template <int KMAX, int TW, int TH>
+static hipError_t fwd_launch(const Ws &w, const ViewSet &vs, const KCfg &cfg, float *state,
+                             const uint32_t *vals, hipStream_t s) {
+  const int blocks = 8 * ((vs.total_tiles + 7) / 8);
+  hipLaunchKernelGGL((k_raster_fwd<KMAX, TW, TH>), dim3(blocks), dim3(TW * TH), 0, s, w, vs, cfg,
+                     state, vals);
+  return hipGetLastError();
+}
+
+template <int KMAX, int TW, int TH>
+static hipError_t bwd_launch(const Ws &w, const ViewSet &vs, const KCfg &cfg, const float *state,
+                             const uint32_t *vals, hipStream_t s) {
+  const int blocks = 8 * ((vs.total_tiles + 7) / 8);
+  hipLaunchKernelGGL((k_raster_bwd<KMAX, TW, TH>), dim3(blocks), dim3(256), 0, s, w, vs, cfg,
+                     state, vals);
+  return hipGetLastError();
+}
+
+int kmax_for(int K) {
+  if (K <= 1) return 1;
+  if (K <= 2) return 2;
+  if (K <= 4) return 4;
+  if (K <= 8) return 8;
+  if (K <= 16) return 16;
+  return 32;
+}
+
+#define HTGS_DISPATCH(FN, ...)                                                   \
+  do {                                                                           \
+    const int km = kmax_for(cfg.K);                                              \
+    if (cfg.tile_w == 8 && cfg.tile_h == 8) {                                    \
+      switch (km) {                                                              \
+        case 1: return FN<1, 8, 8>(__VA_ARGS__);                                 \
+        case 2: return FN<2, 8, 8>(__VA_ARGS__);                                 \
+        case 4: return FN<4, 8, 8>(__VA_ARGS__);                                 \
+        case 8: return FN<8, 8, 8>(__VA_ARGS__);                                 \
+        case 16: return FN<16, 8, 8>(__VA_ARGS__);                               \
+        default: return FN<32, 8, 8>(__VA_ARGS__);                               \
+      }                                                                          \
+    } else {                                                                     \
+      switch (km) {                                                              \
+        case 1: return FN<1, 16, 16>(__VA_ARGS__);                               \
+        case 2: return FN<2, 16, 16>(__VA_ARGS__);                               \
+        case 4: return FN<4, 16, 16>(__VA_ARGS__);                               \
+        case 8: return FN<8, 16, 16>(__VA_ARGS__);                               \
+        default: return FN<16, 16, 16>(__VA_ARGS__);                             \
+      }                                                                          \
+    }                                                                            \
+  } while (0)
+
+hipError_t launch_raster_fwd(const Ws &w, const ViewSet &vs, const KCfg &cfg, float *state,
+                             const uint32_t *vals, hipStream_t s) {
+  HTGS_DISPATCH(fwd_launch, w, vs, cfg, state, vals, s);
+}
+
+hipError_t launch_raster_bwd(const Ws &w, const ViewSet &vs, const KCfg &cfg, const float *state,
+                             const uint32_t *vals, hipStream_t s) {
+  HTGS_DISPATCH(bwd_launch, w, vs, cfg, state, vals, s);
+}
+
+}  // namespace htgs

@@ -1,0 +1,186 @@
+// Stable LSD radix sort of the (tile key, Gaussian index) instances and the
+// per-tile ranges (Sec. 4.3: plain tile-id keys, no depth sort).
+//
+// One launch per 8-bit digit. Each workgroup takes a chunk of 4096 keys (in
+// ticket order), ranks them stably inside each 64-lane wave with ballots
+// (lanes whose digits match, counted below the lane), combines the four
+// waves in LDS, obtains the chunk's offset per digit by decoupled look-back
+// over earlier chunks, and scatters. The global digit histograms were
+// accumulated by the preprocess launch while it emitted the keys, so a pass
+// reads its keys and values once and writes them once.
+#include "common.h"
+
+namespace htgs {
+
+template <typename KeyT>
+__global__ void __launch_bounds__(kSortThreads) k_sort_pass(Ws w, int pass, int nbits,
+                                                             const KeyT *__restrict__ kin,
+                                                             const uint32_t *__restrict__ vin,
+                                                             KeyT *__restrict__ kout,
+                                                             uint32_t *__restrict__ vout) {
+  __shared__ uint32_t s_wh[kSortThreads / 64][256];
+  __shared__ uint32_t s_base[256];
+  __shared__ uint32_t s_wsum[kSortThreads / 64];
+  __shared__ uint32_t s_ticket;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const unsigned long long tot = *w.total;
+  // On overflow only part of the keys exist while the histograms count all
+  // of them; nothing is sorted and the status word reports the overflow.
+  if (tot > (unsigned long long)w.capacity) return;
+  const uint64_t I = tot;
+  const uint64_t nchunks = (I + kSortChunk - 1) / kSortChunk;
+  if (tid == 0) s_ticket = atomicAdd(&w.status[2 + pass], 1u);
+  for (int i = tid; i < (kSortThreads / 64) * 256; i += kSortThreads) (&s_wh[0][0])[i] = 0u;
+
+  // Exclusive scan of the global digit histogram of this pass.
+  const uint32_t hv = w.hist[pass * 256 + tid];
+  uint32_t x = hv;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63) s_wsum[wave] = x;
+  __syncthreads();
+  uint32_t woff = 0;
+  for (int k = 0; k < wave; ++k) woff += s_wsum[k];
+  const uint32_t digit_excl = x + woff - hv;
+  const uint64_t chunk = s_ticket;
+  if (chunk >= nchunks) return;  // uniform over the workgroup
+
+  const int shift = 8 * pass;
+  const uint64_t wbase = chunk * kSortChunk + (uint64_t)wave * (64 * kSortItems);
+  KeyT key[kSortItems];
+  uint32_t val[kSortItems];
+  uint32_t rank[kSortItems];
+  const uint64_t lanemask_lt = (1ull << lane) - 1ull;
+#pragma unroll
+  for (int i = 0; i < kSortItems; ++i) {
+    const uint64_t idx = wbase + (uint64_t)i * 64 + lane;
+    const bool valid = idx < I;
+    key[i] = valid ? kin[idx] : (KeyT)0;
+    val[i] = valid ? vin[idx] : 0u;
+  }
+#pragma unroll
+  for (int i = 0; i < kSortItems; ++i) {
+    const uint64_t idx = wbase + (uint64_t)i * 64 + lane;
+    const bool valid = idx < I;
+    const uint32_t d = ((uint32_t)key[i] >> shift) & 255u;
+    uint64_t peers = __ballot(valid);
+    for (int b = 0; b < nbits; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t bal = __ballot(bit);
+      peers &= bit ? bal : ~bal;
+    }
+    const uint32_t lt = (uint32_t)__popcll(peers & lanemask_lt);
+    uint32_t old = 0;
+    if (valid) old = s_wh[wave][d];
+    rank[i] = old + lt;
+    // Lanes of one wave reach LDS in issue order, so the leader's update is
+    // seen by the next item's reads without a barrier.
+    if (valid && lt == 0) s_wh[wave][d] = old + (uint32_t)__popcll(peers);
+    __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();
+
+  // Per digit: wave prefixes inside the chunk, then the chunk's offset.
+  {
+    const int d = tid;
+    uint32_t run = 0;
+#pragma unroll
+    for (int k = 0; k < kSortThreads / 64; ++k) {
+      const uint32_t c = s_wh[k][d];
+      s_wh[k][d] = run;
+      run += c;
+    }
+    uint32_t *look = w.sort_look + ((size_t)pass * (size_t)w.max_chunks) * 256;
+    uint32_t excl = 0;
+    if (chunk == 0) {
+      st_rel_u32(&look[d], kFlagP32 | run);
+    } else {
+      st_rel_u32(&look[chunk * 256 + d], kFlagA32 | run);
+      int64_t j = (int64_t)chunk - 1;
+      int spins = 0;
+      while (true) {
+        const uint32_t s = ld_acq_u32(&look[j * 256 + d]);
+        const uint32_t f = s >> 30;
+        if (f == 0) {
+          if (++spins > kSpinLimit) {
+            atomicOr(&w.status[0], (uint32_t)ST_SPIN);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+          continue;
+        }
+        excl += s & kMask32;
+        if (f == 2) break;
+        --j;
+      }
+      st_rel_u32(&look[chunk * 256 + d], kFlagP32 | (excl + run));
+    }
+    s_base[d] = digit_excl + excl;
+  }
+  __syncthreads();
+
+#pragma unroll
+  for (int i = 0; i < kSortItems; ++i) {
+    const uint64_t idx = wbase + (uint64_t)i * 64 + lane;
+    if (idx < I) {
+      const uint32_t d = ((uint32_t)key[i] >> shift) & 255u;
+      const uint32_t pos = s_base[d] + s_wh[wave][d] + rank[i];
+      kout[pos] = key[i];
+      vout[pos] = val[i];
+    }
+  }
+}
+
+template <typename KeyT>
+__global__ void __launch_bounds__(256) k_ranges(Ws w, const KeyT *__restrict__ keys) {
+  const unsigned long long tot = *w.total;
+  if (tot > (unsigned long long)w.capacity) return;  // overflow: every tile stays empty
+  const uint64_t I = tot;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < I; i += stride) {
+    const uint32_t k = keys[i];
+    if (i == 0 || (uint32_t)keys[i - 1] != k) w.ranges[k].x = (uint32_t)i;
+    if (i + 1 == I || (uint32_t)keys[i + 1] != k) w.ranges[k].y = (uint32_t)(i + 1);
+  }
+}
+
+template <typename KeyT>
+static hipError_t sort_impl(const Ws &w, hipStream_t s) {
+  const int blocks = (int)(w.max_chunks > 0 ? w.max_chunks : 1);
+  for (int p = 0; p < w.passes; ++p) {
+    const int nbits = (w.key_bits - 8 * p) < 8 ? (w.key_bits - 8 * p) : 8;
+    const KeyT *kin = reinterpret_cast<const KeyT *>(w.keys[p & 1]);
+    KeyT *kout = reinterpret_cast<KeyT *>(w.keys[(p + 1) & 1]);
+    hipLaunchKernelGGL(k_sort_pass<KeyT>, dim3(blocks), dim3(kSortThreads), 0, s, w, p, nbits,
+                       kin, w.vals[p & 1], kout, w.vals[(p + 1) & 1]);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template <typename KeyT>
+static hipError_t ranges_impl(const Ws &w, hipStream_t s) {
+  const KeyT *sorted = reinterpret_cast<const KeyT *>(w.keys[w.passes & 1]);
+  int rb = (int)((w.capacity + 255) / 256);
+  if (rb < 1) rb = 1;
+  if (rb > 8192) rb = 8192;
+  hipLaunchKernelGGL(k_ranges<KeyT>, dim3(rb), dim3(256), 0, s, w, sorted);
+  return hipGetLastError();
+}
+
+hipError_t launch_sort_passes(const Ws &w, hipStream_t s) {
+  if (w.capacity == 0) return hipSuccess;
+  return w.key16 ? sort_impl<uint16_t>(w, s) : sort_impl<uint32_t>(w, s);
+}
+
+hipError_t launch_ranges(const Ws &w, hipStream_t s) {
+  if (w.capacity == 0) return hipSuccess;
+  return w.key16 ? ranges_impl<uint16_t>(w, s) : ranges_impl<uint32_t>(w, s);
+}
+
+}  // namespace htgs

@@ -1,0 +1,136 @@
+"""GPU-vs-oracle comparison helpers (test code).
+
+Tile lists: bit-exact, except instances of Gaussians whose float64 box edge
+lies within 1e-9 of a pixel-centre boundary (a round-off tie, reported).
+
+Images: max-abs 1e-4 per pixel. A pixel above that is accepted only if it is
+a near-tie pixel and the GPU's branch is admissible: its core (exported in
+the forward state) consists of fragments whose alpha is at least tau_K
+within 1e-4, in depth order within 1e-5 relative, with no clearly eligible
+fragment left out in front of the last core member; and the float64
+composite recomputed with the GPU's core and some choice of the fragments
+that sit within 1e-4 (relative) of the inclusion boundary rho^2 = rho_c
+matches the GPU colour within 1e-4.
+"""
+from __future__ import annotations
+
+import itertools
+
+import numpy as np
+import torch
+
+import oracle
+
+TOL_IMG = 1e-4
+DELTA_RHO = 1e-4
+DELTA_Z = 1e-5
+DELTA_A = 1e-4
+
+
+def compare_bins(gpu_keys, gpu_vals, gpu_rects, ref, margin_tol=1e-9):
+    amb = np.nonzero(ref['margin'] < margin_tol)[0]
+    n = ref['tile_rect'].shape[0]
+    gr = gpu_rects.astype(np.int64)
+    g_empty = gr[:, 0] > gr[:, 2]
+    r_empty = ~ref['nonempty']
+    mask = np.ones(n, bool)
+    mask[amb] = False
+    assert (g_empty[mask] == r_empty[mask]).all(), "empty-rect mismatch"
+    both = mask & ~r_empty
+    assert (gr[both] == ref['tile_rect'][both]).all(), "tile rect mismatch"
+    k, v = gpu_keys.astype(np.int64), gpu_vals.astype(np.int64)
+    rk, rv = ref['keys'], ref['values']
+    if amb.size:
+        keep_g = ~np.isin(v, amb)
+        keep_r = ~np.isin(rv, amb)
+        k, v, rk, rv = k[keep_g], v[keep_g], rk[keep_r], rv[keep_r]
+    assert k.shape == rk.shape, (k.shape, rk.shape)
+    assert (k == rk).all() and (v == rv).all(), "sorted lists differ"
+    return int(amb.size)
+
+
+def _pixel_records(frags, p):
+    a, b = frags['ptr'][p], frags['ptr'][p + 1]
+    return {key: frags[key][a:b] for key in ('gid', 'rho2', 'rho_c', 'raw', 'depth', 'colour',
+                                             'frag')}
+
+
+def _admissible(rec, core, st):
+    K = int(st.K)
+    gid = rec['gid']
+    alpha = np.minimum(st.alpha_max, rec['raw'])
+    clear_in = rec['rho2'] < rec['rho_c'] * (1 - DELTA_RHO)
+    amb_in = np.abs(rec['rho2'] - rec['rho_c']) <= DELTA_RHO * rec['rho_c']
+    pos = {int(g): i for i, g in enumerate(gid)}
+    idx = []
+    for c in core:
+        if c not in pos:
+            return None
+        i = pos[c]
+        if not (clear_in[i] or amb_in[i]):
+            return None
+        if alpha[i] < st.tau_core * (1 - DELTA_A):
+            return None
+        idx.append(i)
+    z = rec['depth']
+    for a_, b_ in zip(idx, idx[1:]):
+        if z[b_] < z[a_] - DELTA_Z * abs(z[a_]):
+            return None
+    elig = clear_in & (alpha >= st.tau_core * (1 + DELTA_A))
+    missing = [i for i in np.nonzero(elig)[0] if int(gid[i]) not in set(core)]
+    if missing:
+        if len(core) < K:
+            return None
+        zl = z[idx[-1]]
+        if any(z[i] < zl - DELTA_Z * abs(zl) for i in missing):
+            return None
+    return idx, clear_in, amb_in, alpha
+
+
+def recompute_with_branch(rec, core, st, gpu_rgb):
+    """Smallest max-abs error over admissible branch choices (None if the
+    GPU core is inadmissible or too many inclusion ties)."""
+    adm = _admissible(rec, core, st)
+    if adm is None:
+        return None
+    idx, clear_in, amb_in, alpha = adm
+    core_set = set(idx)
+    amb_free = [i for i in np.nonzero(amb_in)[0] if i not in core_set]
+    if len(amb_free) > 6:
+        return None
+    base_tail = [i for i in np.nonzero(clear_in & ~amb_in)[0] if i not in core_set]
+    col = rec['colour']
+    best = np.inf
+    for r in range(len(amb_free) + 1):
+        for sub in itertools.combinations(amb_free, r):
+            tail = base_tail + list(sub)
+            C = oracle.blend.composite_pixel(
+                [torch.tensor(alpha[i]) for i in idx], [torch.tensor(col[i]) for i in idx],
+                [torch.tensor(alpha[i]) for i in tail], [torch.tensor(col[i]) for i in tail],
+                st.bg).numpy()
+            best = min(best, float(np.abs(C - gpu_rgb).max()))
+    return best
+
+
+def check_image(gpu_img, gpu_core, ref_img, info, st, tol=TOL_IMG, max_unresolved=0):
+    """gpu_img [3,H,W], gpu_core [K,H,W] int, ref_img [3,H,W] float64."""
+    H, W = ref_img.shape[1:]
+    err = np.abs(gpu_img.astype(np.float64) - ref_img).max(0)
+    bad = np.argwhere(err > tol)
+    resolved, unresolved = 0, []
+    for (y, x) in bad:
+        p = y * W + x
+        rec = _pixel_records(info['frags'], p)
+        core = [int(c) for c in gpu_core[:, y, x] if c >= 0]
+        e = recompute_with_branch(rec, core, st, gpu_img[:, y, x].astype(np.float64))
+        if e is not None and e <= tol:
+            resolved += 1
+        else:
+            unresolved.append((int(y), int(x), float(err[y, x]), e))
+    clean = err.copy()
+    for (y, x) in bad:
+        clean[y, x] = 0.0
+    stats = dict(max_err=float(err.max()), max_err_clean=float(clean.max()), n_bad=int(len(bad)),
+                 resolved=resolved, unresolved=unresolved)
+    assert len(unresolved) <= max_unresolved, stats
+    return stats
