@@ -123,10 +123,11 @@ int htgs_workspace_bytes(int64_t n, const htgs_camera *cams, int32_t n_views,
                          int64_t *bytes_out);
 
 /* Bytes of the per-pixel forward state of ALL views (caller-owned, kept from
- * forward to backward): per pixel 8K+24 bytes laid out as float planes of
- * W*H elements: K core ids (int32, -1 = empty, front to back), K core alphas,
- * T_{n+1}, tail sum of alpha, tail sum of alpha*rgb (3 planes), tail product
- * of (1-alpha). Views follow each other in order. */
+ * forward to backward): per pixel 12K+24 bytes laid out as float planes of
+ * W*H elements: K core Gaussian ids (int32, -1 = empty, front to back), K
+ * core alphas, K core positions in the pixel's tile list (int32, used by the
+ * backward), T_{n+1}, tail sum of alpha, tail sum of alpha*rgb (3 planes),
+ * tail product of (1-alpha). Views follow each other in order. */
 int htgs_state_bytes(const htgs_camera *cams, int32_t n_views, const htgs_config *cfg,
                      int64_t *bytes_out);
 

@@ -191,7 +191,7 @@ ViewSet make_views(const htgs_camera *cams, int32_t n_views, const htgs_config *
     P.out_rgb = out_rgb ? out_rgb[v] : nullptr;
     P.grad_rgb = grad_rgb ? grad_rgb[v] : nullptr;
     tiles += (int64_t)P.tiles_x * P.tiles_y;
-    state_off += (int64_t)(2 * cfg->K + 6) * c.width * c.height;
+    state_off += (int64_t)(3 * cfg->K + 6) * c.width * c.height;
   }
   vs.total_tiles = (int32_t)tiles;
   return vs;
@@ -378,7 +378,7 @@ int htgs_state_bytes(const htgs_camera *cams, int32_t n_views, const htgs_config
   if ((e = check_cams(cams, n_views, cfg))) return e;
   int64_t b = 0;
   for (int v = 0; v < n_views; ++v)
-    b += (int64_t)(8 * cfg->K + 24) * cams[v].width * cams[v].height;
+    b += (int64_t)(12 * cfg->K + 24) * cams[v].width * cams[v].height;
   *bytes_out = b;
   return HTGS_OK;
 }

@@ -16,10 +16,10 @@ constexpr int kPreThreads = 256;
 
 // Raster record of one Gaussian in one view (float32). The Pluecker
 // direction d and moment m of the ray through a pixel are affine in the
-// pixel's offset from a reference point (xc, yc) near the splat's
-// footprint: d = D0 + dx Du + dy Dv, m = M0 + dx Mu + dy Mv, dx, dy in
-// pixels. Centring keeps the float32 evaluation of m accurate where rho is
-// small. (xc, yc) = (ixc + 0.5 - hx, iyc + 0.5 - hy).
+// pixel's offset from a reference pixel (ix, iy) inside the splat's
+// footprint: d = D0 + dx Du + dy Dv, m = M0 + dx Mu + dy Mv, with dx, dy
+// the integer pixel offsets. Centring keeps the float32 evaluation of m
+// accurate where rho is small.
 enum RecField {
   R_D0 = 0, R_DU = 3, R_DV = 6, R_M0 = 9, R_MU = 12, R_MV = 15,
   R_R3 = 18,    // third view row of M T (scaled axes' z components)
@@ -27,9 +27,10 @@ enum RecField {
   R_O = 22,     // opacity
   R_RC = 23,    // rho_c (squared cutoff radius)
   R_RGB = 24,   // colour (3)
-  R_HX = 27, R_HY = 28,
-  R_IX = 29, R_IY = 30,  // int32 bit patterns
-  R_FLAGS = 31           // bit c set: colour channel c was clamped at 0
+  R_IX = 27, R_IY = 28,  // reference pixel, int32 bit patterns
+  R_BB0 = 29,   // covered pixel rect: x0 | y0 << 16
+  R_BB1 = 30,   //                     x1 | y1 << 16 (inclusive)
+  R_FLAGS = 31  // bit c set: colour channel c was clamped at 0
 };
 
 // Per-instance backward partials: sums over the tile's pixels of the
@@ -39,10 +40,14 @@ enum PartialField {
   P_D0 = 0, P_DX = 3, P_DY = 6, P_M0 = 9, P_MX = 12, P_MY = 15, P_O = 18, P_C = 19
 };
 
-// Staged record in the raster kernels: tile-centred coefficients (28 floats).
+// Staged record in the raster kernels: tile-centred coefficients, the
+// instance's position in the tile list and its pixel rect relative to the
+// tile (32 floats).
 enum StageField {
   S_D0 = 0, S_DU = 3, S_DV = 6, S_M0 = 9, S_MU = 12, S_MV = 15, S_R3 = 18,
-  S_MUZ = 21, S_O = 22, S_RC = 23, S_RGB = 24, S_GID = 27, S_FLOATS = 28
+  S_MUZ = 21, S_O = 22, S_RC = 23, S_RGB = 24, S_POS = 27,
+  S_BB0 = 28, S_BB1 = 29, S_BB2 = 30, S_BB3 = 31,  // tile-local x0, y0, x1, y1 (int bits)
+  S_FLOATS = 32
 };
 
 struct ViewParams {

@@ -190,10 +190,10 @@ __device__ inline uint32_t preprocess_view(const GaussPtrs &gp, const KCfg &cfg,
   if (count == 0) return 0;
   *packed = (uint32_t)rect.x | ((uint32_t)rect.y << 10) | ((uint32_t)(rect.z - rect.x + 1) << 20);
 
-  // Reference point: the box centre clamped to the covered pixel range.
-  const double xc = fmin(fmax(p1, x0), x1 + 1.0);
-  const double yc = fmin(fmax(p2, y0), y1 + 1.0);
-  const double uc = (xc - cx) / fx, vc = (yc - cy) / fy;
+  // Reference point: the centre of the covered pixel nearest the box centre.
+  const double ixd = fmin(fmax(floor(p1), x0), x1);
+  const double iyd = fmin(fmax(floor(p2), y0), y1);
+  const double uc = (ixd + 0.5 - cx) / fx, vc = (iyd + 0.5 - cy) / fy;
   double D0[3], Du[3], Dv[3];
   cross3(Rv[0], Rv[1], D0);
   cross3(Rv[1], Rv[2], Du);
@@ -214,11 +214,10 @@ __device__ inline uint32_t preprocess_view(const GaussPtrs &gp, const KCfg &cfg,
   rec[R_MUZ] = (float)mv[2];
   rec[R_O] = (float)a.o;
   rec[R_RC] = (float)rc;
-  const double ixd = floor(xc), iyd = floor(yc);
-  rec[R_HX] = (float)(0.5 - (xc - ixd));
-  rec[R_HY] = (float)(0.5 - (yc - iyd));
   rec[R_IX] = __int_as_float((int)ixd);
   rec[R_IY] = __int_as_float((int)iyd);
+  rec[R_BB0] = __uint_as_float((uint32_t)x0 | ((uint32_t)y0 << 16));
+  rec[R_BB1] = __uint_as_float((uint32_t)x1 | ((uint32_t)y1 << 16));
 
   // View-dependent colour (Sec. 3.1; 3DGS convention).
   double dv[3] = {a.mu[0] - V.cam_pos[0], a.mu[1] - V.cam_pos[1], a.mu[2] - V.cam_pos[2]};

@@ -1,26 +1,30 @@
 // Tile rasterizer, forward and backward (Sec. 3.2 and Sec. 3.3).
 //
-// Forward: one workgroup per tile, one lane per pixel. The tile's instances
-// are staged through LDS in batches of one record per lane; every lane then
-// walks the batch: Pluecker direction d and moment m of its pixel ray in
-// splat space (affine in the pixel offset, tile-centred), rho^2 = |m|^2/|d|^2
-// (Eq. rho-pluecker), alpha = min(alpha_max, o exp(-rho^2/2)), and for
-// fragments with alpha >= tau_K the view depth of the maximum-density point
-// z = (M T [(d x m)/|d|^2; 1])_z (Sec. 3.3). Those go through an unrolled
-// insertion network into a register core of K (depth, alpha, id, rgb)
-// entries; what falls off the end, and every other fragment, is added to
-// the order-independent tail (sum alpha, sum alpha rgb, prod (1 - alpha)).
-// The composite is Eq. pixel_color_computation.
+// Forward: one workgroup per tile; each wave owns an 8x8 pixel block, one
+// lane per pixel. The tile's instances are staged through LDS in batches of
+// one record per lane; each wave then keeps only the staged splats whose
+// covered pixel rect meets its block and walks them: Pluecker direction d
+// and moment m of its pixel ray in splat space (affine in the pixel offset,
+// tile-centred), rho^2 = |m|^2/|d|^2 (Eq. rho-pluecker), alpha =
+// min(alpha_max, o exp(-rho^2/2)), and for fragments with alpha >= tau_K the
+// view depth of the maximum-density point z = (M T [(d x m)/|d|^2; 1])_z
+// (Sec. 3.3). Those go through an unrolled insertion network into a
+// register core of K (depth, alpha, list position, rgb) entries; what falls
+// off the end, and every other fragment, is added to the order-independent
+// tail (sum alpha, sum alpha rgb, prod (1 - alpha)). The composite is
+// Eq. pixel_color_computation.
 //
 // Backward: one workgroup per tile. First each pixel's adjoint factors are
 // built in LDS: the core terms T_i (c_i - B_i) . G and T_i by walking the
 // stored core back to front, and the tail factors shared by every tail
 // fragment of the pixel (Sec. 3.3, last paragraph). Then each wave takes 64
-// of the tile's instances, one per lane, and loops over the tile's pixels,
-// recomputing rho^2 and alpha exactly as the forward did and accumulating
-// the gradient of its splat's record in registers. Each lane writes one
-// partial per instance, so there are no floating-point atomics and the
-// result is deterministic.
+// of the tile's instances, one per lane, and loops over the tile's pixels
+// (skipping 8x8 blocks no lane's rect touches), recomputing rho^2 and alpha
+// exactly as the forward did. Because d and m are affine in the pixel
+// offset (lx, ly), the gradient w.r.t. their 18 affine coefficients follows
+// from six moments of dL/d(rho^2)-weights per vector (sum of w, w lx, w ly,
+// w lx^2, w lx ly, w ly^2), accumulated in registers. Each lane writes one
+// partial per instance: no floating-point atomics, deterministic results.
 #include <float.h>
 
 #include "common.h"
@@ -32,14 +36,44 @@ constexpr float kNegHalfLog2e = -0.72134752044448170368f;  // -1 / (2 ln 2)
 __device__ __forceinline__ float exp2_fast(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ float rcp_fast(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// Tile-local pixel coordinates and their products, read as scalars:
+// (lx, ly, lx^2, lx ly, ly^2, -, -, -) for tile pixel index ly * TW + lx.
+template <int TW, int TH>
+struct PixTable {
+  float v[TW * TH][8];
+};
+
+constexpr PixTable<16, 16> make_table16() {
+  PixTable<16, 16> t{};
+  for (int p = 0; p < 256; ++p) {
+    const float x = (float)(p % 16), y = (float)(p / 16);
+    t.v[p][0] = x; t.v[p][1] = y; t.v[p][2] = x * x; t.v[p][3] = x * y; t.v[p][4] = y * y;
+  }
+  return t;
+}
+constexpr PixTable<8, 8> make_table8() {
+  PixTable<8, 8> t{};
+  for (int p = 0; p < 64; ++p) {
+    const float x = (float)(p % 8), y = (float)(p / 8);
+    t.v[p][0] = x; t.v[p][1] = y; t.v[p][2] = x * x; t.v[p][3] = x * y; t.v[p][4] = y * y;
+  }
+  return t;
+}
+__constant__ PixTable<16, 16> kPix16 = make_table16();
+__constant__ PixTable<8, 8> kPix8 = make_table8();
+
+template <int TW>
+__device__ __forceinline__ const float *pix_entry(int p) {
+  if constexpr (TW == 16) return kPix16.v[p];
+  else return kPix8.v[p];
+}
+
 // Tile-centred staged record: d = D0t + lx Du + ly Dv with (lx, ly) the
 // pixel's integer offset from the tile's first pixel.
 __device__ __forceinline__ void stage_record(const float *__restrict__ rec, int px0, int py0,
-                                             uint32_t gid, float *st) {
-  const int ix = __float_as_int(rec[R_IX]);
-  const int iy = __float_as_int(rec[R_IY]);
-  const float dx0 = (float)(px0 - ix) + rec[R_HX];
-  const float dy0 = (float)(py0 - iy) + rec[R_HY];
+                                             uint32_t pos, float *st) {
+  const float dx0 = (float)(px0 - __float_as_int(rec[R_IX]));
+  const float dy0 = (float)(py0 - __float_as_int(rec[R_IY]));
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     st[S_D0 + k] = fmaf(dy0, rec[R_DV + k], fmaf(dx0, rec[R_DU + k], rec[R_D0 + k]));
@@ -54,7 +88,12 @@ __device__ __forceinline__ void stage_record(const float *__restrict__ rec, int 
   st[S_MUZ] = rec[R_MUZ];
   st[S_O] = rec[R_O];
   st[S_RC] = rec[R_RC];
-  st[S_GID] = __uint_as_float(gid);
+  st[S_POS] = __uint_as_float(pos);
+  const uint32_t b0 = __float_as_uint(rec[R_BB0]), b1 = __float_as_uint(rec[R_BB1]);
+  st[S_BB0] = __int_as_float((int)(b0 & 0xffffu) - px0);
+  st[S_BB1] = __int_as_float((int)(b0 >> 16) - py0);
+  st[S_BB2] = __int_as_float((int)(b1 & 0xffffu) - px0);
+  st[S_BB3] = __int_as_float((int)(b1 >> 16) - py0);
 }
 
 __device__ __forceinline__ void eval_ray(const float *st, float lx, float ly, float d[3], float m[3],
@@ -104,6 +143,11 @@ __device__ __forceinline__ bool tile_info(const ViewSet &vs, TileInfo &ti) {
   return true;
 }
 
+__device__ __forceinline__ bool rect_meets_block(const float *bb, int bx, int by) {
+  return (__float_as_int(bb[2]) >= bx) && (__float_as_int(bb[0]) <= bx + 7) &&
+         (__float_as_int(bb[3]) >= by) && (__float_as_int(bb[1]) <= by + 7);
+}
+
 // ---------------------------------------------------------------------------
 // Forward
 // ---------------------------------------------------------------------------
@@ -112,15 +156,19 @@ __global__ void __launch_bounds__(TW *TH) k_raster_fwd(Ws w, ViewSet vs, KCfg cf
                                                        float *__restrict__ state,
                                                        const uint32_t *__restrict__ vals) {
   constexpr int NT = TW * TH;
+  constexpr int NW = NT / 64;   // waves, one 8x8 block each
+  constexpr int BX = TW / 8;
   constexpr int SV = S_FLOATS / 4;
   __shared__ float4 s_stage[NT * SV];
+  __shared__ uint16_t s_list[NW][NT];
   __shared__ uint32_t s_nfrag;
 
   TileInfo ti;
   if (!tile_info(vs, ti)) return;
   const ViewParams &V = vs.v[ti.v];
-  const int tid = threadIdx.x;
-  const int lx = tid % TW, ly = tid / TW;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int bx = (wave % BX) * 8, by = (wave / BX) * 8;
+  const int lx = bx + (lane & 7), ly = by + (lane >> 3);
   const int px0 = ti.tx * TW, py0 = ti.ty * TH;
   const int px = px0 + lx, py = py0 + ly;
   const bool inside = (px < V.width) && (py < V.height);
@@ -129,12 +177,13 @@ __global__ void __launch_bounds__(TW *TH) k_raster_fwd(Ws w, ViewSet vs, KCfg cf
   const int K = cfg.K;
   const float tau_core = cfg.tau_core, amax = cfg.alpha_max;
   const float *recs = w.records + (int64_t)ti.v * cfg.n * kRecFloats;
+  const uint64_t lanemask_lt = (1ull << lane) - 1ull;
 
   float cz[KMAX], ca[KMAX], cr[KMAX], cg[KMAX], cb[KMAX];
-  int cid[KMAX];
+  int cp[KMAX];
 #pragma unroll
   for (int i = 0; i < KMAX; ++i) {
-    cz[i] = INFINITY; ca[i] = 0.f; cr[i] = cg[i] = cb[i] = 0.f; cid[i] = -1;
+    cz[i] = INFINITY; ca[i] = 0.f; cr[i] = cg[i] = cb[i] = 0.f; cp[i] = -1;
   }
   float zlast = INFINITY;
   float A = 0.f, S0 = 0.f, S1 = 0.f, S2 = 0.f, P = 1.f;
@@ -149,17 +198,37 @@ __global__ void __launch_bounds__(TW *TH) k_raster_fwd(Ws w, ViewSet vs, KCfg cf
       float rec[kRecFloats];
       load_record(recs, gid, rec);
       float st[S_FLOATS];
-      stage_record(rec, px0, py0, gid, st);
+      stage_record(rec, px0, py0, base - rg.x + tid, st);
 #pragma unroll
       for (int k = 0; k < SV; ++k)
         s_stage[tid * SV + k] = make_float4(st[4 * k], st[4 * k + 1], st[4 * k + 2], st[4 * k + 3]);
     }
     __syncthreads();
+    // This wave's list: the staged splats whose pixel rect meets its block.
+    int nlist = cnt;
+    if constexpr (NW > 1) {
+      nlist = 0;
+      for (int j0 = 0; j0 < cnt; j0 += 64) {
+        const int j = j0 + lane;
+        bool hit = false;
+        if (j < cnt) {
+          const float4 b = s_stage[j * SV + S_BB0 / 4];
+          const float bb[4] = {b.x, b.y, b.z, b.w};
+          hit = rect_meets_block(bb, bx, by);
+        }
+        const uint64_t mk = __ballot(hit);
+        if (hit) s_list[wave][nlist + __popcll(mk & lanemask_lt)] = (uint16_t)j;
+        nlist += __popcll(mk);
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
     if (!inside) continue;
-    for (int j = 0; j < cnt; ++j) {
-      float st[S_FLOATS];
+    for (int q = 0; q < nlist; ++q) {
+      int j = q;
+      if constexpr (NW > 1) j = s_list[wave][q];
+      float st[28];
 #pragma unroll
-      for (int k = 0; k < SV; ++k) {
+      for (int k = 0; k < 7; ++k) {
         const float4 t = s_stage[j * SV + k];
         st[4 * k] = t.x; st[4 * k + 1] = t.y; st[4 * k + 2] = t.z; st[4 * k + 3] = t.w;
       }
@@ -175,7 +244,7 @@ __global__ void __launch_bounds__(TW *TH) k_raster_fwd(Ws w, ViewSet vs, KCfg cf
       if (alpha >= tau_core && K > 0) {
         float z = max_point_depth(st, d, m, inv);
         if (z < zlast) {
-          int id = (int)__float_as_uint(st[S_GID]);
+          int id = (int)__float_as_uint(st[S_POS]);
           float a = alpha;
           float zl = zlast;
 #pragma unroll
@@ -184,7 +253,7 @@ __global__ void __launch_bounds__(TW *TH) k_raster_fwd(Ws w, ViewSet vs, KCfg cf
               const bool sw = z < cz[i];
               const float nz = sw ? z : cz[i]; z = sw ? cz[i] : z; cz[i] = nz;
               const float na = sw ? a : ca[i]; a = sw ? ca[i] : a; ca[i] = na;
-              const int ni = sw ? id : cid[i]; id = sw ? cid[i] : id; cid[i] = ni;
+              const int ni = sw ? id : cp[i]; id = sw ? cp[i] : id; cp[i] = ni;
               const float nr = sw ? tr : cr[i]; tr = sw ? cr[i] : tr; cr[i] = nr;
               const float ng = sw ? tg : cg[i]; tg = sw ? cg[i] : tg; cg[i] = ng;
               const float nb = sw ? tb : cb[i]; tb = sw ? cb[i] : tb; cb[i] = nb;
@@ -214,7 +283,7 @@ __global__ void __launch_bounds__(TW *TH) k_raster_fwd(Ws w, ViewSet vs, KCfg cf
   float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
 #pragma unroll
   for (int i = 0; i < KMAX; ++i) {
-    if (i < K && cid[i] >= 0) {
+    if (i < K && cp[i] >= 0) {
       const float wgt = ca[i] * T;
       C0 = fmaf(wgt, cr[i], C0);
       C1 = fmaf(wgt, cg[i], C1);
@@ -239,16 +308,18 @@ __global__ void __launch_bounds__(TW *TH) k_raster_fwd(Ws w, ViewSet vs, KCfg cf
 #pragma unroll
     for (int i = 0; i < KMAX; ++i) {
       if (i < K) {
-        sp[(int64_t)i * npix] = __int_as_float(cid[i]);
+        const int gid = cp[i] >= 0 ? (int)vals[rg.x + (uint32_t)cp[i]] : -1;
+        sp[(int64_t)i * npix] = __int_as_float(gid);
         sp[(int64_t)(K + i) * npix] = ca[i];
+        sp[(int64_t)(2 * K + i) * npix] = __int_as_float(cp[i]);
       }
     }
-    sp[(int64_t)(2 * K) * npix] = T;
-    sp[(int64_t)(2 * K + 1) * npix] = A;
-    sp[(int64_t)(2 * K + 2) * npix] = S0;
-    sp[(int64_t)(2 * K + 3) * npix] = S1;
-    sp[(int64_t)(2 * K + 4) * npix] = S2;
-    sp[(int64_t)(2 * K + 5) * npix] = P;
+    sp[(int64_t)(3 * K) * npix] = T;
+    sp[(int64_t)(3 * K + 1) * npix] = A;
+    sp[(int64_t)(3 * K + 2) * npix] = S0;
+    sp[(int64_t)(3 * K + 3) * npix] = S1;
+    sp[(int64_t)(3 * K + 4) * npix] = S2;
+    sp[(int64_t)(3 * K + 5) * npix] = P;
   }
 }
 
@@ -257,10 +328,10 @@ __global__ void __launch_bounds__(TW *TH) k_raster_fwd(Ws w, ViewSet vs, KCfg cf
 // ---------------------------------------------------------------------------
 template <int KMAX>
 struct PixLayout {
-  // G(3), w1, q1, q2, pad(2), ids[KMAX], dL/dalpha_i[KMAX], T_i[KMAX]
-  static constexpr int kIds = 8;
-  static constexpr int kCoef = 8 + KMAX;
-  static constexpr int kT = 8 + 2 * KMAX;
+  // G(3), w1, q1, q2, pad(2), dL/dalpha_i[KMAX], T_i[KMAX], list position_i[KMAX]
+  static constexpr int kCoef = 8;
+  static constexpr int kT = 8 + KMAX;
+  static constexpr int kPos = 8 + 2 * KMAX;
   static constexpr int kStride = ((8 + 3 * KMAX) + 3) / 4 * 4;
 };
 
@@ -269,8 +340,12 @@ __global__ void __launch_bounds__(256) k_raster_bwd(Ws w, ViewSet vs, KCfg cfg,
                                                     const float *__restrict__ state,
                                                     const uint32_t *__restrict__ vals) {
   constexpr int NT = TW * TH;
+  constexpr int NB = NT / 64;
+  constexpr int BX = TW / 8;
   using L = PixLayout<KMAX>;
   __shared__ float4 s_pix[NT * L::kStride / 4];
+  __shared__ uint8_t s_cnt[4][NT];
+  __shared__ uint16_t s_ent[4][NT][KMAX];
 
   TileInfo ti;
   if (!tile_info(vs, ti)) return;
@@ -287,10 +362,10 @@ __global__ void __launch_bounds__(256) k_raster_bwd(Ws w, ViewSet vs, KCfg cfg,
     const int px = px0 + p % TW, py = py0 + p / TW;
     float *Pp = sp_all + p * L::kStride;
     float G[3] = {0.f, 0.f, 0.f}, w1 = 0.f, q1 = 0.f, q2 = 0.f;
-    int ids[KMAX];
+    int pos[KMAX];
     float coef[KMAX], Ti[KMAX];
 #pragma unroll
-    for (int i = 0; i < KMAX; ++i) { ids[i] = -1; coef[i] = 0.f; Ti[i] = 0.f; }
+    for (int i = 0; i < KMAX; ++i) { pos[i] = -1; coef[i] = 0.f; Ti[i] = 0.f; }
     if (px < V.width && py < V.height) {
       const int64_t pix = (int64_t)py * V.width + px;
       for (int c = 0; c < 3; ++c) G[c] = V.grad_rgb[c * npix + pix];
@@ -300,22 +375,23 @@ __global__ void __launch_bounds__(256) k_raster_bwd(Ws w, ViewSet vs, KCfg cfg,
       for (int i = 0; i < KMAX; ++i) {
         ca[i] = 0.f; cc[i][0] = cc[i][1] = cc[i][2] = 0.f;
         if (i < K) {
-          ids[i] = __float_as_int(sp[(int64_t)i * npix]);
+          const int id = __float_as_int(sp[(int64_t)i * npix]);
           ca[i] = sp[(int64_t)(K + i) * npix];
-          if (ids[i] >= 0) {
-            const float *r = recs + (int64_t)ids[i] * kRecFloats + R_RGB;
+          pos[i] = __float_as_int(sp[(int64_t)(2 * K + i) * npix]);
+          if (id >= 0) {
+            const float *r = recs + (int64_t)id * kRecFloats + R_RGB;
             cc[i][0] = r[0]; cc[i][1] = r[1]; cc[i][2] = r[2];
           }
         }
       }
-      const float A = sp[(int64_t)(2 * K + 1) * npix];
-      const float S[3] = {sp[(int64_t)(2 * K + 2) * npix], sp[(int64_t)(2 * K + 3) * npix],
-                          sp[(int64_t)(2 * K + 4) * npix]};
-      const float Pt = sp[(int64_t)(2 * K + 5) * npix];
+      const float A = sp[(int64_t)(3 * K + 1) * npix];
+      const float S[3] = {sp[(int64_t)(3 * K + 2) * npix], sp[(int64_t)(3 * K + 3) * npix],
+                          sp[(int64_t)(3 * K + 4) * npix]};
+      const float Pt = sp[(int64_t)(3 * K + 5) * npix];
       float T = 1.f;
 #pragma unroll
       for (int i = 0; i < KMAX; ++i) {
-        if (i < K && ids[i] >= 0) {
+        if (i < K && pos[i] >= 0) {
           Ti[i] = T;
           T *= 1.f - ca[i];
         }
@@ -332,7 +408,7 @@ __global__ void __launch_bounds__(256) k_raster_bwd(Ws w, ViewSet vs, KCfg cfg,
       float B[3] = {X[0], X[1], X[2]};
 #pragma unroll
       for (int i = KMAX - 1; i >= 0; --i) {
-        if (i < K && ids[i] >= 0) {
+        if (i < K && pos[i] >= 0) {
           coef[i] = Ti[i] * (G[0] * (cc[i][0] - B[0]) + G[1] * (cc[i][1] - B[1]) +
                              G[2] * (cc[i][2] - B[2]));
           for (int c = 0; c < 3; ++c) B[c] = fmaf(ca[i], cc[i][c] - B[c], B[c]);
@@ -349,9 +425,9 @@ __global__ void __launch_bounds__(256) k_raster_bwd(Ws w, ViewSet vs, KCfg cfg,
     Pp[3] = w1; Pp[4] = q1; Pp[5] = q2; Pp[6] = 0.f; Pp[7] = 0.f;
 #pragma unroll
     for (int i = 0; i < KMAX; ++i) {
-      Pp[L::kIds + i] = __int_as_float(ids[i]);
       Pp[L::kCoef + i] = coef[i];
       Pp[L::kT + i] = Ti[i];
+      Pp[L::kPos + i] = __int_as_float(pos[i]);
     }
   }
   __syncthreads();
@@ -361,6 +437,7 @@ __global__ void __launch_bounds__(256) k_raster_bwd(Ws w, ViewSet vs, KCfg cfg,
   const uint32_t count = rg.y - rg.x;
   const uint32_t nch = (count + 63u) >> 6;
   const float tau_core = cfg.tau_core, amax = cfg.alpha_max;
+  (void)tau_core;
   for (uint32_t c = wave; c < nch; c += 4) {
     const uint32_t j = rg.x + c * 64u + lane;
     const bool active = j < rg.y;
@@ -368,12 +445,16 @@ __global__ void __launch_bounds__(256) k_raster_bwd(Ws w, ViewSet vs, KCfg cfg,
 #pragma unroll
     for (int k = 0; k < S_FLOATS; ++k) st[k] = 0.f;
     st[S_RC] = -1.f;
-    uint32_t gid = 0, slot = 0;
+    st[S_BB0] = __int_as_float(1 << 20);
+    st[S_BB1] = __int_as_float(1 << 20);
+    st[S_BB2] = __int_as_float(-1);
+    st[S_BB3] = __int_as_float(-1);
+    uint32_t slot = 0;
     if (active) {
-      gid = vals[j];
+      const uint32_t gid = vals[j];
       float rec[kRecFloats];
       load_record(recs, gid, rec);
-      stage_record(rec, px0, py0, gid, st);
+      stage_record(rec, px0, py0, j - rg.x, st);
       uint32_t pre = 0;
       for (int u = 0; u < ti.v; ++u) {
         const int4 r = w.rects[(int64_t)u * cfg.n + gid];
@@ -382,71 +463,111 @@ __global__ void __launch_bounds__(256) k_raster_bwd(Ws w, ViewSet vs, KCfg cfg,
       const int4 r = w.rects[(int64_t)ti.v * cfg.n + gid];
       slot = w.offsets[gid] + pre + (uint32_t)((ti.ty - r.y) * (r.z - r.x + 1) + (ti.tx - r.x));
     }
-    float acc[22];
-#pragma unroll
-    for (int k = 0; k < 22; ++k) acc[k] = 0.f;
-    for (int p = 0; p < NT; ++p) {
-      const float flx = (float)(p % TW), fly = (float)(p / TW);
-      float d[3], m[3], dd, mm;
-      eval_ray(st, flx, fly, d, m, dd, mm);
-      if (!(active && is_fragment(dd, mm, st[S_RC]))) continue;
+    // Core members of each pixel that belong to this chunk: (lane, slot).
+    for (int q = 0; q < NB; ++q) {
+      const int p = q * 64 + lane;
       const float *Pp = sp_all + p * L::kStride;
-      const float inv = rcp_fast(dd);
-      const float r2 = mm * inv;
-      const float e = exp2_fast(r2 * kNegHalfLog2e);
-      const float araw = st[S_O] * e;
-      const float alpha = fminf(amax, araw);
-      const float G0 = Pp[0], G1 = Pp[1], G2 = Pp[2];
-      bool core = false;
-      float dLda = 0.f, Tc = 0.f;
-      if (alpha >= tau_core) {
+      uint32_t n = 0;
 #pragma unroll
-        for (int i = 0; i < KMAX; ++i) {
-          if (i < K && __float_as_uint(Pp[L::kIds + i]) == gid) {
-            core = true;
-            dLda = Pp[L::kCoef + i];
-            Tc = Pp[L::kT + i];
+      for (int i = 0; i < KMAX; ++i) {
+        if (i < K) {
+          const int ps = __float_as_int(Pp[L::kPos + i]);
+          const uint32_t dl = (uint32_t)(ps - (int)(c * 64u));
+          if (ps >= 0 && dl < 64u) {
+            s_ent[wave][p][n] = (uint16_t)(dl | ((uint32_t)i << 8));
+            ++n;
           }
         }
       }
-      float wc;
-      if (core) {
-        wc = alpha * Tc;
-      } else {
-        const float w1 = Pp[3];
-        const float gdc = fmaf(G2, st[S_RGB + 2], fmaf(G1, st[S_RGB + 1], G0 * st[S_RGB]));
-        dLda = w1 * gdc - Pp[4] - Pp[5] / (1.f - alpha);
-        wc = w1 * alpha;
-      }
-      acc[P_C + 0] = fmaf(wc, G0, acc[P_C + 0]);
-      acc[P_C + 1] = fmaf(wc, G1, acc[P_C + 1]);
-      acc[P_C + 2] = fmaf(wc, G2, acc[P_C + 2]);
-      if (araw <= amax) {
-        acc[P_O] = fmaf(dLda, e, acc[P_O]);
-        const float s1 = -alpha * dLda * inv;   // 2 dL/drho^2 / |d|^2, dL/drho^2 = -alpha/2 dL/dalpha
-        const float s2 = -s1 * r2;
+      s_cnt[wave][p] = (uint8_t)n;
+    }
+    __builtin_amdgcn_wave_barrier();
+
+    // acc: d-moments (6), m-moments (6), dL/do, dL/drgb (3)
+    float acc[16];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          const float gm = s1 * m[k];
-          const float gd = s2 * d[k];
-          acc[P_M0 + k] += gm;
-          acc[P_MX + k] = fmaf(flx, gm, acc[P_MX + k]);
-          acc[P_MY + k] = fmaf(fly, gm, acc[P_MY + k]);
-          acc[P_D0 + k] += gd;
-          acc[P_DX + k] = fmaf(flx, gd, acc[P_DX + k]);
-          acc[P_DY + k] = fmaf(fly, gd, acc[P_DY + k]);
+    for (int k = 0; k < 16; ++k) acc[k] = 0.f;
+    for (int blk = 0; blk < NB; ++blk) {
+      const int bx = (blk % BX) * 8, by = (blk / BX) * 8;
+      const bool hitb = active && rect_meets_block(st + S_BB0, bx, by);
+      if (__ballot(hitb) == 0ull) continue;
+      for (int q = 0; q < 64; ++q) {
+        const int p = (by + (q >> 3)) * TW + bx + (q & 7);
+        const float *tab = pix_entry<TW>(p);
+        const float flx = tab[0], fly = tab[1];
+        float d[3], m[3], dd, mm;
+        eval_ray(st, flx, fly, d, m, dd, mm);
+        const bool frag = hitb && is_fragment(dd, mm, st[S_RC]);
+        const int ncore = s_cnt[wave][p];
+        int cslot = -1;
+        for (int e = 0; e < ncore; ++e) {
+          const uint32_t ent = s_ent[wave][p][e];
+          if ((int)(ent & 255u) == lane) cslot = (int)(ent >> 8);
+        }
+        if (!frag) continue;
+        const float *Pp = sp_all + p * L::kStride;
+        const float inv = rcp_fast(dd);
+        const float r2 = mm * inv;
+        const float e = exp2_fast(r2 * kNegHalfLog2e);
+        const float araw = st[S_O] * e;
+        const float alpha = fminf(amax, araw);
+        const float G0 = Pp[0], G1 = Pp[1], G2 = Pp[2], w1 = Pp[3];
+        float dLda, wc;
+        if (cslot >= 0) {
+          dLda = Pp[L::kCoef + cslot];
+          wc = alpha * Pp[L::kT + cslot];
+        } else {
+          const float gdc = fmaf(G2, st[S_RGB + 2], fmaf(G1, st[S_RGB + 1], G0 * st[S_RGB]));
+          dLda = fmaf(w1, gdc, -Pp[4]) - Pp[5] * rcp_fast(1.f - alpha);
+          wc = w1 * alpha;
+        }
+        acc[13] = fmaf(wc, G0, acc[13]);
+        acc[14] = fmaf(wc, G1, acc[14]);
+        acc[15] = fmaf(wc, G2, acc[15]);
+        if (araw <= amax) {
+          acc[12] = fmaf(dLda, e, acc[12]);
+          const float s1 = -alpha * dLda * inv;   // weight of m: 2 dL/drho^2 / |d|^2
+          const float s2 = -s1 * r2;              // weight of d
+          acc[0] += s2;
+          acc[1] = fmaf(flx, s2, acc[1]);
+          acc[2] = fmaf(fly, s2, acc[2]);
+          acc[3] = fmaf(tab[2], s2, acc[3]);
+          acc[4] = fmaf(tab[3], s2, acc[4]);
+          acc[5] = fmaf(tab[4], s2, acc[5]);
+          acc[6] += s1;
+          acc[7] = fmaf(flx, s1, acc[7]);
+          acc[8] = fmaf(fly, s1, acc[8]);
+          acc[9] = fmaf(tab[2], s1, acc[9]);
+          acc[10] = fmaf(tab[3], s1, acc[10]);
+          acc[11] = fmaf(tab[4], s1, acc[11]);
         }
       }
     }
     if (active && (uint64_t)slot < (uint64_t)w.capacity) {
+      float out[kPartialFloats];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const float D0 = st[S_D0 + k], Du = st[S_DU + k], Dv = st[S_DV + k];
+        const float M0 = st[S_M0 + k], Mu = st[S_MU + k], Mv = st[S_MV + k];
+        out[P_D0 + k] = fmaf(Dv, acc[2], fmaf(Du, acc[1], D0 * acc[0]));
+        out[P_DX + k] = fmaf(Dv, acc[4], fmaf(Du, acc[3], D0 * acc[1]));
+        out[P_DY + k] = fmaf(Dv, acc[5], fmaf(Du, acc[4], D0 * acc[2]));
+        out[P_M0 + k] = fmaf(Mv, acc[8], fmaf(Mu, acc[7], M0 * acc[6]));
+        out[P_MX + k] = fmaf(Mv, acc[10], fmaf(Mu, acc[9], M0 * acc[7]));
+        out[P_MY + k] = fmaf(Mv, acc[11], fmaf(Mu, acc[10], M0 * acc[8]));
+      }
+      out[P_O] = acc[12];
+      out[P_C] = acc[13];
+      out[P_C + 1] = acc[14];
+      out[P_C + 2] = acc[15];
+      out[22] = 0.f;
+      out[23] = 0.f;
       float4 *dst = reinterpret_cast<float4 *>(w.partials + (int64_t)slot * kPartialFloats);
-      dst[0] = make_float4(acc[0], acc[1], acc[2], acc[3]);
-      dst[1] = make_float4(acc[4], acc[5], acc[6], acc[7]);
-      dst[2] = make_float4(acc[8], acc[9], acc[10], acc[11]);
-      dst[3] = make_float4(acc[12], acc[13], acc[14], acc[15]);
-      dst[4] = make_float4(acc[16], acc[17], acc[18], acc[19]);
-      dst[5] = make_float4(acc[20], acc[21], 0.f, 0.f);
+#pragma unroll
+      for (int k = 0; k < kPartialFloats / 4; ++k)
+        dst[k] = make_float4(out[4 * k], out[4 * k + 1], out[4 * k + 2], out[4 * k + 3]);
     }
+    __builtin_amdgcn_wave_barrier();
   }
 }
 

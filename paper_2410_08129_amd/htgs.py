@@ -317,12 +317,13 @@ def state_planes(frame: Frame, view: int = 0):
     K = int(frame.st.K)
     off = 0
     for c in frame.cams[:view]:
-        off += (2 * K + 6) * c.width * c.height
+        off += (3 * K + 6) * c.width * c.height
     cam = frame.cams[view]
     npix = cam.width * cam.height
-    blk = frame.state[off: off + (2 * K + 6) * npix].view(2 * K + 6, cam.height, cam.width)
-    return dict(core_ids=blk[:K].view(torch.int32), core_alpha=blk[K:2 * K], T=blk[2 * K],
-                A=blk[2 * K + 1], S=blk[2 * K + 2: 2 * K + 5], P=blk[2 * K + 5])
+    blk = frame.state[off: off + (3 * K + 6) * npix].view(3 * K + 6, cam.height, cam.width)
+    return dict(core_ids=blk[:K].view(torch.int32), core_alpha=blk[K:2 * K],
+                core_pos=blk[2 * K:3 * K].view(torch.int32), T=blk[3 * K], A=blk[3 * K + 1],
+                S=blk[3 * K + 2: 3 * K + 5], P=blk[3 * K + 5])
 
 
 # ---------------------------------------------------------------------------

@@ -268,8 +268,15 @@ def test_degenerate_splats_parity_and_finite():
                                 near_degenerate_frac=0.02)
     cam = scenes.look_at((0, 0, -25), (0, 0, 0), (0, -1, 0), 70.0, 3840, 2160)
     st = scenes.RenderSettings(K=16, tile_w=8, tile_h=8)
-    # only a crop is rendered on both sides
-    crop = cam.crop(1700, 900, 96, 80)
+    # a crop centred on a visible zero-axis splat is rendered on both sides
+    pre = oracle.splat.prepare(sc.means, sc.log_scales, sc.quats, sc.opacity_logits, cam,
+                               st.tau_alpha)
+    p = pre['p'].numpy()
+    deg = np.isinf(sc.log_scales).any(1)
+    cand = np.nonzero(deg & pre['visible'].numpy() & (p[:, 0] > 100) & (p[:, 0] < 3700)
+                      & (p[:, 1] > 100) & (p[:, 1] < 2000))[0]
+    g = int(cand[0])
+    crop = cam.crop(int(p[g, 0]) - 48, int(p[g, 1]) - 40, 96, 80)
     params, frame = gpu_forward(sc, [crop], st)
     img = frame.images[0]
     assert torch.isfinite(img).all()
