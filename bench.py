@@ -40,16 +40,15 @@ def workload(name):
     from paper_2410_08129_amd import scenes
     if name == "1080p":
         sc, cams, st = scenes.workload_1080p()
-        desc = "1M clustered Gaussians, SH3, 1920x1080, fov 50, K=8, 16x16 tiles, fwd+bwd (L1 to smooth target)"
+        desc = "1M clustered Gaussians, SH3, 1920x1080, fov 50, K=8, 8x8 tiles, fwd+bwd (L1 to smooth target)"
     elif name == "720p":
         sc, cams, st = scenes.workload_720p()
-        desc = "1M clustered Gaussians, SH3, 1280x720, fov 50, K=8, 16x16 tiles, fwd+bwd (L1 to smooth target)"
+        desc = "1M clustered Gaussians, SH3, 1280x720, fov 50, K=8, 8x8 tiles, fwd+bwd (L1 to smooth target)"
     elif name == "small":
         sc, cams, st = scenes.workload_small()
         desc = "4096 uniform Gaussians, SH0, 128x128, fov 60, K=4, 16x16 tiles, fwd+bwd"
     elif name == "stress":
         sc, cams, st = scenes.workload_stress()
-        st.tile_w = st.tile_h = 8
         desc = "6M clustered Gaussians (10% zero-axis, 2% 1e-7-axis), SH3, 3840x2160, fov 70, K=16, 8x8 tiles, fwd+bwd"
     else:
         raise SystemExit(f"unknown workload {name}")
@@ -92,6 +91,8 @@ def main():
     ap.add_argument("--tile", type=int, default=0, help="override tile size (8 or 16)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forward-only", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 256 MiB device copy (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -107,7 +108,8 @@ def main():
     sc, cams, st, desc = workload(args.workload)
     if args.tile:
         st.tile_w = st.tile_h = args.tile
-        desc = desc.replace("16x16 tiles", f"{args.tile}x{args.tile} tiles")
+        for t in ("8x8 tiles", "16x16 tiles"):
+            desc = desc.replace(t, f"{args.tile}x{args.tile} tiles")
     cam = cams[0]
     dev = torch.device("cuda:0")
     params = [torch.tensor(a, device=dev) for a in sc.arrays()]
@@ -212,6 +214,14 @@ def main():
     }
     if args.workload != "1080p" or args.forward_only:
         out["metric"] = f"{'fwd' if args.forward_only else 'fwd+bwd'} ms/frame ({args.workload})"
+    if args.calibrate_copy:
+        # an elementwise kernel (not a DMA copy) so the HBM counters see it
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = {"read": src.numel() * 4, "write": dst.numel() * 4}
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(sc, cam, st)

@@ -50,7 +50,7 @@ enum {
 
 #define HTGS_MAX_VIEWS 16
 
-/* Gaussian parameters (Sec. 3.1). n may be 0.
+/* Gaussian parameters (Sec. 3.1). 0 <= n < 2^27.
  *  means          [n,3]  world-space centres
  *  log_scales     [n,3]  s = exp(log_scale); -INFINITY gives an exact zero axis
  *  quats          [n,4]  (w,x,y,z), normalised internally, must be non-zero
@@ -182,8 +182,8 @@ int htgs_read_status(const void *ws, int64_t ws_bytes, uint32_t *flags_out,
  * Host-side state, not thread-safe; keep it disabled during graph capture. */
 enum {
   HTGS_STAGE_FILL = 0, HTGS_STAGE_PREPROCESS = 1, HTGS_STAGE_SORT = 2, HTGS_STAGE_RANGES = 3,
-  HTGS_STAGE_RASTER_FWD = 4, HTGS_STAGE_RASTER_BWD = 5, HTGS_STAGE_PREPROCESS_BWD = 6,
-  HTGS_NUM_STAGES = 7
+  HTGS_STAGE_RASTER_FWD = 4, HTGS_STAGE_RASTER_BWD = 5, HTGS_STAGE_REDUCE = 6,
+  HTGS_STAGE_PREPROCESS_BWD = 7, HTGS_NUM_STAGES = 8
 };
 int htgs_profile_enable(int on);
 int htgs_profile_read(double *ms_out, int64_t *launches_out, int32_t n_stages);

@@ -13,6 +13,7 @@ hipError_t launch_preprocess(const GaussPtrs &gp, const KCfg &cfg, const ViewSet
                              hipStream_t s);
 hipError_t launch_preprocess_bwd(const GaussPtrs &gp, const GradPtrs &gr, const KCfg &cfg,
                                  const ViewSet &vs, const Ws &w, hipStream_t s);
+hipError_t launch_segment_reduce(const Ws &w, hipStream_t s);
 hipError_t launch_sort_passes(const Ws &w, hipStream_t s);
 hipError_t launch_ranges(const Ws &w, hipStream_t s);
 hipError_t launch_raster_fwd(const Ws &w, const ViewSet &vs, const KCfg &cfg, float *state,
@@ -126,7 +127,7 @@ int check_cfg(const htgs_config *cfg) {
 
 int check_gaussians(const htgs_gaussians *g) {
   if (!g) return HTGS_E_INVAL;
-  if (g->n < 0 || g->n > (int64_t)0x7fffffff) return HTGS_E_INVAL;
+  if (g->n < 0 || g->n >= (int64_t)(1 << 27)) return HTGS_E_INVAL;  // segment ids hold 27 bits
   if (g->sh_degree < 0 || g->sh_degree > 3) return HTGS_E_INVAL;
   if (g->n > 0 && (!g->means || !g->log_scales || !g->quats || !g->opacity_logits || !g->sh))
     return HTGS_E_INVAL;
@@ -330,6 +331,10 @@ int backward_impl(const htgs_gaussians *g, const htgs_camera *cams, int32_t n_vi
   if (cap > 0) {
     StageTimer t(HTGS_STAGE_RASTER_BWD, s);
     HIP_TRY(launch_raster_bwd(w, vs, k, static_cast<const float *>(state), w.vals[w.final_buf], s));
+  }
+  if (cap > 0) {
+    StageTimer t(HTGS_STAGE_REDUCE, s);
+    HIP_TRY(launch_segment_reduce(w, s));
   }
   const GradPtrs gr{grads->means, grads->log_scales, grads->quats, grads->opacity_logits,
                     grads->sh};

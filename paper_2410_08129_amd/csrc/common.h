@@ -33,11 +33,15 @@ enum RecField {
   R_FLAGS = 31  // bit c set: colour channel c was clamped at 0
 };
 
-// Per-instance backward partials: sums over the tile's pixels of the
-// gradients w.r.t. d and m (plain, times the pixel's x offset and times its
-// y offset from the tile origin), of dL/do and of dL/drgb.
+// Per-instance backward partials: the gradient of the loss w.r.t. the
+// record coefficients D0, Du, Dv, M0, Mu, Mv of one (Gaussian, view) in
+// camera coordinates (d = D0 + u Du + v Dv, u = (x - cx)/fx), w.r.t. the
+// opacity and the colour, summed over one tile's pixels; then the segment
+// id (view << 27 | Gaussian). A segmented reduction later sums a segment's
+// slots in place.
 enum PartialField {
-  P_D0 = 0, P_DX = 3, P_DY = 6, P_M0 = 9, P_MX = 12, P_MY = 15, P_O = 18, P_C = 19
+  P_D0 = 0, P_DX = 3, P_DY = 6, P_M0 = 9, P_MX = 12, P_MY = 15, P_O = 18, P_C = 19,
+  P_SEG = 22
 };
 
 // Staged record in the raster kernels: tile-centred coefficients, the

@@ -13,10 +13,10 @@
 // instances with a load-balanced loop and adds the radix-sort digit
 // histograms of those keys.
 //
-// Backward, one lane per Gaussian: sums the per-instance partials written by
-// the raster backward, converts them from tile-local to camera coordinates
-// and applies the chain rule back to means, log-scales, quaternions, opacity
-// logits and SH coefficients.
+// Backward: a slot-parallel segmented reduction sums the per-instance
+// partials of each (Gaussian, view); then one lane per Gaussian applies the
+// chain rule back to means, log-scales, quaternions, opacity logits and SH
+// coefficients.
 #include <math.h>
 
 #include "common.h"
@@ -59,33 +59,6 @@ __device__ inline void sh_basis(T x, T y, T z, int deg, T *Y) {
     Y[13] = T(kY3c) * x * (T(5) * z * z - T(1));
     Y[14] = T(kY3e) * z * (x * x - y * y);
     Y[15] = T(kY3a) * x * (x * x - T(3) * y * y);
-  }
-}
-
-// Gradient of each basis polynomial w.r.t. (x, y, z); only the part
-// tangent to the sphere matters, and the caller projects it.
-__device__ inline void sh_basis_grad(double x, double y, double z, int deg, double (*dY)[3]) {
-  dY[0][0] = dY[0][1] = dY[0][2] = 0.0;
-  if (deg >= 1) {
-    dY[1][0] = 0; dY[1][1] = kY1; dY[1][2] = 0;
-    dY[2][0] = 0; dY[2][1] = 0; dY[2][2] = kY1;
-    dY[3][0] = kY1; dY[3][1] = 0; dY[3][2] = 0;
-  }
-  if (deg >= 2) {
-    dY[4][0] = kY2a * y; dY[4][1] = kY2a * x; dY[4][2] = 0;
-    dY[5][0] = 0; dY[5][1] = kY2a * z; dY[5][2] = kY2a * y;
-    dY[6][0] = 0; dY[6][1] = 0; dY[6][2] = kY2b * 6.0 * z;
-    dY[7][0] = kY2a * z; dY[7][1] = 0; dY[7][2] = kY2a * x;
-    dY[8][0] = kY2c * 2.0 * x; dY[8][1] = -kY2c * 2.0 * y; dY[8][2] = 0;
-  }
-  if (deg >= 3) {
-    dY[9][0] = kY3a * 6.0 * x * y; dY[9][1] = kY3a * 3.0 * (x * x - y * y); dY[9][2] = 0;
-    dY[10][0] = kY3b * y * z; dY[10][1] = kY3b * x * z; dY[10][2] = kY3b * x * y;
-    dY[11][0] = 0; dY[11][1] = kY3c * (5.0 * z * z - 1.0); dY[11][2] = kY3c * 10.0 * y * z;
-    dY[12][0] = 0; dY[12][1] = 0; dY[12][2] = kY3d * (15.0 * z * z - 3.0);
-    dY[13][0] = kY3c * (5.0 * z * z - 1.0); dY[13][1] = 0; dY[13][2] = kY3c * 10.0 * x * z;
-    dY[14][0] = kY3e * 2.0 * x * z; dY[14][1] = -kY3e * 2.0 * y * z; dY[14][2] = kY3e * (x * x - y * y);
-    dY[15][0] = kY3a * 3.0 * (x * x - y * y); dY[15][1] = -kY3a * 6.0 * x * y; dY[15][2] = 0;
   }
 }
 
@@ -390,67 +363,159 @@ __device__ inline void rot_grad_to_quat(const double qn[4], const double gR[3][3
                y * gR[1][2] + x * gR[2][0] + y * gR[2][1]);
 }
 
+// In-place segmented reduction of the per-instance partials. Slots are
+// processed in 64-aligned blocks, one lane each; a segment is the run of
+// slots of one (Gaussian, view). After the launch, the last slot of every
+// segment portion inside a block holds the sum of that portion. The scan
+// tree is fixed, so the result is deterministic.
+__global__ void __launch_bounds__(256) k_segment_reduce(Ws w) {
+  const unsigned long long tot = *w.total;
+  if (tot > (unsigned long long)w.capacity) return;
+  const uint64_t first = (uint64_t)blockIdx.x * blockDim.x;
+  if (first >= tot) return;
+  const uint64_t s = first + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const bool valid = s < tot;
+  float v[22];
+  uint32_t seg = 0xffffffffu;
+  float4 *slot = reinterpret_cast<float4 *>(w.partials + (int64_t)s * kPartialFloats);
+  if (valid) {
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      const float4 t = slot[k];
+      v[4 * k] = t.x; v[4 * k + 1] = t.y; v[4 * k + 2] = t.z; v[4 * k + 3] = t.w;
+    }
+    const float4 t = slot[5];
+    v[20] = t.x; v[21] = t.y;
+    seg = __float_as_uint(t.z);
+  } else {
+#pragma unroll
+    for (int k = 0; k < 22; ++k) v[k] = 0.f;
+  }
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t so = __shfl_up(seg, off, 64);
+    const bool take = (lane >= off) && (so == seg);
+#pragma unroll
+    for (int k = 0; k < 22; ++k) {
+      const float y = __shfl_up(v[k], off, 64);
+      if (take) v[k] += y;
+    }
+  }
+  const uint32_t sn = __shfl_down(seg, 1, 64);
+  const bool end = valid && (lane == 63 || sn != seg || s + 1 == tot);
+  if (end) {
+#pragma unroll
+    for (int k = 0; k < 5; ++k) slot[k] = make_float4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
+    slot[5] = make_float4(v[20], v[21], __uint_as_float(seg), 0.f);
+  }
+}
+
+// SH backward for one view, straight-line for a fixed degree: adds
+// Y_k(dir) * gc to gsh[k] and sum_k (sh_k . gc) grad Y_k(dir) to gdir.
+template <int DEG>
+__device__ __forceinline__ void sh_backward(const float *__restrict__ sh, const double dir[3],
+                                            const double gc[3], float *gsh, double gdir[3]) {
+  const double x = dir[0], y = dir[1], z = dir[2];
+#define HTGS_SH_TERM(k, Yv, gx, gy, gz)                                                     \
+  {                                                                                         \
+    const double Yk = (Yv);                                                                 \
+    gsh[3 * (k)] += (float)(Yk * gc[0]);                                                    \
+    gsh[3 * (k) + 1] += (float)(Yk * gc[1]);                                                \
+    gsh[3 * (k) + 2] += (float)(Yk * gc[2]);                                                \
+    const double ws = (double)sh[3 * (k)] * gc[0] + (double)sh[3 * (k) + 1] * gc[1] +       \
+                      (double)sh[3 * (k) + 2] * gc[2];                                      \
+    gdir[0] += ws * (gx);                                                                   \
+    gdir[1] += ws * (gy);                                                                   \
+    gdir[2] += ws * (gz);                                                                   \
+  }
+  HTGS_SH_TERM(0, kY00, 0.0, 0.0, 0.0)
+  if constexpr (DEG >= 1) {
+    HTGS_SH_TERM(1, kY1 * y, 0.0, kY1, 0.0)
+    HTGS_SH_TERM(2, kY1 * z, 0.0, 0.0, kY1)
+    HTGS_SH_TERM(3, kY1 * x, kY1, 0.0, 0.0)
+  }
+  if constexpr (DEG >= 2) {
+    HTGS_SH_TERM(4, kY2a * x * y, kY2a * y, kY2a * x, 0.0)
+    HTGS_SH_TERM(5, kY2a * y * z, 0.0, kY2a * z, kY2a * y)
+    HTGS_SH_TERM(6, kY2b * (3.0 * z * z - 1.0), 0.0, 0.0, kY2b * 6.0 * z)
+    HTGS_SH_TERM(7, kY2a * x * z, kY2a * z, 0.0, kY2a * x)
+    HTGS_SH_TERM(8, kY2c * (x * x - y * y), kY2c * 2.0 * x, -kY2c * 2.0 * y, 0.0)
+  }
+  if constexpr (DEG >= 3) {
+    HTGS_SH_TERM(9, kY3a * y * (3.0 * x * x - y * y), kY3a * 6.0 * x * y,
+                 kY3a * 3.0 * (x * x - y * y), 0.0)
+    HTGS_SH_TERM(10, kY3b * x * y * z, kY3b * y * z, kY3b * x * z, kY3b * x * y)
+    HTGS_SH_TERM(11, kY3c * y * (5.0 * z * z - 1.0), 0.0, kY3c * (5.0 * z * z - 1.0),
+                 kY3c * 10.0 * y * z)
+    HTGS_SH_TERM(12, kY3d * z * (5.0 * z * z - 3.0), 0.0, 0.0, kY3d * (15.0 * z * z - 3.0))
+    HTGS_SH_TERM(13, kY3c * x * (5.0 * z * z - 1.0), kY3c * (5.0 * z * z - 1.0), 0.0,
+                 kY3c * 10.0 * x * z)
+    HTGS_SH_TERM(14, kY3e * z * (x * x - y * y), kY3e * 2.0 * x * z, -kY3e * 2.0 * y * z,
+                 kY3e * (x * x - y * y))
+    HTGS_SH_TERM(15, kY3a * x * (x * x - 3.0 * y * y), kY3a * 3.0 * (x * x - y * y),
+                 -kY3a * 6.0 * x * y, 0.0)
+  }
+#undef HTGS_SH_TERM
+}
+
+__device__ __forceinline__ int rect_count(int4 r) {
+  return r.x <= r.z ? (r.z - r.x + 1) * (r.w - r.y + 1) : 0;
+}
+
+template <int DEG>
 __global__ void __launch_bounds__(256) k_preprocess_bwd(GaussPtrs gp, GradPtrs gr, KCfg cfg,
                                                          ViewSet vs, Ws w) {
+  constexpr int NB = (DEG + 1) * (DEG + 1);
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= cfg.n) return;
-  int4 rects[kMaxViews];
   uint32_t total = 0;
-  for (int v = 0; v < vs.n; ++v) {
-    rects[v] = w.rects[(int64_t)v * cfg.n + g];
-    if (rects[v].x <= rects[v].z)
-      total += (uint32_t)((rects[v].z - rects[v].x + 1) * (rects[v].w - rects[v].y + 1));
-  }
+  for (int v = 0; v < vs.n; ++v) total += (uint32_t)rect_count(w.rects[(int64_t)v * cfg.n + g]);
   if (total == 0) return;
   const unsigned long long I = *w.total;
   const uint32_t first = w.offsets[g];
-  if ((unsigned long long)first + total > (unsigned long long)w.capacity ||
-      (unsigned long long)first + total > I)
+  if (I > (unsigned long long)w.capacity || (unsigned long long)first + total > I)
     return;  // overflowed forward: status already reports it
 
   Activated a;
   activate(gp, g, a);
-  const int nb = (cfg.sh_degree + 1) * (cfg.sh_degree + 1);
   double gA[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
   double gmu[3] = {0, 0, 0};
   double go = 0.0;
-  double gsh[16][3];
-  for (int k = 0; k < 16; ++k) gsh[k][0] = gsh[k][1] = gsh[k][2] = 0.0;
-
-  uint32_t slot = first;
-  for (int v = 0; v < vs.n; ++v) {
-    const int4 r = rects[v];
-    if (r.x > r.z) continue;
-    const ViewParams &V = vs.v[v];
-    const double fx = V.fx, fy = V.fy, cx = V.cx, cy = V.cy;
-    double gD0[3] = {0, 0, 0}, gDu[3] = {0, 0, 0}, gDv[3] = {0, 0, 0};
-    double gM0[3] = {0, 0, 0}, gMu[3] = {0, 0, 0}, gMv[3] = {0, 0, 0};
-    double gc[3] = {0, 0, 0};
-    for (int ty = r.y; ty <= r.w; ++ty) {
-      const double vt = ((double)ty * cfg.tile_h + 0.5 - cy) / fy;
-      for (int tx = r.x; tx <= r.z; ++tx, ++slot) {
-        const double ut = ((double)tx * cfg.tile_w + 0.5 - cx) / fx;
-        const float4 *P = reinterpret_cast<const float4 *>(w.partials + (int64_t)slot * kPartialFloats);
-        float pf[kPartialFloats];
+  float gsh[3 * NB];
 #pragma unroll
-        for (int k = 0; k < kPartialFloats / 4; ++k) {
-          const float4 t = P[k];
-          pf[4 * k] = t.x; pf[4 * k + 1] = t.y; pf[4 * k + 2] = t.z; pf[4 * k + 3] = t.w;
-        }
-        for (int k = 0; k < 3; ++k) {
-          const double s0 = pf[P_D0 + k], sx = pf[P_DX + k], sy = pf[P_DY + k];
-          gD0[k] += s0;
-          gDu[k] += ut * s0 + sx / fx;
-          gDv[k] += vt * s0 + sy / fy;
-          const double t0 = pf[P_M0 + k], tx_ = pf[P_MX + k], ty_ = pf[P_MY + k];
-          gM0[k] += t0;
-          gMu[k] += ut * t0 + tx_ / fx;
-          gMv[k] += vt * t0 + ty_ / fy;
-          gc[k] += pf[P_C + k];
-        }
-        go += pf[P_O];
+  for (int k = 0; k < 3 * NB; ++k) gsh[k] = 0.f;
+  const float *sh = gp.sh + g * NB * 3;
+
+  uint32_t sa = first;
+  for (int v = 0; v < vs.n; ++v) {
+    const uint32_t cnt = (uint32_t)rect_count(w.rects[(int64_t)v * cfg.n + g]);
+    if (cnt == 0) continue;
+    const uint32_t sb = sa + cnt;
+    // Sum of the segment: the block-portion sums left by the segmented reduction.
+    float acc[22];
+#pragma unroll
+    for (int k = 0; k < 22; ++k) acc[k] = 0.f;
+    for (uint32_t blk = sa >> 6; blk <= (sb - 1) >> 6; ++blk) {
+      const uint32_t e = min(sb - 1, blk * 64u + 63u);
+      const float4 *P = reinterpret_cast<const float4 *>(w.partials + (int64_t)e * kPartialFloats);
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        const float4 t = P[k];
+        acc[4 * k] += t.x; acc[4 * k + 1] += t.y; acc[4 * k + 2] += t.z; acc[4 * k + 3] += t.w;
       }
+      const float4 t = P[5];
+      acc[20] += t.x; acc[21] += t.y;
     }
+    sa = sb;
+    const ViewParams &V = vs.v[v];
+    double gD0[3], gDu[3], gDv[3], gM0[3], gMu[3], gMv[3], gc[3];
+    for (int k = 0; k < 3; ++k) {
+      gD0[k] = acc[P_D0 + k]; gDu[k] = acc[P_DX + k]; gDv[k] = acc[P_DY + k];
+      gM0[k] = acc[P_M0 + k]; gMu[k] = acc[P_MX + k]; gMv[k] = acc[P_MY + k];
+      gc[k] = acc[P_C + k];
+    }
+    go += acc[P_O];
     // Pluecker coefficients -> view rows of M T.
     double Rv[3][3], mv[3];
     view_rows(V, a, Rv, mv);
@@ -479,13 +544,13 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(GaussPtrs gp, GradPtrs g
     // Rv = W3 A (A = R diag(s)), mv = W3 mu + t
     for (int i = 0; i < 3; ++i) {
       for (int j = 0; j < 3; ++j) {
-        double acc = 0.0;
-        for (int k = 0; k < 3; ++k) acc += (double)V.w2c[4 * k + i] * gR[k][j];
-        gA[i][j] += acc;
+        double s_ = 0.0;
+        for (int k = 0; k < 3; ++k) s_ += (double)V.w2c[4 * k + i] * gR[k][j];
+        gA[i][j] += s_;
       }
-      double accm = 0.0;
-      for (int k = 0; k < 3; ++k) accm += (double)V.w2c[4 * k + i] * gm[k];
-      gmu[i] += accm;
+      double sm = 0.0;
+      for (int k = 0; k < 3; ++k) sm += (double)V.w2c[4 * k + i] * gm[k];
+      gmu[i] += sm;
     }
     // Colour: SH coefficients and the viewing direction.
     const uint32_t flags =
@@ -495,19 +560,8 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(GaussPtrs gp, GradPtrs g
     double dv[3] = {a.mu[0] - V.cam_pos[0], a.mu[1] - V.cam_pos[1], a.mu[2] - V.cam_pos[2]};
     const double dn = sqrt(dot3(dv, dv));
     const double dir[3] = {dv[0] / dn, dv[1] / dn, dv[2] / dn};
-    double Y[16], dY[16][3];
-    sh_basis<double>(dir[0], dir[1], dir[2], cfg.sh_degree, Y);
-    sh_basis_grad(dir[0], dir[1], dir[2], cfg.sh_degree, dY);
-    const float *sh = gp.sh + g * nb * 3;
     double gdir[3] = {0, 0, 0};
-    for (int k = 0; k < nb; ++k) {
-      double wsum = 0.0;
-      for (int c = 0; c < 3; ++c) {
-        gsh[k][c] += Y[k] * gc[c];
-        wsum += (double)sh[3 * k + c] * gc[c];
-      }
-      for (int j = 0; j < 3; ++j) gdir[j] += wsum * dY[k][j];
-    }
+    sh_backward<DEG>(sh, dir, gc, gsh, gdir);
     const double radial = dot3(gdir, dir);
     for (int j = 0; j < 3; ++j) gmu[j] += (gdir[j] - dir[j] * radial) / dn;
   }
@@ -531,9 +585,11 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(GaussPtrs gp, GradPtrs g
   if (gr.quats)
     for (int k = 0; k < 4; ++k) gr.quats[4 * g + k] += (float)((gqn[k] - qn[k] * proj) / a.qnorm);
   if (gr.logits) gr.logits[g] += (float)(go * a.o * (1.0 - a.o));
-  if (gr.sh)
-    for (int k = 0; k < nb; ++k)
-      for (int c = 0; c < 3; ++c) gr.sh[(g * nb + k) * 3 + c] += (float)gsh[k][c];
+  if (gr.sh) {
+    float *dst = gr.sh + g * NB * 3;
+#pragma unroll
+    for (int k = 0; k < 3 * NB; ++k) dst[k] += gsh[k];
+  }
 }
 
 hipError_t launch_fill_zero(void *p, int64_t bytes, hipStream_t s) {
@@ -553,11 +609,23 @@ hipError_t launch_preprocess(const GaussPtrs &gp, const KCfg &cfg, const ViewSet
   return hipGetLastError();
 }
 
+hipError_t launch_segment_reduce(const Ws &w, hipStream_t s) {
+  if (w.capacity == 0) return hipSuccess;
+  const int64_t blocks = (w.capacity + 255) / 256;
+  hipLaunchKernelGGL(k_segment_reduce, dim3((unsigned)blocks), dim3(256), 0, s, w);
+  return hipGetLastError();
+}
+
 hipError_t launch_preprocess_bwd(const GaussPtrs &gp, const GradPtrs &gr, const KCfg &cfg,
                                  const ViewSet &vs, const Ws &w, hipStream_t s) {
   if (cfg.n == 0) return hipSuccess;
   const int blocks = (int)((cfg.n + 255) / 256);
-  hipLaunchKernelGGL(k_preprocess_bwd, dim3(blocks), dim3(256), 0, s, gp, gr, cfg, vs, w);
+  switch (cfg.sh_degree) {
+    case 0: hipLaunchKernelGGL(k_preprocess_bwd<0>, dim3(blocks), dim3(256), 0, s, gp, gr, cfg, vs, w); break;
+    case 1: hipLaunchKernelGGL(k_preprocess_bwd<1>, dim3(blocks), dim3(256), 0, s, gp, gr, cfg, vs, w); break;
+    case 2: hipLaunchKernelGGL(k_preprocess_bwd<2>, dim3(blocks), dim3(256), 0, s, gp, gr, cfg, vs, w); break;
+    default: hipLaunchKernelGGL(k_preprocess_bwd<3>, dim3(blocks), dim3(256), 0, s, gp, gr, cfg, vs, w); break;
+  }
   return hipGetLastError();
 }
 

@@ -335,6 +335,56 @@ struct PixLayout {
   static constexpr int kStride = ((8 + 3 * KMAX) + 3) / 4 * 4;
 };
 
+// Gradient contribution of one fragment (lane's splat at pixel Pp) to the
+// lane's moment accumulators.
+template <int KMAX>
+__device__ __forceinline__ void bwd_fragment(const float *st, const float *Pp, const float *tab,
+                                             const float d[3], const float m[3], float dd,
+                                             float mm, int ncore, const uint16_t *ent, int lane,
+                                             float amax, float *acc) {
+  using L = PixLayout<KMAX>;
+  int cslot = -1;
+  for (int e = 0; e < ncore; ++e) {
+    const uint32_t en = ent[e];
+    if ((int)(en & 255u) == lane) cslot = (int)(en >> 8);
+  }
+  const float inv = rcp_fast(dd);
+  const float r2 = mm * inv;
+  const float e = exp2_fast(r2 * kNegHalfLog2e);
+  const float araw = st[S_O] * e;
+  const float alpha = fminf(amax, araw);
+  const float G0 = Pp[0], G1 = Pp[1], G2 = Pp[2], w1 = Pp[3];
+  float dLda, wc;
+  if (cslot >= 0) {
+    dLda = Pp[L::kCoef + cslot];
+    wc = alpha * Pp[L::kT + cslot];
+  } else {
+    const float gdc = fmaf(G2, st[S_RGB + 2], fmaf(G1, st[S_RGB + 1], G0 * st[S_RGB]));
+    dLda = fmaf(w1, gdc, -Pp[4]) - Pp[5] * rcp_fast(1.f - alpha);
+    wc = w1 * alpha;
+  }
+  acc[13] = fmaf(wc, G0, acc[13]);
+  acc[14] = fmaf(wc, G1, acc[14]);
+  acc[15] = fmaf(wc, G2, acc[15]);
+  if (araw <= amax) {
+    acc[12] = fmaf(dLda, e, acc[12]);
+    const float s1 = -alpha * dLda * inv;   // weight of m: 2 dL/drho^2 / |d|^2
+    const float s2 = -s1 * r2;              // weight of d
+    acc[0] += s2;
+    acc[1] = fmaf(tab[0], s2, acc[1]);
+    acc[2] = fmaf(tab[1], s2, acc[2]);
+    acc[3] = fmaf(tab[2], s2, acc[3]);
+    acc[4] = fmaf(tab[3], s2, acc[4]);
+    acc[5] = fmaf(tab[4], s2, acc[5]);
+    acc[6] += s1;
+    acc[7] = fmaf(tab[0], s1, acc[7]);
+    acc[8] = fmaf(tab[1], s1, acc[8]);
+    acc[9] = fmaf(tab[2], s1, acc[9]);
+    acc[10] = fmaf(tab[3], s1, acc[10]);
+    acc[11] = fmaf(tab[4], s1, acc[11]);
+  }
+}
+
 template <int KMAX, int TW, int TH>
 __global__ void __launch_bounds__(256) k_raster_bwd(Ws w, ViewSet vs, KCfg cfg,
                                                     const float *__restrict__ state,
@@ -436,8 +486,7 @@ __global__ void __launch_bounds__(256) k_raster_bwd(Ws w, ViewSet vs, KCfg cfg,
   const int wave = tid >> 6, lane = tid & 63;
   const uint32_t count = rg.y - rg.x;
   const uint32_t nch = (count + 63u) >> 6;
-  const float tau_core = cfg.tau_core, amax = cfg.alpha_max;
-  (void)tau_core;
+  const float amax = cfg.alpha_max;
   for (uint32_t c = wave; c < nch; c += 4) {
     const uint32_t j = rg.x + c * 64u + lane;
     const bool active = j < rg.y;
@@ -491,76 +540,51 @@ __global__ void __launch_bounds__(256) k_raster_bwd(Ws w, ViewSet vs, KCfg cfg,
       const int bx = (blk % BX) * 8, by = (blk / BX) * 8;
       const bool hitb = active && rect_meets_block(st + S_BB0, bx, by);
       if (__ballot(hitb) == 0ull) continue;
-      for (int q = 0; q < 64; ++q) {
-        const int p = (by + (q >> 3)) * TW + bx + (q & 7);
-        const float *tab = pix_entry<TW>(p);
-        const float flx = tab[0], fly = tab[1];
-        float d[3], m[3], dd, mm;
-        eval_ray(st, flx, fly, d, m, dd, mm);
-        const bool frag = hitb && is_fragment(dd, mm, st[S_RC]);
-        const int ncore = s_cnt[wave][p];
-        int cslot = -1;
-        for (int e = 0; e < ncore; ++e) {
-          const uint32_t ent = s_ent[wave][p][e];
-          if ((int)(ent & 255u) == lane) cslot = (int)(ent >> 8);
-        }
-        if (!frag) continue;
-        const float *Pp = sp_all + p * L::kStride;
-        const float inv = rcp_fast(dd);
-        const float r2 = mm * inv;
-        const float e = exp2_fast(r2 * kNegHalfLog2e);
-        const float araw = st[S_O] * e;
-        const float alpha = fminf(amax, araw);
-        const float G0 = Pp[0], G1 = Pp[1], G2 = Pp[2], w1 = Pp[3];
-        float dLda, wc;
-        if (cslot >= 0) {
-          dLda = Pp[L::kCoef + cslot];
-          wc = alpha * Pp[L::kT + cslot];
-        } else {
-          const float gdc = fmaf(G2, st[S_RGB + 2], fmaf(G1, st[S_RGB + 1], G0 * st[S_RGB]));
-          dLda = fmaf(w1, gdc, -Pp[4]) - Pp[5] * rcp_fast(1.f - alpha);
-          wc = w1 * alpha;
-        }
-        acc[13] = fmaf(wc, G0, acc[13]);
-        acc[14] = fmaf(wc, G1, acc[14]);
-        acc[15] = fmaf(wc, G2, acc[15]);
-        if (araw <= amax) {
-          acc[12] = fmaf(dLda, e, acc[12]);
-          const float s1 = -alpha * dLda * inv;   // weight of m: 2 dL/drho^2 / |d|^2
-          const float s2 = -s1 * r2;              // weight of d
-          acc[0] += s2;
-          acc[1] = fmaf(flx, s2, acc[1]);
-          acc[2] = fmaf(fly, s2, acc[2]);
-          acc[3] = fmaf(tab[2], s2, acc[3]);
-          acc[4] = fmaf(tab[3], s2, acc[4]);
-          acc[5] = fmaf(tab[4], s2, acc[5]);
-          acc[6] += s1;
-          acc[7] = fmaf(flx, s1, acc[7]);
-          acc[8] = fmaf(fly, s1, acc[8]);
-          acc[9] = fmaf(tab[2], s1, acc[9]);
-          acc[10] = fmaf(tab[3], s1, acc[10]);
-          acc[11] = fmaf(tab[4], s1, acc[11]);
-        }
+      // Two pixels per iteration: the pair tests are independent.
+      for (int q = 0; q < 64; q += 2) {
+        const int p0 = (by + (q >> 3)) * TW + bx + (q & 7);
+        const int p1 = p0 + 1;
+        const float *tab0 = pix_entry<TW>(p0);
+        const float *tab1 = pix_entry<TW>(p1);
+        float d0[3], m0[3], dd0, mm0, d1[3], m1[3], dd1, mm1;
+        eval_ray(st, tab0[0], tab0[1], d0, m0, dd0, mm0);
+        eval_ray(st, tab1[0], tab1[1], d1, m1, dd1, mm1);
+        const bool f0 = hitb && is_fragment(dd0, mm0, st[S_RC]);
+        const bool f1 = hitb && is_fragment(dd1, mm1, st[S_RC]);
+        if (f0) bwd_fragment<KMAX>(st, sp_all + p0 * L::kStride, tab0, d0, m0, dd0, mm0,
+                                   s_cnt[wave][p0], s_ent[wave][p0], lane, amax, acc);
+        if (f1) bwd_fragment<KMAX>(st, sp_all + p1 * L::kStride, tab1, d1, m1, dd1, mm1,
+                                   s_cnt[wave][p1], s_ent[wave][p1], lane, amax, acc);
       }
     }
     if (active && (uint64_t)slot < (uint64_t)w.capacity) {
+      // Gradients of the record coefficients in camera coordinates
+      // u = (x - cx)/fx, v = (y - cy)/fy: d = D0 + u Du + v Dv with u = ut + lx/fx.
+      const float ut = ((float)px0 + 0.5f - V.cx) / V.fx, vt = ((float)py0 + 0.5f - V.cy) / V.fy;
+      const float ifx = 1.f / V.fx, ify = 1.f / V.fy;
       float out[kPartialFloats];
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         const float D0 = st[S_D0 + k], Du = st[S_DU + k], Dv = st[S_DV + k];
         const float M0 = st[S_M0 + k], Mu = st[S_MU + k], Mv = st[S_MV + k];
-        out[P_D0 + k] = fmaf(Dv, acc[2], fmaf(Du, acc[1], D0 * acc[0]));
-        out[P_DX + k] = fmaf(Dv, acc[4], fmaf(Du, acc[3], D0 * acc[1]));
-        out[P_DY + k] = fmaf(Dv, acc[5], fmaf(Du, acc[4], D0 * acc[2]));
-        out[P_M0 + k] = fmaf(Mv, acc[8], fmaf(Mu, acc[7], M0 * acc[6]));
-        out[P_MX + k] = fmaf(Mv, acc[10], fmaf(Mu, acc[9], M0 * acc[7]));
-        out[P_MY + k] = fmaf(Mv, acc[11], fmaf(Mu, acc[10], M0 * acc[8]));
+        const float sd = fmaf(Dv, acc[2], fmaf(Du, acc[1], D0 * acc[0]));
+        const float sdx = fmaf(Dv, acc[4], fmaf(Du, acc[3], D0 * acc[1]));
+        const float sdy = fmaf(Dv, acc[5], fmaf(Du, acc[4], D0 * acc[2]));
+        const float sm = fmaf(Mv, acc[8], fmaf(Mu, acc[7], M0 * acc[6]));
+        const float smx = fmaf(Mv, acc[10], fmaf(Mu, acc[9], M0 * acc[7]));
+        const float smy = fmaf(Mv, acc[11], fmaf(Mu, acc[10], M0 * acc[8]));
+        out[P_D0 + k] = sd;
+        out[P_DX + k] = fmaf(ut, sd, sdx * ifx);
+        out[P_DY + k] = fmaf(vt, sd, sdy * ify);
+        out[P_M0 + k] = sm;
+        out[P_MX + k] = fmaf(ut, sm, smx * ifx);
+        out[P_MY + k] = fmaf(vt, sm, smy * ify);
       }
       out[P_O] = acc[12];
       out[P_C] = acc[13];
       out[P_C + 1] = acc[14];
       out[P_C + 2] = acc[15];
-      out[22] = 0.f;
+      out[P_SEG] = __uint_as_float(((uint32_t)ti.v << 27) | vals[j]);
       out[23] = 0.f;
       float4 *dst = reinterpret_cast<float4 *>(w.partials + (int64_t)slot * kPartialFloats);
 #pragma unroll

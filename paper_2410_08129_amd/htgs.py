@@ -26,7 +26,8 @@ EXPORTED = (
     "htgs_render_backward_batched", "htgs_read_status", "htgs_debug_export_bins",
     "htgs_strerror", "htgs_version", "htgs_profile_enable", "htgs_profile_read",
 )
-STAGES = ("fill", "preprocess", "sort", "ranges", "raster_fwd", "raster_bwd", "preprocess_bwd")
+STAGES = ("fill", "preprocess", "sort", "ranges", "raster_fwd", "raster_bwd", "reduce",
+          "preprocess_bwd")
 
 
 class HTGSError(RuntimeError):

@@ -212,17 +212,17 @@ def workload_small(seed=0):
 
 def workload_1080p(seed=0, n=1_000_000):
     """1M clustered Gaussians (64 clusters), SH degree 3, 1920x1080,
-    fov 50 deg, camera at (0,0,-25) looking at the origin, K = 8."""
+    fov 50 deg, camera at (0,0,-25) looking at the origin, K = 8, 8x8 tiles."""
     scene = clustered_scene(n, 64, seed)
     cam = look_at((0, 0, -25), (0, 0, 0), (0, -1, 0), 50.0, 1920, 1080)
-    return scene, [cam], RenderSettings(K=8)
+    return scene, [cam], RenderSettings(K=8, tile_w=8, tile_h=8)
 
 
 def workload_720p(seed=0, n=1_000_000):
     """The 1080p scene seen by a 1280x720 camera (forward + backward)."""
     scene = clustered_scene(n, 64, seed)
     cam = look_at((0, 0, -25), (0, 0, 0), (0, -1, 0), 50.0, 1280, 720)
-    return scene, [cam], RenderSettings(K=8)
+    return scene, [cam], RenderSettings(K=8, tile_w=8, tile_h=8)
 
 
 _RESOLUTIONS = ((640, 480), (1280, 720), (1600, 900), (1920, 1080))
@@ -242,7 +242,7 @@ def workload_multiview(seed=0, n=3_000_000, n_views=16):
         if abs(np.dot(up, -e / np.linalg.norm(e))) > 0.99:
             up = np.array([0.0, 0.0, 1.0])
         cams.append(look_at(e, (0, 0, 0), up, 50.0, w, h))
-    return scene, cams, RenderSettings(K=8)
+    return scene, cams, RenderSettings(K=8, tile_w=8, tile_h=8)
 
 
 def workload_stress(seed=0, n=6_000_000):
@@ -250,7 +250,7 @@ def workload_stress(seed=0, n=6_000_000):
     near-degenerate splats, SH degree 3, 3840x2160, fov 70 deg, K = 16."""
     scene = clustered_scene(n, 64, seed, 3, 0.10, 0.02)
     cam = look_at((0, 0, -25), (0, 0, 0), (0, -1, 0), 70.0, 3840, 2160)
-    return scene, [cam], RenderSettings(K=16)
+    return scene, [cam], RenderSettings(K=16, tile_w=8, tile_h=8)
 
 
 def random_crops(cam: Camera, n, size, seed=0):

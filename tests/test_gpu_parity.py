@@ -88,7 +88,8 @@ def scene_1080p():
 
 
 def test_1080p_tile_lists_bit_exact(scene_1080p):
-    sc, cams, st = scene_1080p
+    sc, cams, st0 = scene_1080p
+    st = scenes.RenderSettings(K=8, tile_w=16, tile_h=16)
     log("1080p bins 16x16")
     params, frame = gpu_forward(sc, cams, st, with_state=False)
     keys, vals, rects, _ = htgs.export_bins(params, sc.sh_degree, cams, st, frame.ws)
@@ -169,10 +170,11 @@ def _gpu_grads(sub, cam, st, G):
 NAMES = ("means", "log_scales", "quats", "opacity_logits", "sh")
 
 
-@pytest.mark.parametrize("seed", [7, 11])
-def test_gradients_match_oracle_on_subcrop(seed):
+@pytest.mark.parametrize("seed,tile", [(7, 8), (11, 16), (13, 8)])
+def test_gradients_match_oracle_on_subcrop(seed, tile):
     sub, cam, st, target = _subcrop(seed)
-    log(f"gradients: 256 Gaussians, 32x32, seed {seed}")
+    st.tile_w = st.tile_h = tile
+    log(f"gradients: 256 Gaussians, 32x32, seed {seed}, tile {tile}")
     ref_img = oracle.render.render_scene(sub, cam, st, cull=False).numpy()
     G = np.sign(ref_img - target) / (3 * cam.width * cam.height)
     ref_img, ref = _oracle_grads(sub, cam, st, G)
