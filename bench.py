@@ -55,24 +55,28 @@ def workload(name):
     return sc, cams, st, desc
 
 
-def cpu_baseline(sc, cam, st, n_crops=4, size=64):
+def cpu_baseline(sc, cam, st, min_seconds=10.0, max_crops=64, size=64):
     """The FP64 oracle on a bounded sample: forward + autograd backward of
-    seeded 64x64 crops; extrapolated to the full frame by pixel count."""
-    import numpy as np
+    seeded 64x64 crops (as many as fit in about min_seconds, at least 2);
+    extrapolated to the full frame by pixel count."""
     import torch
 
     import oracle
     from paper_2410_08129_amd import scenes
     torch.set_num_threads(os.cpu_count() or 1)
-    crops = scenes.random_crops(cam, n_crops, size, seed=5)
+    crops = scenes.random_crops(cam, max_crops, size, seed=5)
     target = scenes.smooth_target(cam.height, cam.width)
     t0 = time.perf_counter()
+    n_crops = 0
     for (x0, y0, c) in crops:
         ps = [torch.tensor(a, dtype=torch.float64, requires_grad=True) for a in sc.arrays()]
         img = oracle.render.render(*ps, sc.sh_degree, c, st)
         tgt = torch.tensor(target[:, y0:y0 + size, x0:x0 + size], dtype=torch.float64)
         loss = (img - tgt).abs().mean()
         loss.backward()
+        n_crops += 1
+        if n_crops >= 2 and time.perf_counter() - t0 >= min_seconds:
+            break
     dt = time.perf_counter() - t0
     per_px = dt / (n_crops * size * size)
     frame_ms = per_px * cam.width * cam.height * 1e3
