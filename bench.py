@@ -1,12 +1,18 @@
 #!/usr/bin/env python3
-"""Benchmark of the hot path: one step = forward render + L1 loss gradient +
-backward, through the C ABI, on one MI355X.
+"""Benchmark of the hot path on one MI355X, through the C ABI.
 
+A step is one forward render + the L1-loss image gradient + the backward.
 Default workload: 1M clustered Gaussians (SH degree 3), one 1920x1080
-camera, K = 8, 16x16 tiles, L1 loss against a seeded smooth target. Inputs
-are resident in HBM before timing. Prints ONE JSON line.
+camera, K = 8; tile shape, forward LDS batch depth and tile order picked by
+the autotuner. Inputs are resident in HBM before timing. Prints ONE JSON
+line on stdout; progress goes to stderr.
 
-    python bench.py [--steps K] [--warmup W] [--workload 1080p|720p|small|stress]
+    python bench.py [--steps K] [--warmup W] [--workload 1080p|720p|small|stress|multiview]
+
+The default run also measures the batched multi-view step (3M Gaussians,
+16 views of uneven resolution): 16 sequential single-view fwd+bwd calls of
+the same kernels versus one replay of a hipGraph holding the batched
+fwd+bwd; reported under "multiview" (skip with --no-multiview).
 """
 from __future__ import annotations
 
@@ -24,9 +30,10 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 
-# Algorithmic float32 flops of the rasterizer (FMA = 2):
-# a candidate pair (tile pixel x tile instance) evaluates d, m, |d|^2, |m|^2
-# and the cutoff test; a fragment adds alpha and its core/tail work.
+# Algorithmic float32 flops of the rasterizer (FMA = 2): a candidate pair
+# (tile pixel x tile instance) evaluates d, m, |d|^2, |m|^2 and the cutoff
+# test; a fragment adds alpha and its tail (forward) or its adjoint
+# (backward) work. Core insertion is not counted.
 FLOPS_PAIR = 35
 FLOPS_FRAG_FWD = 15
 FLOPS_FRAG_BWD = 64
@@ -40,16 +47,21 @@ def workload(name):
     from paper_2410_08129_amd import scenes
     if name == "1080p":
         sc, cams, st = scenes.workload_1080p()
-        desc = "1M clustered Gaussians, SH3, 1920x1080, fov 50, K=8, 8x8 tiles, fwd+bwd (L1 to smooth target)"
+        desc = "1M clustered Gaussians, SH3, 1920x1080, fov 50, K=8, fwd+bwd (L1 to smooth target)"
     elif name == "720p":
         sc, cams, st = scenes.workload_720p()
-        desc = "1M clustered Gaussians, SH3, 1280x720, fov 50, K=8, 8x8 tiles, fwd+bwd (L1 to smooth target)"
+        desc = "1M clustered Gaussians, SH3, 1280x720, fov 50, K=8, fwd+bwd (L1 to smooth target)"
     elif name == "small":
         sc, cams, st = scenes.workload_small()
-        desc = "4096 uniform Gaussians, SH0, 128x128, fov 60, K=4, 16x16 tiles, fwd+bwd"
+        desc = "4096 uniform Gaussians, SH0, 128x128, fov 60, K=4, fwd+bwd"
     elif name == "stress":
         sc, cams, st = scenes.workload_stress()
-        desc = "6M clustered Gaussians (10% zero-axis, 2% 1e-7-axis), SH3, 3840x2160, fov 70, K=16, 8x8 tiles, fwd+bwd"
+        desc = ("6M clustered Gaussians (10% zero-axis, 2% 1e-7-axis), SH3, 3840x2160, fov 70, "
+                "K=16, fwd+bwd")
+    elif name == "multiview":
+        sc, cams, st = scenes.workload_multiview()
+        desc = ("3M clustered Gaussians (128 clusters), SH3, 16 views of uneven resolution, "
+                "fov 50, K=8, fwd+bwd")
     else:
         raise SystemExit(f"unknown workload {name}")
     return sc, cams, st, desc
@@ -86,23 +98,22 @@ def cpu_baseline(sc, cam, st, min_seconds=10.0, max_crops=64, size=64):
                        f"total, extrapolated by pixel count to {cam.width}x{cam.height}")
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="1080p")
-    ap.add_argument("--tile", type=int, default=0, help="override tile size (8 or 16)")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forward-only", action="store_true")
-    ap.add_argument("--calibrate-copy", action="store_true",
-                    help="also run a plain 256 MiB device copy (reference for HBM counters)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the renderer runs on a single MI355X).", file=sys.stderr)
-        sys.exit(2)
+def settings_desc(st):
+    return {"tile": [st.tile_w, st.tile_h], "lds_batch": st.lds_batch or st.tile_w * st.tile_h,
+            "cost_order": bool(st.cost_order)}
 
+
+def tune(params, sc, cams, st, args):
+    from paper_2410_08129_amd import autotune
+    if args.tile:
+        st.tile_w = st.tile_h = args.tile
+        return st, {"mode": "fixed"}
+    st2, rep = autotune.tune(params, sc.sh_degree, cams, st)
+    log(f"bench: autotune -> {settings_desc(st2)}")
+    return st2, rep
+
+
+def run_single(args):
     import numpy as np
     import torch
 
@@ -110,13 +121,10 @@ def main():
 
     log(f"bench: workload {args.workload}, generating scene")
     sc, cams, st, desc = workload(args.workload)
-    if args.tile:
-        st.tile_w = st.tile_h = args.tile
-        for t in ("8x8 tiles", "16x16 tiles"):
-            desc = desc.replace(t, f"{args.tile}x{args.tile} tiles")
     cam = cams[0]
     dev = torch.device("cuda:0")
     params = [torch.tensor(a, device=dev) for a in sc.arrays()]
+    st, tune_rep = tune(params, sc, [cam], st, args)
     target = torch.tensor(scenes.smooth_target(cam.height, cam.width), device=dev)
     n_inst = htgs.count_instances(params, sc.sh_degree, [cam], st)
     ws = htgs.alloc_workspace(sc.n, [cam], st, n_inst, dev)
@@ -140,7 +148,7 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    flags, n_inst2, n_frag = htgs.read_status(ws, fragments=True)
+    flags, _, n_frag = htgs.read_status(ws, fragments=True)
     if flags:
         raise SystemExit(f"status flags {flags} after warm-up")
     log(f"bench: warm-up done, {n_frag} fragments")
@@ -158,38 +166,33 @@ def main():
     ms_step = (t1 - t0) * 1e3 / args.steps
     log(f"bench: {args.steps} steps, {ms_step:.3f} ms/step")
 
-    # Algorithmic work of the rasterizer.
-    keys, vals, _, _ = htgs.export_bins(params, sc.sh_degree, [cam], st, ws)
+    # Algorithmic work of the rasterizer: candidate pairs from the tile lists.
+    keys, _, _, _ = htgs.export_bins(params, sc.sh_degree, [cam], st, ws)
     tiles_x = (cam.width + st.tile_w - 1) // st.tile_w
     tiles_y = (cam.height + st.tile_h - 1) // st.tile_h
-    tx = np.arange(tiles_x)
-    ty = np.arange(tiles_y)
-    pw = np.minimum(st.tile_w, cam.width - tx * st.tile_w)
-    ph = np.minimum(st.tile_h, cam.height - ty * st.tile_h)
+    pw = np.minimum(st.tile_w, cam.width - np.arange(tiles_x) * st.tile_w)
+    ph = np.minimum(st.tile_h, cam.height - np.arange(tiles_y) * st.tile_h)
     tile_px = (ph[:, None] * pw[None, :]).reshape(-1)
     per_tile = np.bincount(keys.astype(np.int64), minlength=tiles_x * tiles_y)
     pairs = int((per_tile * tile_px).sum())
 
-    stages = {k: dict(ms_per_launch=(v[0] / max(v[1], 1)), launches_per_step=v[1] / args.steps,
-                      ms_per_step=v[0] / args.steps) for k, v in prof.items() if v[1]}
-    work = {
-        "raster_fwd": (FLOPS_PAIR * pairs + FLOPS_FRAG_FWD * n_frag) / 1e12,
-        "raster_bwd": (FLOPS_PAIR * pairs + FLOPS_FRAG_BWD * n_frag) / 1e12,
-    }
-    dom = max(("raster_fwd", "raster_bwd") if not args.forward_only else ("raster_fwd",),
-              key=lambda k: stages.get(k, {}).get("ms_per_step", 0.0))
+    stages = {k: dict(ms_per_launch=(v[0] / max(v[1], 1)), ms_per_step=v[0] / args.steps)
+              for k, v in prof.items() if v[1]}
+    work = {"raster_fwd": (FLOPS_PAIR * pairs + FLOPS_FRAG_FWD * n_frag) / 1e12,
+            "raster_bwd": (FLOPS_PAIR * pairs + FLOPS_FRAG_BWD * n_frag) / 1e12}
+    cands = ("raster_fwd",) if args.forward_only else ("raster_fwd", "raster_bwd")
+    dom = max(cands, key=lambda k: stages.get(k, {}).get("ms_per_step", 0.0))
     ach = work[dom] / (stages[dom]["ms_per_launch"] * 1e-3)
-    roofline = dict(kernel=dom, bound="alu", achieved=round(ach, 3), peak=round(FP32_PEAK_TFLOPS, 1),
-                    unit="TFLOP/s", frac=round(ach / FP32_PEAK_TFLOPS, 4), traffic=None)
-    # Binning: each radix pass reads and writes key + value once.
+    roofline = dict(kernel=dom, bound="alu", achieved=round(ach, 3),
+                    peak=round(FP32_PEAK_TFLOPS, 1), unit="TFLOP/s",
+                    frac=round(ach / FP32_PEAK_TFLOPS, 4), traffic=None)
     kb = 2 if (tiles_x * tiles_y) <= 65536 else 4
     sort_bytes_launch = n_inst * (2 * kb + 8)
-    sort = stages.get("sort")
     binning = None
-    if sort:
-        gbs = sort_bytes_launch / (sort["ms_per_launch"] * 1e-3) / 1e9
-        binning = dict(kernel="sort_pass", bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS,
-                       unit="GB/s", frac=round(gbs / HBM_PEAK_GBS, 4),
+    if "sort" in stages:
+        gbs = sort_bytes_launch / (stages["sort"]["ms_per_launch"] * 1e-3) / 1e9
+        binning = dict(kernel="sort_pass", bound="hbm", achieved=round(gbs, 1),
+                       peak=HBM_PEAK_GBS, unit="GB/s", frac=round(gbs / HBM_PEAK_GBS, 4),
                        bytes_per_launch=sort_bytes_launch)
 
     out = {
@@ -205,8 +208,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": desc, "gaussians": sc.n, "width": cam.width, "height": cam.height,
-                   "K": st.K, "tile": [st.tile_w, st.tile_h]},
+        "config": {"workload": desc, "gaussians": sc.n, "width": cam.width,
+                   "height": cam.height, "K": st.K, **settings_desc(st)},
         "roofline": roofline,
         "binning_roofline": binning,
         "stages_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in stages.items()},
@@ -215,6 +218,7 @@ def main():
         "candidate_pairs": pairs,
         "gaussian_pixels_per_s": sc.n * cam.width * cam.height / (ms_step * 1e-3),
         "candidate_pairs_per_s": pairs / (ms_step * 1e-3),
+        "autotune": tune_rep,
     }
     if args.workload != "1080p" or args.forward_only:
         out["metric"] = f"{'fwd' if args.forward_only else 'fwd+bwd'} ms/frame ({args.workload})"
@@ -226,6 +230,137 @@ def main():
         torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = {"read": src.numel() * 4, "write": dst.numel() * 4}
+        del src, dst
+    del ws, state, grads, params
+    torch.cuda.empty_cache()
+    return out, (sc, cam, st)
+
+
+def run_multiview(args, steps=3, warmup=1):
+    """Plain (16 sequential single-view fwd+bwd calls, no graph) vs batched
+    (one hipGraph replay of the batched fwd+bwd); same kernels, same
+    accuracy (batched gradient = sum of per-view gradients)."""
+    import torch
+
+    from paper_2410_08129_amd import htgs, scenes
+
+    log("bench: multiview, generating 3M-Gaussian scene")
+    sc, cams, st, desc = workload("multiview")
+    dev = torch.device("cuda:0")
+    params = [torch.tensor(a, device=dev) for a in sc.arrays()]
+    st, tune_rep = tune(params, sc, cams, st, args)
+    targets = [torch.tensor(scenes.smooth_target(c.height, c.width, seed=1 + v), device=dev)
+               for v, c in enumerate(cams)]
+    imgs = [torch.empty((3, c.height, c.width), dtype=torch.float32, device=dev) for c in cams]
+    gimgs = [torch.empty_like(im) for im in imgs]
+
+    # plain: one workspace and state sized for the largest view, reused
+    counts = [htgs.count_instances(params, sc.sh_degree, [c], st) for c in cams]
+    big = max(range(len(cams)), key=lambda v: cams[v].width * cams[v].height)
+    ws1 = htgs.alloc_workspace(sc.n, [cams[big]], st, max(counts), dev)
+    st1 = torch.empty(htgs.state_bytes([cams[big]], st) // 4, dtype=torch.float32, device=dev)
+    grads_p = [torch.zeros_like(p) for p in params]
+
+    def plain_step():
+        for g in grads_p:
+            g.zero_()
+        for v, c in enumerate(cams):
+            fr = htgs.forward(params, sc.sh_degree, [c], st, ws=ws1, state=st1, images=[imgs[v]])
+            torch.sub(imgs[v], targets[v], out=gimgs[v])
+            gimgs[v].sign_().mul_(1.0 / imgs[v].numel())
+            htgs.backward(params, fr, [gimgs[v]], grads=grads_p)
+
+    n_b = htgs.count_instances(params, sc.sh_degree, cams, st)
+    wsb = htgs.alloc_workspace(sc.n, cams, st, n_b, dev)
+    stb = torch.empty(htgs.state_bytes(cams, st) // 4, dtype=torch.float32, device=dev)
+    grads_b = [torch.zeros_like(p) for p in params]
+    imgs_b = [torch.empty_like(im) for im in imgs]
+    gimgs_b = [torch.empty_like(im) for im in imgs]
+    log(f"bench: multiview {len(cams)} views, {sum(counts)} instances (per view), "
+        f"{n_b} (batched), batched ws {wsb.numel() / 2**30:.1f} GiB")
+
+    def batched_step():
+        for g in grads_b:
+            g.zero_()
+        fr = htgs.forward(params, sc.sh_degree, cams, st, ws=wsb, state=stb, images=imgs_b)
+        for v in range(len(cams)):
+            torch.sub(imgs_b[v], targets[v], out=gimgs_b[v])
+            gimgs_b[v].sign_().mul_(1.0 / imgs_b[v].numel())
+        htgs.backward(params, fr, gimgs_b, grads=grads_b)
+
+    for _ in range(warmup):
+        plain_step()
+        batched_step()
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        batched_step()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        batched_step()
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps
+
+    ms_plain = timed(plain_step)
+    ms_batched = timed(graph.replay)
+    flags, _ = htgs.read_status(wsb)
+    rel = {}
+    for name, a, b in zip(("means", "log_scales", "quats", "opacity_logits", "sh"),
+                          grads_b, grads_p):
+        rel[name] = float((a - b).norm() / b.norm().clamp_min(1e-30))
+    img_err = max(float((a - b).abs().max()) for a, b in zip(imgs_b, imgs))
+    log(f"bench: multiview plain {ms_plain:.2f} ms, batched {ms_batched:.2f} ms")
+    out = dict(workload=desc, views=[[c.width, c.height] for c in cams], steps=steps,
+               plain_ms_per_step=round(ms_plain, 3), batched_ms_per_step=round(ms_batched, 3),
+               speedup=round(ms_plain / ms_batched, 3), status_flags=flags,
+               batched_vs_plain_image_max_abs=img_err, batched_vs_plain_grad_rel=rel,
+               instances=n_b, settings=settings_desc(st), autotune=tune_rep)
+    del wsb, ws1, stb, st1, params, grads_p, grads_b
+    torch.cuda.empty_cache()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="1080p")
+    ap.add_argument("--tile", type=int, default=0, help="fixed tile size (8 or 16), no autotune")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-multiview", action="store_true")
+    ap.add_argument("--forward-only", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 256 MiB elementwise copy (reference for HBM counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the renderer runs on a single MI355X).", file=sys.stderr)
+        sys.exit(2)
+
+    if args.workload == "multiview":
+        mv = run_multiview(args, steps=max(1, args.steps // 5), warmup=1)
+        out = {"metric": "batched vs plain speedup (16 views, 3M Gaussians)",
+               "value": mv["speedup"], "unit": "x", "n_gpus": 1, "steps": mv["steps"],
+               "warmup": 1, "ms_per_step": mv["batched_ms_per_step"], "higher_is_better": True,
+               "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+               "config": {"workload": mv["workload"]}, "multiview": mv}
+        print(json.dumps(out), flush=True)
+        return
+
+    out, (sc, cam, st) = run_single(args)
+    if not args.no_multiview and args.workload == "1080p" and not args.forward_only:
+        out["multiview"] = run_multiview(args)
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(sc, cam, st)

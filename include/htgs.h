@@ -90,7 +90,10 @@ typedef struct htgs_camera {
  *  alpha_max  alpha clamp, alpha = min(alpha_max, o exp(-rho^2/2)), in (0,1)
  *  bg         background colour c_bg of Eq. pixel_color_computation
  *  tile_w/h   8x8 or 16x16 pixels
- *  lds_batch  records staged per batch in the forward; 0 = the tile's pixel count */
+ *  lds_batch  records staged per batch in the forward: 0 or the tile's pixel
+ *             count (one per thread), or, with 8x8 tiles, twice that
+ *  flags      HTGS_FLAG_COST_ORDER: rasterize tiles in descending order of
+ *             their instance count (better load balance on uneven scenes) */
 typedef struct htgs_config {
   int32_t K;
   float tau_alpha;
@@ -100,8 +103,10 @@ typedef struct htgs_config {
   int32_t tile_w;
   int32_t tile_h;
   int32_t lds_batch;
-  uint32_t flags; /* reserved, must be 0 */
+  uint32_t flags;
 } htgs_config;
+
+#define HTGS_FLAG_COST_ORDER 1u
 
 /* Gradient outputs, same shapes as htgs_gaussians. The backward ADDS into
  * them (+=); any pointer may be NULL to skip that parameter. */

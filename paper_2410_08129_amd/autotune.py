@@ -1,0 +1,105 @@
+"""Autotuner: picks the tile shape, the forward LDS batch depth and the tile
+order for a workload by timing a few forward+backward steps of each
+candidate on the device (HIP events), and caches the choice as JSON.
+
+Environment: HTGS_TUNE = search (default) | cache (use the cache, search on
+a miss) | off (keep the given settings); HTGS_TUNE_CACHE = path of the JSON
+cache (default ~/.cache/htgs_tune.json). The cache key is the device name,
+log2 buckets of the Gaussian count and of the total pixel count, the number
+of views, K and the SH degree.
+"""
+from __future__ import annotations
+
+import dataclasses
+import json
+import math
+import os
+
+import torch
+
+from . import htgs
+
+CANDIDATES = (
+    # (tile, lds_batch multiplier, cost order)
+    (8, 1, False), (8, 2, False), (8, 1, True), (8, 2, True), (16, 1, False), (16, 1, True),
+)
+
+
+def _cache_path():
+    return os.environ.get("HTGS_TUNE_CACHE", os.path.expanduser("~/.cache/htgs_tune.json"))
+
+
+def _key(n, cams, st, sh_degree):
+    px = sum(c.width * c.height for c in cams)
+    dev = torch.cuda.get_device_name(0) if torch.cuda.is_available() else "cpu"
+    return (f"{dev}|n{int(math.log2(max(n, 1)))}|px{int(math.log2(max(px, 1)))}|v{len(cams)}"
+            f"|K{st.K}|sh{sh_degree}")
+
+
+def apply(st, cand):
+    tile, mult, order = cand
+    return dataclasses.replace(st, tile_w=tile, tile_h=tile,
+                               lds_batch=(tile * tile * mult) if mult > 1 else 0,
+                               cost_order=bool(order))
+
+
+def _time_candidate(params, sh_degree, cams, st, steps):
+    dev = params[0].device
+    n_inst = htgs.count_instances(params, sh_degree, cams, st)
+    ws = htgs.alloc_workspace(params[0].shape[0], cams, st, n_inst, dev)
+    state = torch.empty(htgs.state_bytes(cams, st) // 4, dtype=torch.float32, device=dev)
+    imgs = [torch.empty((3, c.height, c.width), dtype=torch.float32, device=dev) for c in cams]
+    gimgs = [torch.full_like(im, 1.0 / im.numel()) for im in imgs]
+    grads = [torch.zeros_like(p) for p in params]
+
+    def step():
+        fr = htgs.forward(params, sh_degree, cams, st, ws=ws, state=state, images=imgs)
+        htgs.backward(params, fr, gimgs, grads=grads)
+
+    step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def tune(params, sh_degree, cams, st, steps=3, verbose=False):
+    """Returns (settings, report) for this workload."""
+    mode = os.environ.get("HTGS_TUNE", "search")
+    if mode == "off":
+        return st, {"mode": "off"}
+    key = _key(params[0].shape[0], cams, st, sh_degree)
+    path = _cache_path()
+    cache = {}
+    if os.path.exists(path):
+        try:
+            cache = json.load(open(path))
+        except (OSError, ValueError):
+            cache = {}
+    if mode == "cache" and key in cache:
+        return apply(st, tuple(cache[key]["choice"])), {"mode": "cache", **cache[key]}
+    times = {}
+    by_name = {}
+    for cand in CANDIDATES:
+        if cand[0] == 16 and st.K > 16:
+            continue
+        ms = _time_candidate(params, sh_degree, cams, apply(st, cand), steps)
+        name = f"tile{cand[0]}_batch{cand[1]}x_{'cost' if cand[2] else 'xcd'}"
+        times[name] = ms
+        by_name[name] = cand
+        if verbose:
+            print(f"autotune {name}: {ms:.3f} ms", flush=True)
+    best = min(times, key=times.get)
+    choice = by_name[best]
+    entry = {"choice": list(choice), "best": best, "ms": times}
+    cache[key] = entry
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        json.dump(cache, open(path, "w"), indent=1)
+    except OSError:
+        pass
+    return apply(st, choice), {"mode": "search", **entry}

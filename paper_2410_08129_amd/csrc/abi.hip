@@ -16,6 +16,7 @@ hipError_t launch_preprocess_bwd(const GaussPtrs &gp, const GradPtrs &gr, const 
 hipError_t launch_segment_reduce(const Ws &w, hipStream_t s);
 hipError_t launch_sort_passes(const Ws &w, hipStream_t s);
 hipError_t launch_ranges(const Ws &w, hipStream_t s);
+hipError_t launch_tile_order(const Ws &w, int total_tiles, hipStream_t s);
 hipError_t launch_raster_fwd(const Ws &w, const ViewSet &vs, const KCfg &cfg, float *state,
                              const uint32_t *vals, hipStream_t s);
 hipError_t launch_raster_bwd(const Ws &w, const ViewSet &vs, const KCfg &cfg, const float *state,
@@ -29,8 +30,8 @@ constexpr int64_t kMaxCapacity = (1ll << 30) - 1;
 int64_t align_up(int64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  int64_t status, total, pp_look, hist, sort_look, ranges, zero_end;
-  int64_t records, rects, offsets, keys0, keys1, vals0, vals1, partials, bytes;
+  int64_t status, total, pp_look, hist, sort_look, ranges, order_hist, zero_end;
+  int64_t records, rects, offsets, order, keys0, keys1, vals0, vals1, partials, bytes;
   int64_t capacity, max_chunks;
   int32_t key_bits, passes, key16;
 };
@@ -56,10 +57,12 @@ Layout make_layout(int64_t n, int n_views, int64_t total_tiles, int64_t capacity
   L.hist = o; o = align_up(o + 4 * 256 * 4);
   L.sort_look = o; o = align_up(o + (int64_t)L.passes * L.max_chunks * 256 * 4);
   L.ranges = o; o = align_up(o + 8 * total_tiles);
+  L.order_hist = o; o = align_up(o + 2 * 32 * 4);
   L.zero_end = o;
   L.records = o; o = align_up(o + (int64_t)n_views * n * kRecFloats * 4);
   L.rects = o; o = align_up(o + (int64_t)n_views * n * 16);
   L.offsets = o; o = align_up(o + 4 * n);
+  L.order = o; o = align_up(o + 4 * total_tiles);
   L.keys0 = o; o = align_up(o + kb * capacity);
   L.keys1 = o; o = align_up(o + kb * capacity);
   L.vals0 = o; o = align_up(o + 4 * capacity);
@@ -91,6 +94,8 @@ Ws make_ws(void *base, const Layout &L) {
   w.hist = reinterpret_cast<uint32_t *>(b + L.hist);
   w.sort_look = reinterpret_cast<uint32_t *>(b + L.sort_look);
   w.ranges = reinterpret_cast<uint2 *>(b + L.ranges);
+  w.order_hist = reinterpret_cast<uint32_t *>(b + L.order_hist);
+  w.order = reinterpret_cast<uint32_t *>(b + L.order);
   w.records = reinterpret_cast<float *>(b + L.records);
   w.rects = reinterpret_cast<int4 *>(b + L.rects);
   w.offsets = reinterpret_cast<uint32_t *>(b + L.offsets);
@@ -120,8 +125,10 @@ int check_cfg(const htgs_config *cfg) {
   const bool t16 = cfg->tile_w == 16 && cfg->tile_h == 16;
   if (!t8 && !t16) return HTGS_E_INVAL;
   if (t16 && cfg->K > 16) return HTGS_E_INVAL;
-  if (cfg->lds_batch != 0 && cfg->lds_batch != cfg->tile_w * cfg->tile_h) return HTGS_E_INVAL;
-  if (cfg->flags != 0) return HTGS_E_INVAL;
+  const int np = cfg->tile_w * cfg->tile_h;
+  if (cfg->lds_batch != 0 && cfg->lds_batch != np && !(t8 && cfg->lds_batch == 2 * np))
+    return HTGS_E_INVAL;
+  if (cfg->flags & ~(uint32_t)HTGS_FLAG_COST_ORDER) return HTGS_E_INVAL;
   return HTGS_OK;
 }
 
@@ -209,6 +216,8 @@ KCfg make_kcfg(const htgs_gaussians *g, const htgs_config *cfg) {
   for (int c = 0; c < 3; ++c) k.bg[c] = cfg->bg[c];
   k.tile_w = cfg->tile_w;
   k.tile_h = cfg->tile_h;
+  k.batch_mult = (cfg->lds_batch == 2 * cfg->tile_w * cfg->tile_h) ? 2 : 1;
+  k.cost_order = (cfg->flags & HTGS_FLAG_COST_ORDER) ? 1 : 0;
   return k;
 }
 
@@ -286,6 +295,7 @@ int run_front(const htgs_gaussians *g, const ViewSet &vs, const htgs_config *cfg
   if (sort && L.capacity > 0) {
     StageTimer t(HTGS_STAGE_RANGES, s);
     HIP_TRY(launch_ranges(w, s));
+    if (cfg->flags & HTGS_FLAG_COST_ORDER) HIP_TRY(launch_tile_order(w, vs.total_tiles, s));
   }
   return HTGS_OK;
 }

@@ -80,6 +80,8 @@ struct KCfg {
   float tau_alpha, tau_core, alpha_max;
   float bg[3];
   int32_t tile_w, tile_h;
+  int32_t batch_mult;   // records staged per forward thread and batch (1 or 2)
+  int32_t cost_order;   // raster workgroups take tiles in descending-cost order
 };
 
 struct GaussPtrs {
@@ -99,6 +101,8 @@ struct Ws {
   uint32_t *hist;              // [4][256] digit histograms
   uint32_t *sort_look;         // [passes][max_chunks][256]
   uint2 *ranges;               // [total_tiles] (start, end)
+  uint32_t *order_hist;        // [2][32] cost-bucket counts and cursors
+  uint32_t *order;             // [total_tiles] tiles by descending instance count
   float *records;              // [views][n][32]
   int4 *rects;                 // [views][n] tile rect (tx0, ty0, tx1, ty1), empty if tx0 > tx1
   uint32_t *offsets;           // [n] first instance slot of each Gaussian

@@ -133,9 +133,15 @@ struct TileInfo {
   int t, v, tx, ty;
 };
 
-__device__ __forceinline__ bool tile_info(const ViewSet &vs, TileInfo &ti) {
-  ti.t = xcd_tile(blockIdx.x, vs.total_tiles);
-  if (ti.t >= vs.total_tiles) return false;
+__device__ __forceinline__ bool tile_info(const ViewSet &vs, const KCfg &cfg, const Ws &w,
+                                          TileInfo &ti) {
+  if (cfg.cost_order) {
+    if ((int)blockIdx.x >= vs.total_tiles) return false;
+    ti.t = (int)w.order[blockIdx.x];
+  } else {
+    ti.t = xcd_tile(blockIdx.x, vs.total_tiles);
+    if (ti.t >= vs.total_tiles) return false;
+  }
   ti.v = view_of_tile(vs, ti.t);
   const int lt = ti.t - vs.v[ti.v].tile_base;
   ti.tx = lt % vs.v[ti.v].tiles_x;
@@ -151,20 +157,21 @@ __device__ __forceinline__ bool rect_meets_block(const float *bb, int bx, int by
 // ---------------------------------------------------------------------------
 // Forward
 // ---------------------------------------------------------------------------
-template <int KMAX, int TW, int TH>
+template <int KMAX, int TW, int TH, int BM>
 __global__ void __launch_bounds__(TW *TH) k_raster_fwd(Ws w, ViewSet vs, KCfg cfg,
                                                        float *__restrict__ state,
                                                        const uint32_t *__restrict__ vals) {
   constexpr int NT = TW * TH;
-  constexpr int NW = NT / 64;   // waves, one 8x8 block each
+  constexpr int NBATCH = NT * BM;   // records staged per batch
+  constexpr int NW = NT / 64;       // waves, one 8x8 block each
   constexpr int BX = TW / 8;
   constexpr int SV = S_FLOATS / 4;
-  __shared__ float4 s_stage[NT * SV];
-  __shared__ uint16_t s_list[NW][NT];
+  __shared__ float4 s_stage[NBATCH * SV];
+  __shared__ uint16_t s_list[NW][NBATCH];
   __shared__ uint32_t s_nfrag;
 
   TileInfo ti;
-  if (!tile_info(vs, ti)) return;
+  if (!tile_info(vs, cfg, w, ti)) return;
   const ViewParams &V = vs.v[ti.v];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int bx = (wave % BX) * 8, by = (wave / BX) * 8;
@@ -190,18 +197,22 @@ __global__ void __launch_bounds__(TW *TH) k_raster_fwd(Ws w, ViewSet vs, KCfg cf
   uint32_t nfrag = 0;
   if (tid == 0) s_nfrag = 0u;
 
-  for (uint32_t base = rg.x; base < rg.y; base += NT) {
-    const int cnt = (int)min((uint32_t)NT, rg.y - base);
+  for (uint32_t base = rg.x; base < rg.y; base += NBATCH) {
+    const int cnt = (int)min((uint32_t)NBATCH, rg.y - base);
     __syncthreads();
-    if (tid < cnt) {
-      const uint32_t gid = vals[base + tid];
-      float rec[kRecFloats];
-      load_record(recs, gid, rec);
-      float st[S_FLOATS];
-      stage_record(rec, px0, py0, base - rg.x + tid, st);
 #pragma unroll
-      for (int k = 0; k < SV; ++k)
-        s_stage[tid * SV + k] = make_float4(st[4 * k], st[4 * k + 1], st[4 * k + 2], st[4 * k + 3]);
+    for (int r0 = 0; r0 < NBATCH; r0 += NT) {
+      const int r = r0 + tid;
+      if (r < cnt) {
+        const uint32_t gid = vals[base + r];
+        float rec[kRecFloats];
+        load_record(recs, gid, rec);
+        float st[S_FLOATS];
+        stage_record(rec, px0, py0, base - rg.x + r, st);
+#pragma unroll
+        for (int k = 0; k < SV; ++k)
+          s_stage[r * SV + k] = make_float4(st[4 * k], st[4 * k + 1], st[4 * k + 2], st[4 * k + 3]);
+      }
     }
     __syncthreads();
     // This wave's list: the staged splats whose pixel rect meets its block.
@@ -398,7 +409,7 @@ __global__ void __launch_bounds__(256) k_raster_bwd(Ws w, ViewSet vs, KCfg cfg,
   __shared__ uint16_t s_ent[4][NT][KMAX];
 
   TileInfo ti;
-  if (!tile_info(vs, ti)) return;
+  if (!tile_info(vs, cfg, w, ti)) return;
   const ViewParams &V = vs.v[ti.v];
   const int tid = threadIdx.x;
   const int px0 = ti.tx * TW, py0 = ti.ty * TH;
@@ -602,8 +613,15 @@ template <int KMAX, int TW, int TH>
 static hipError_t fwd_launch(const Ws &w, const ViewSet &vs, const KCfg &cfg, float *state,
                              const uint32_t *vals, hipStream_t s) {
   const int blocks = 8 * ((vs.total_tiles + 7) / 8);
-  hipLaunchKernelGGL((k_raster_fwd<KMAX, TW, TH>), dim3(blocks), dim3(TW * TH), 0, s, w, vs, cfg,
-                     state, vals);
+  if constexpr (TW == 8) {
+    if (cfg.batch_mult == 2) {
+      hipLaunchKernelGGL((k_raster_fwd<KMAX, TW, TH, 2>), dim3(blocks), dim3(TW * TH), 0, s, w,
+                         vs, cfg, state, vals);
+      return hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL((k_raster_fwd<KMAX, TW, TH, 1>), dim3(blocks), dim3(TW * TH), 0, s, w, vs,
+                     cfg, state, vals);
   return hipGetLastError();
 }
 

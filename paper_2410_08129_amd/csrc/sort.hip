@@ -148,6 +148,44 @@ __global__ void __launch_bounds__(256) k_ranges(Ws w, const KeyT *__restrict__ k
   }
 }
 
+// Tiles in descending order of their instance count, by power-of-two
+// buckets (bucket clz(count) - 1; empty tiles last). The order inside a
+// bucket is arbitrary; it only decides which workgroup runs a tile first.
+__device__ __forceinline__ uint32_t cost_bucket(uint2 r) {
+  const uint32_t c = r.y - r.x;
+  return c == 0 ? 31u : (uint32_t)__clz(c) - 1u;
+}
+
+__global__ void __launch_bounds__(256) k_tile_order_count(Ws w, int total_tiles) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < total_tiles; t += gridDim.x * blockDim.x)
+    atomicAdd(&w.order_hist[cost_bucket(w.ranges[t])], 1u);
+}
+
+__global__ void __launch_bounds__(256) k_tile_order_place(Ws w, int total_tiles) {
+  __shared__ uint32_t s_base[32];
+  if (threadIdx.x < 32) {
+    uint32_t b = 0;
+    for (uint32_t k = 0; k < threadIdx.x; ++k) b += w.order_hist[k];
+    s_base[threadIdx.x] = b;
+  }
+  __syncthreads();
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < total_tiles; t += gridDim.x * blockDim.x) {
+    const uint32_t b = cost_bucket(w.ranges[t]);
+    w.order[s_base[b] + atomicAdd(&w.order_hist[32 + b], 1u)] = (uint32_t)t;
+  }
+}
+
+hipError_t launch_tile_order(const Ws &w, int total_tiles, hipStream_t s) {
+  int blocks = (total_tiles + 255) / 256;
+  if (blocks > 1024) blocks = 1024;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_tile_order_count, dim3(blocks), dim3(256), 0, s, w, total_tiles);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_tile_order_place, dim3(blocks), dim3(256), 0, s, w, total_tiles);
+  return hipGetLastError();
+}
+
 template <typename KeyT>
 static hipError_t sort_impl(const Ws &w, hipStream_t s) {
   const int blocks = (int)(w.max_chunks > 0 ? w.max_chunks : 1);

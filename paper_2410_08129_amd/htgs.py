@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libhtgs.so")
 HTGS_OK = 0
 HTGS_STATUS_OVERFLOW = 1
 HTGS_STATUS_SPIN_TIMEOUT = 2
+HTGS_FLAG_COST_ORDER = 1
 MAX_VIEWS = 16
 
 EXPORTED = (
@@ -134,8 +135,8 @@ def config_struct(st) -> Config:
     c.tau_alpha, c.tau_core, c.alpha_max = float(st.tau_alpha), float(st.tau_core), float(st.alpha_max)
     c.bg = (ctypes.c_float * 3)(*[float(b) for b in st.bg])
     c.tile_w, c.tile_h = int(st.tile_w), int(st.tile_h)
-    c.lds_batch = 0
-    c.flags = 0
+    c.lds_batch = int(getattr(st, "lds_batch", 0))
+    c.flags = HTGS_FLAG_COST_ORDER if getattr(st, "cost_order", False) else 0
     return c
 
 

@@ -92,6 +92,8 @@ class RenderSettings:
     bg: tuple = (0.0, 0.0, 0.0)
     tile_w: int = 16
     tile_h: int = 16
+    lds_batch: int = 0          # forward records per batch: 0 = tile pixels, 2x allowed at 8x8
+    cost_order: bool = False    # rasterize tiles in descending instance-count order
 
 
 def look_at(eye, target, up_world, fov_x_deg, width, height, z_near=0.2) -> Camera:
