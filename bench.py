@@ -117,7 +117,7 @@ def run_single(args):
     import numpy as np
     import torch
 
-    from paper_2410_08129_amd import htgs, scenes
+    from paper_2410_08129_amd import htgs, pmc, scenes
 
     log(f"bench: workload {args.workload}, generating scene")
     sc, cams, st, desc = workload(args.workload)
@@ -183,18 +183,47 @@ def run_single(args):
     cands = ("raster_fwd",) if args.forward_only else ("raster_fwd", "raster_bwd")
     dom = max(cands, key=lambda k: stages.get(k, {}).get("ms_per_step", 0.0))
     ach = work[dom] / (stages[dom]["ms_per_launch"] * 1e-3)
+    # HBM bytes per launch of that kernel from the stored counter record of
+    # this workload, if it was taken on the current kernel sources
+    kmax = next(k for k in (1, 2, 4, 8, 16, 32) if k >= max(st.K, 1))
+    if dom == "raster_bwd":
+        key = f"k_raster_bwd<{kmax}, {st.tile_w}, {st.tile_h}>"
+    else:
+        bm = 2 if st.lds_batch == 2 * st.tile_w * st.tile_h else 1
+        key = f"k_raster_fwd<{kmax}, {st.tile_w}, {st.tile_h}, {bm}>"
+    tr = pmc.traffic_for(os.path.join(ROOT, "profiles", f"hbm_traffic_{args.workload}.json"), key)
     roofline = dict(kernel=dom, bound="alu", achieved=round(ach, 3),
                     peak=round(FP32_PEAK_TFLOPS, 1), unit="TFLOP/s",
-                    frac=round(ach / FP32_PEAK_TFLOPS, 4), traffic=None)
-    kb = 2 if (tiles_x * tiles_y) <= 65536 else 4
-    sort_bytes_launch = n_inst * (2 * kb + 8)
+                    frac=round(ach / FP32_PEAK_TFLOPS, 4),
+                    traffic=(round(tr["total"]) if tr else None))
+    if tr:
+        roofline["traffic_unit"] = "bytes/launch"
+    # HBM-bound front end (algorithmic bytes): per sort pass, keys and
+    # values read and written once; binning + sort as a whole, B_bin =
+    # 8 N + I [(k+4) emit + k histogram + 2 P (k+4) sort + k ranges] + 8 tiles;
+    # preprocess reads the parameters and writes record, rect and offset.
+    n_tiles = tiles_x * tiles_y
+    key_bits = max(1, (n_tiles - 1).bit_length())
+    passes = (key_bits + 7) // 8
+    kb = 2 if key_bits <= 16 else 4
+    sort_bytes_launch = n_inst * 2 * (kb + 4)
+    b_bin = 8 * sc.n + n_inst * ((kb + 4) + kb + 2 * passes * (kb + 4) + kb) + 8 * n_tiles
+    b_pre = sc.n * (4 * (11 + 3 * (sc.sh_degree + 1) ** 2) + 4 * 32 + 16 + 4)
     binning = None
     if "sort" in stages:
         gbs = sort_bytes_launch / (stages["sort"]["ms_per_launch"] * 1e-3) / 1e9
-        binning = dict(kernel="sort_pass", bound="hbm", achieved=round(gbs, 1),
-                       peak=HBM_PEAK_GBS, unit="GB/s", frac=round(gbs / HBM_PEAK_GBS, 4),
-                       bytes_per_launch=sort_bytes_launch)
-
+        t_front = sum(stages[k]["ms_per_step"] for k in ("preprocess", "sort", "ranges")
+                      if k in stages)
+        gbs_front = (b_bin + b_pre) / (t_front * 1e-3) / 1e9
+        t_sort = sum(stages[k]["ms_per_step"] for k in ("sort", "ranges") if k in stages)
+        binning = dict(
+            kernel="sort_pass", bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS,
+            unit="GB/s", frac=round(gbs / HBM_PEAK_GBS, 4), bytes_per_launch=sort_bytes_launch,
+            sort_and_ranges=dict(ms=round(t_sort, 4), bytes=n_inst * (2 * passes * (kb + 4) + kb)
+                                 + 8 * n_tiles),
+            front_end=dict(stages="preprocess+emit+sort+ranges", ms=round(t_front, 4),
+                           bytes=b_bin + b_pre, achieved=round(gbs_front, 1),
+                           frac=round(gbs_front / HBM_PEAK_GBS, 4)))
     out = {
         "metric": "fwd+bwd ms/frame at 1080p & 1M Gaussians",
         "value": round(ms_step, 4),

@@ -120,6 +120,7 @@ constexpr uint32_t kFlagA32 = 1u << 30, kFlagP32 = 2u << 30, kMask32 = (1u << 30
 constexpr unsigned long long kFlagA64 = 1ull << 62, kFlagP64 = 2ull << 62,
                              kMask64 = (1ull << 62) - 1ull;
 constexpr int kSpinLimit = 1 << 22;
+constexpr int kLookWindow = 4;   // look-back words read per round trip
 
 enum StatusBits : uint32_t { ST_OVERFLOW = 1u, ST_SPIN = 2u };
 

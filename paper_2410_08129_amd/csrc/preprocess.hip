@@ -284,19 +284,31 @@ __global__ void __launch_bounds__(kPreThreads) k_preprocess(GaussPtrs gp, KCfg c
       int64_t j = blk - 1;
       int spins = 0;
       while (true) {
-        const unsigned long long s = ld_acq_u64(&w.pp_look[j]);
-        const unsigned f = (unsigned)(s >> 62);
-        if (f == 0) {
+        // kLookWindow predecessors per round trip; stop at the first
+        // inclusive (P) or unpublished word.
+        unsigned long long sv[kLookWindow];
+#pragma unroll
+        for (int k = 0; k < kLookWindow; ++k) sv[k] = (j - k >= 0) ? ld_acq_u64(&w.pp_look[j - k]) : 0ull;
+        int used = 0;
+        bool done = false;
+#pragma unroll
+        for (int k = 0; k < kLookWindow; ++k) {
+          if (done || used < k) continue;
+          const unsigned f = (unsigned)(sv[k] >> 62);
+          if (f == 0) continue;
+          excl += sv[k] & kMask64;
+          used = k + 1;
+          done = (f == 2);
+        }
+        if (done) break;
+        j -= used;
+        if (used == 0) {
           if (++spins > kSpinLimit) {
             atomicOr(&w.status[0], (uint32_t)ST_SPIN);
             break;
           }
           __builtin_amdgcn_s_sleep(1);
-          continue;
         }
-        excl += s & kMask64;
-        if (f == 2) break;
-        --j;
       }
       st_rel_u64(&w.pp_look[blk], kFlagP64 | (excl + block_total));
     }

@@ -8,11 +8,12 @@
 // tile-centred), rho^2 = |m|^2/|d|^2 (Eq. rho-pluecker), alpha =
 // min(alpha_max, o exp(-rho^2/2)), and for fragments with alpha >= tau_K the
 // view depth of the maximum-density point z = (M T [(d x m)/|d|^2; 1])_z
-// (Sec. 3.3). Those go through an unrolled insertion network into a
-// register core of K (depth, alpha, list position, rgb) entries; what falls
-// off the end, and every other fragment, is added to the order-independent
-// tail (sum alpha, sum alpha rgb, prod (1 - alpha)). The composite is
-// Eq. pixel_color_computation.
+// (Sec. 3.3). Those enter a register core of K (depth, alpha, list
+// position) entries kept sorted by a select-based shift. Every fragment is
+// added to running sums (sum alpha, sum alpha rgb, prod (1 - alpha)); at
+// the end the core members are taken back out of them, which leaves the
+// order-independent tail of everything that never entered the core or fell
+// off its end. The composite is Eq. pixel_color_computation.
 //
 // Backward: one workgroup per tile. First each pixel's adjoint factors are
 // built in LDS: the core terms T_i (c_i - B_i) . G and T_i by walking the
@@ -186,11 +187,15 @@ __global__ void __launch_bounds__(TW *TH) k_raster_fwd(Ws w, ViewSet vs, KCfg cf
   const float *recs = w.records + (int64_t)ti.v * cfg.n * kRecFloats;
   const uint64_t lanemask_lt = (1ull << lane) - 1ull;
 
-  float cz[KMAX], ca[KMAX], cr[KMAX], cg[KMAX], cb[KMAX];
+  // Core: depth, alpha and list position of up to K fragments, sorted by
+  // depth (ties keep list order). Every fragment is added to the running
+  // sums (alpha, alpha rgb, prod 1 - alpha); the core members are taken out
+  // of them once the list is done, which leaves exactly the tail sums.
+  float cz[KMAX], ca[KMAX];
   int cp[KMAX];
 #pragma unroll
   for (int i = 0; i < KMAX; ++i) {
-    cz[i] = INFINITY; ca[i] = 0.f; cr[i] = cg[i] = cb[i] = 0.f; cp[i] = -1;
+    cz[i] = INFINITY; ca[i] = 0.f; cp[i] = -1;
   }
   float zlast = INFINITY;
   float A = 0.f, S0 = 0.f, S1 = 0.f, S2 = 0.f, P = 1.f;
@@ -250,38 +255,39 @@ __global__ void __launch_bounds__(TW *TH) k_raster_fwd(Ws w, ViewSet vs, KCfg cf
       const float inv = rcp_fast(dd);
       const float r2 = mm * inv;
       const float alpha = fminf(amax, st[S_O] * exp2_fast(r2 * kNegHalfLog2e));
-      float ta = alpha, tr = st[S_RGB], tg = st[S_RGB + 1], tb = st[S_RGB + 2];
-      bool to_tail = true;
+      A += alpha;
+      S0 = fmaf(alpha, st[S_RGB], S0);
+      S1 = fmaf(alpha, st[S_RGB + 1], S1);
+      S2 = fmaf(alpha, st[S_RGB + 2], S2);
+      P *= 1.f - alpha;
       if (alpha >= tau_core && K > 0) {
-        float z = max_point_depth(st, d, m, inv);
+        const float z = max_point_depth(st, d, m, inv);
         if (z < zlast) {
-          int id = (int)__float_as_uint(st[S_POS]);
-          float a = alpha;
-          float zl = zlast;
+          // Insert at the first entry deeper than z; the entries from there
+          // on move back by one and the last one drops out of the core.
+          const int pos = (int)__float_as_uint(st[S_POS]);
+          bool c[KMAX];
 #pragma unroll
-          for (int i = 0; i < KMAX; ++i) {
-            if (i < K) {
-              const bool sw = z < cz[i];
-              const float nz = sw ? z : cz[i]; z = sw ? cz[i] : z; cz[i] = nz;
-              const float na = sw ? a : ca[i]; a = sw ? ca[i] : a; ca[i] = na;
-              const int ni = sw ? id : cp[i]; id = sw ? cp[i] : id; cp[i] = ni;
-              const float nr = sw ? tr : cr[i]; tr = sw ? cr[i] : tr; cr[i] = nr;
-              const float ng = sw ? tg : cg[i]; tg = sw ? cg[i] : tg; cg[i] = ng;
-              const float nb = sw ? tb : cb[i]; tb = sw ? cb[i] : tb; cb[i] = nb;
-              if (i == K - 1) zl = cz[i];
-            }
+          for (int i = 0; i < KMAX; ++i) c[i] = z < cz[i];
+          // (Entries at K and beyond, if K < KMAX, are shifted too but never
+          // read.)
+#pragma unroll
+          for (int i = KMAX - 1; i >= 1; --i) {
+            cz[i] = c[i - 1] ? cz[i - 1] : (c[i] ? z : cz[i]);
+            ca[i] = c[i - 1] ? ca[i - 1] : (c[i] ? alpha : ca[i]);
+            cp[i] = c[i - 1] ? cp[i - 1] : (c[i] ? pos : cp[i]);
           }
-          zlast = zl;
-          ta = a;
-          to_tail = id >= 0;
+          cz[0] = c[0] ? z : cz[0];
+          ca[0] = c[0] ? alpha : ca[0];
+          cp[0] = c[0] ? pos : cp[0];
+          if (K == KMAX) {
+            zlast = cz[KMAX - 1];
+          } else {
+#pragma unroll
+            for (int i = 0; i < KMAX; ++i)
+              if (i == K - 1) zlast = cz[i];
+          }
         }
-      }
-      if (to_tail) {
-        A += ta;
-        S0 = fmaf(ta, tr, S0);
-        S1 = fmaf(ta, tg, S1);
-        S2 = fmaf(ta, tb, S2);
-        P *= 1.f - ta;
       }
     }
   }
@@ -291,16 +297,42 @@ __global__ void __launch_bounds__(TW *TH) k_raster_fwd(Ws w, ViewSet vs, KCfg cf
   if (tid == 0 && s_nfrag) atomicAdd(w.frags, (unsigned long long)s_nfrag);
   if (!inside) return;
 
+  // Composite (Eq. pixel_color_computation): the core front to back, then
+  // the tail behind it.
   float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
+  float Ac = 0.f, Sc0 = 0.f, Sc1 = 0.f, Sc2 = 0.f;
+  uint32_t ncore = 0;
+  int gids[KMAX];
 #pragma unroll
   for (int i = 0; i < KMAX; ++i) {
+    gids[i] = -1;
     if (i < K && cp[i] >= 0) {
-      const float wgt = ca[i] * T;
-      C0 = fmaf(wgt, cr[i], C0);
-      C1 = fmaf(wgt, cg[i], C1);
-      C2 = fmaf(wgt, cb[i], C2);
-      T *= 1.f - ca[i];
+      const uint32_t gid = vals[rg.x + (uint32_t)cp[i]];
+      gids[i] = (int)gid;
+      const float4 c = *reinterpret_cast<const float4 *>(recs + (int64_t)gid * kRecFloats + R_RGB);
+      const float a = ca[i];
+      const float wgt = a * T;
+      C0 = fmaf(wgt, c.x, C0);
+      C1 = fmaf(wgt, c.y, C1);
+      C2 = fmaf(wgt, c.z, C2);
+      T *= 1.f - a;
+      Ac += a;
+      Sc0 = fmaf(a, c.x, Sc0);
+      Sc1 = fmaf(a, c.y, Sc1);
+      Sc2 = fmaf(a, c.z, Sc2);
+      ++ncore;
     }
+  }
+  // Tail sums: everything minus the core; exactly empty when no fragment
+  // is left over.
+  if (nfrag == ncore) {
+    A = 0.f; S0 = S1 = S2 = 0.f; P = 1.f;
+  } else {
+    A = fmaxf(A - Ac, 0.f);
+    S0 = fmaxf(S0 - Sc0, 0.f);
+    S1 = fmaxf(S1 - Sc1, 0.f);
+    S2 = fmaxf(S2 - Sc2, 0.f);
+    P = T > 0.f ? fminf(P / T, 1.f) : 0.f;
   }
   float X0 = P * cfg.bg[0], X1 = P * cfg.bg[1], X2 = P * cfg.bg[2];
   if (A > 0.f) {
@@ -319,8 +351,7 @@ __global__ void __launch_bounds__(TW *TH) k_raster_fwd(Ws w, ViewSet vs, KCfg cf
 #pragma unroll
     for (int i = 0; i < KMAX; ++i) {
       if (i < K) {
-        const int gid = cp[i] >= 0 ? (int)vals[rg.x + (uint32_t)cp[i]] : -1;
-        sp[(int64_t)i * npix] = __int_as_float(gid);
+        sp[(int64_t)i * npix] = __int_as_float(gids[i]);
         sp[(int64_t)(K + i) * npix] = ca[i];
         sp[(int64_t)(2 * K + i) * npix] = __int_as_float(cp[i]);
       }

@@ -4,13 +4,18 @@
 // One launch per 8-bit digit. Each workgroup takes a chunk of 4096 keys (in
 // ticket order), ranks them stably inside each 64-lane wave with ballots
 // (lanes whose digits match, counted below the lane), combines the four
-// waves in LDS, obtains the chunk's offset per digit by decoupled look-back
-// over earlier chunks, and scatters. The global digit histograms were
-// accumulated by the preprocess launch while it emitted the keys, so a pass
-// reads its keys and values once and writes them once.
+// waves in LDS, publishes its digit counts for the decoupled look-back over
+// earlier chunks, and reorders the chunk by digit in LDS. The look-back gives
+// each digit's global offset; the chunk then writes its LDS copy in order,
+// so consecutive lanes store consecutive addresses of one digit's run. The
+// global digit histograms were accumulated by the preprocess launch while it
+// emitted the keys, so a pass reads its keys and values once and writes them
+// once.
 #include "common.h"
 
 namespace htgs {
+
+constexpr int kSortWaves = kSortThreads / 64;
 
 template <typename KeyT>
 __global__ void __launch_bounds__(kSortThreads) k_sort_pass(Ws w, int pass, int nbits,
@@ -18,10 +23,14 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_pass(Ws w, int pass, int 
                                                              const uint32_t *__restrict__ vin,
                                                              KeyT *__restrict__ kout,
                                                              uint32_t *__restrict__ vout) {
-  __shared__ uint32_t s_wh[kSortThreads / 64][256];
-  __shared__ uint32_t s_base[256];
-  __shared__ uint32_t s_wsum[kSortThreads / 64];
+  static_assert(kSortThreads == 256, "one thread per digit");
+  __shared__ uint32_t s_wh[kSortWaves][256];  // per wave and digit: count, then local offset
+  __shared__ uint32_t s_off[256];             // global position of local slot 0, per digit
+  __shared__ uint32_t s_wsum[kSortWaves];
+  __shared__ uint32_t s_csum[kSortWaves];
   __shared__ uint32_t s_ticket;
+  __shared__ KeyT s_key[kSortChunk];
+  __shared__ uint32_t s_val[kSortChunk];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const unsigned long long tot = *w.total;
@@ -31,7 +40,7 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_pass(Ws w, int pass, int 
   const uint64_t I = tot;
   const uint64_t nchunks = (I + kSortChunk - 1) / kSortChunk;
   if (tid == 0) s_ticket = atomicAdd(&w.status[2 + pass], 1u);
-  for (int i = tid; i < (kSortThreads / 64) * 256; i += kSortThreads) (&s_wh[0][0])[i] = 0u;
+  for (int i = tid; i < kSortWaves * 256; i += kSortThreads) (&s_wh[0][0])[i] = 0u;
 
   // Exclusive scan of the global digit histogram of this pass.
   const uint32_t hv = w.hist[pass * 256 + tid];
@@ -50,7 +59,8 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_pass(Ws w, int pass, int 
   if (chunk >= nchunks) return;  // uniform over the workgroup
 
   const int shift = 8 * pass;
-  const uint64_t wbase = chunk * kSortChunk + (uint64_t)wave * (64 * kSortItems);
+  const uint64_t cbase = chunk * kSortChunk;
+  const uint64_t wbase = cbase + (uint64_t)wave * (64 * kSortItems);
   KeyT key[kSortItems];
   uint32_t val[kSortItems];
   uint32_t rank[kSortItems];
@@ -84,54 +94,93 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_pass(Ws w, int pass, int 
   }
   __syncthreads();
 
-  // Per digit: wave prefixes inside the chunk, then the chunk's offset.
-  {
-    const int d = tid;
-    uint32_t run = 0;
+  // Per digit (thread d): counts of the chunk, published at once for the
+  // successors' look-back; the local start of each digit is the exclusive
+  // scan of the counts over digits.
+  const int d = tid;
+  uint32_t cnt = 0;
 #pragma unroll
-    for (int k = 0; k < kSortThreads / 64; ++k) {
-      const uint32_t c = s_wh[k][d];
+  for (int k = 0; k < kSortWaves; ++k) cnt += s_wh[k][d];
+  uint32_t *look = w.sort_look + ((size_t)pass * (size_t)w.max_chunks) * 256;
+  st_rel_u32(&look[chunk * 256 + d], (chunk == 0 ? kFlagP32 : kFlagA32) | cnt);
+  uint32_t c = cnt;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(c, off, 64);
+    if (lane >= off) c += y;
+  }
+  if (lane == 63) s_csum[wave] = c;
+  __syncthreads();
+  uint32_t local_start = c - cnt;
+  for (int k = 0; k < wave; ++k) local_start += s_csum[k];
+  {
+    uint32_t run = local_start;
+#pragma unroll
+    for (int k = 0; k < kSortWaves; ++k) {
+      const uint32_t v = s_wh[k][d];
       s_wh[k][d] = run;
-      run += c;
+      run += v;
     }
-    uint32_t *look = w.sort_look + ((size_t)pass * (size_t)w.max_chunks) * 256;
-    uint32_t excl = 0;
-    if (chunk == 0) {
-      st_rel_u32(&look[d], kFlagP32 | run);
-    } else {
-      st_rel_u32(&look[chunk * 256 + d], kFlagA32 | run);
-      int64_t j = (int64_t)chunk - 1;
-      int spins = 0;
-      while (true) {
-        const uint32_t s = ld_acq_u32(&look[j * 256 + d]);
-        const uint32_t f = s >> 30;
-        if (f == 0) {
-          if (++spins > kSpinLimit) {
-            atomicOr(&w.status[0], (uint32_t)ST_SPIN);
-            break;
-          }
-          __builtin_amdgcn_s_sleep(1);
-          continue;
-        }
-        excl += s & kMask32;
-        if (f == 2) break;
-        --j;
-      }
-      st_rel_u32(&look[chunk * 256 + d], kFlagP32 | (excl + run));
-    }
-    s_base[d] = digit_excl + excl;
   }
   __syncthreads();
 
+  // Reorder the chunk by digit in LDS.
 #pragma unroll
   for (int i = 0; i < kSortItems; ++i) {
     const uint64_t idx = wbase + (uint64_t)i * 64 + lane;
     if (idx < I) {
-      const uint32_t d = ((uint32_t)key[i] >> shift) & 255u;
-      const uint32_t pos = s_base[d] + s_wh[wave][d] + rank[i];
-      kout[pos] = key[i];
-      vout[pos] = val[i];
+      const uint32_t dd = ((uint32_t)key[i] >> shift) & 255u;
+      const uint32_t lp = s_wh[wave][dd] + rank[i];
+      s_key[lp] = key[i];
+      s_val[lp] = val[i];
     }
+  }
+
+  // Look-back over earlier chunks for this digit's global offset, reading
+  // kLookWindow predecessors per round trip.
+  uint32_t excl = 0;
+  if (chunk > 0) {
+    int64_t j = (int64_t)chunk - 1;
+    int spins = 0;
+    while (true) {
+      uint32_t sv[kLookWindow];
+#pragma unroll
+      for (int k = 0; k < kLookWindow; ++k)
+        sv[k] = (j - k >= 0) ? ld_acq_u32(&look[(j - k) * 256 + d]) : 0u;
+      int used = 0;
+      bool done = false;
+#pragma unroll
+      for (int k = 0; k < kLookWindow; ++k) {
+        if (done || used < k) continue;      // stop at the first P or unpublished word
+        const uint32_t f = sv[k] >> 30;
+        if (f == 0) continue;
+        excl += sv[k] & kMask32;
+        used = k + 1;
+        done = (f == 2);
+      }
+      if (done) break;
+      j -= used;
+      if (used == 0) {
+        if (++spins > kSpinLimit) {
+          atomicOr(&w.status[0], (uint32_t)ST_SPIN);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+    st_rel_u32(&look[chunk * 256 + d], kFlagP32 | (excl + cnt));
+  }
+  // position of local slot p of digit d: digit_excl + excl + (p - local_start)
+  s_off[d] = digit_excl + excl - local_start;
+  __syncthreads();
+
+  const uint64_t left = I - cbase;
+  const int n_local = left < (uint64_t)kSortChunk ? (int)left : kSortChunk;
+  for (int p = tid; p < n_local; p += kSortThreads) {
+    const KeyT k = s_key[p];
+    const uint32_t pos = s_off[((uint32_t)k >> shift) & 255u] + (uint32_t)p;
+    kout[pos] = k;
+    vout[pos] = s_val[p];
   }
 }
 
