@@ -37,38 +37,6 @@ constexpr float kNegHalfLog2e = -0.72134752044448170368f;  // -1 / (2 ln 2)
 __device__ __forceinline__ float exp2_fast(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ float rcp_fast(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// Tile-local pixel coordinates and their products, read as scalars:
-// (lx, ly, lx^2, lx ly, ly^2, -, -, -) for tile pixel index ly * TW + lx.
-template <int TW, int TH>
-struct PixTable {
-  float v[TW * TH][8];
-};
-
-constexpr PixTable<16, 16> make_table16() {
-  PixTable<16, 16> t{};
-  for (int p = 0; p < 256; ++p) {
-    const float x = (float)(p % 16), y = (float)(p / 16);
-    t.v[p][0] = x; t.v[p][1] = y; t.v[p][2] = x * x; t.v[p][3] = x * y; t.v[p][4] = y * y;
-  }
-  return t;
-}
-constexpr PixTable<8, 8> make_table8() {
-  PixTable<8, 8> t{};
-  for (int p = 0; p < 64; ++p) {
-    const float x = (float)(p % 8), y = (float)(p / 8);
-    t.v[p][0] = x; t.v[p][1] = y; t.v[p][2] = x * x; t.v[p][3] = x * y; t.v[p][4] = y * y;
-  }
-  return t;
-}
-__constant__ PixTable<16, 16> kPix16 = make_table16();
-__constant__ PixTable<8, 8> kPix8 = make_table8();
-
-template <int TW>
-__device__ __forceinline__ const float *pix_entry(int p) {
-  if constexpr (TW == 16) return kPix16.v[p];
-  else return kPix8.v[p];
-}
-
 // Tile-centred staged record: d = D0t + lx Du + ly Dv with (lx, ly) the
 // pixel's integer offset from the tile's first pixel.
 __device__ __forceinline__ void stage_record(const float *__restrict__ rec, int px0, int py0,
@@ -108,18 +76,15 @@ __device__ __forceinline__ void eval_ray(const float *st, float lx, float ly, fl
   mm = fmaf(m[2], m[2], fmaf(m[1], m[1], m[0] * m[0]));
 }
 
+// alpha = min(alpha_max, o exp(-rho^2 / 2)) with rho^2 = mm / dd.
+__device__ __forceinline__ float frag_alpha(float o, float mm, float inv, float amax) {
+  return fminf(amax, o * exp2_fast((mm * inv) * kNegHalfLog2e));
+}
+
 __device__ __forceinline__ bool is_fragment(float dd, float mm, float rc) {
   return (dd >= FLT_MIN) && (mm <= rc * dd);
 }
 
-__device__ __forceinline__ float max_point_depth(const float *st, const float d[3], const float m[3],
-                                                 float inv) {
-  const float c0 = fmaf(d[1], m[2], -d[2] * m[1]);
-  const float c1 = fmaf(d[2], m[0], -d[0] * m[2]);
-  const float c2 = fmaf(d[0], m[1], -d[1] * m[0]);
-  const float r = fmaf(st[S_R3 + 2], c2, fmaf(st[S_R3 + 1], c1, st[S_R3] * c0));
-  return fmaf(r, inv, st[S_MUZ]);
-}
 
 __device__ __forceinline__ void load_record(const float *__restrict__ recs, uint32_t gid, float *rec) {
   const float4 *r4 = reinterpret_cast<const float4 *>(recs + (int64_t)gid * kRecFloats);
@@ -187,15 +152,17 @@ __global__ void __launch_bounds__(TW *TH) k_raster_fwd(Ws w, ViewSet vs, KCfg cf
   const float *recs = w.records + (int64_t)ti.v * cfg.n * kRecFloats;
   const uint64_t lanemask_lt = (1ull << lane) - 1ull;
 
-  // Core: depth, alpha and list position of up to K fragments, sorted by
-  // depth (ties keep list order). Every fragment is added to the running
-  // sums (alpha, alpha rgb, prod 1 - alpha); the core members are taken out
-  // of them once the list is done, which leaves exactly the tail sums.
-  float cz[KMAX], ca[KMAX];
+  // Core: depth and list position of up to K fragments, sorted by depth
+  // (ties keep list order). Every fragment is added to the running sums
+  // (alpha, alpha rgb, prod 1 - alpha); once the list is done the core
+  // members' alphas are recomputed from their records (same arithmetic, so
+  // the same values) and taken out of the sums, which leaves exactly the
+  // tail sums.
+  float cz[KMAX];
   int cp[KMAX];
 #pragma unroll
   for (int i = 0; i < KMAX; ++i) {
-    cz[i] = INFINITY; ca[i] = 0.f; cp[i] = -1;
+    cz[i] = INFINITY; cp[i] = -1;
   }
   float zlast = INFINITY;
   float A = 0.f, S0 = 0.f, S1 = 0.f, S2 = 0.f, P = 1.f;
@@ -239,33 +206,42 @@ __global__ void __launch_bounds__(TW *TH) k_raster_fwd(Ws w, ViewSet vs, KCfg cf
       __builtin_amdgcn_wave_barrier();
     }
     if (!inside) continue;
-    for (int q = 0; q < nlist; ++q) {
-      int j = q;
-      if constexpr (NW > 1) j = s_list[wave][q];
-      float st[28];
+    // One staged splat per step; the ray-test part of the next one is read
+    // from LDS while this one is evaluated (two register buffers).
+    auto stage_index = [&](int q) -> int {
+      if constexpr (NW > 1) return s_list[wave][q];
+      else return q;
+    };
+    auto fetch = [&](int j, float *e) {
 #pragma unroll
-      for (int k = 0; k < 7; ++k) {
+      for (int k = 0; k < S_EVAL4; ++k) {
         const float4 t = s_stage[j * SV + k];
-        st[4 * k] = t.x; st[4 * k + 1] = t.y; st[4 * k + 2] = t.z; st[4 * k + 3] = t.w;
+        e[4 * k] = t.x; e[4 * k + 1] = t.y; e[4 * k + 2] = t.z; e[4 * k + 3] = t.w;
       }
+    };
+    auto step = [&](int j, const float *e) {
       float d[3], m[3], dd, mm;
-      eval_ray(st, flx, fly, d, m, dd, mm);
-      if (!is_fragment(dd, mm, st[S_RC])) continue;
+      eval_ray(e, flx, fly, d, m, dd, mm);
+      if (!is_fragment(dd, mm, e[S_RC])) return;
       ++nfrag;
       const float inv = rcp_fast(dd);
-      const float r2 = mm * inv;
-      const float alpha = fminf(amax, st[S_O] * exp2_fast(r2 * kNegHalfLog2e));
+      const float alpha = frag_alpha(e[S_O], mm, inv, amax);
+      const float4 f0 = s_stage[j * SV + S_R3 / 4];    // R3, depth of the mean
+      const float4 f1 = s_stage[j * SV + S_RGB / 4];   // rgb, list position
       A += alpha;
-      S0 = fmaf(alpha, st[S_RGB], S0);
-      S1 = fmaf(alpha, st[S_RGB + 1], S1);
-      S2 = fmaf(alpha, st[S_RGB + 2], S2);
+      S0 = fmaf(alpha, f1.x, S0);
+      S1 = fmaf(alpha, f1.y, S1);
+      S2 = fmaf(alpha, f1.z, S2);
       P *= 1.f - alpha;
       if (alpha >= tau_core && K > 0) {
-        const float z = max_point_depth(st, d, m, inv);
+        const float r = fmaf(f0.z, fmaf(d[0], m[1], -d[1] * m[0]),
+                             fmaf(f0.y, fmaf(d[2], m[0], -d[0] * m[2]),
+                                  f0.x * fmaf(d[1], m[2], -d[2] * m[1])));
+        const float z = fmaf(r, inv, f0.w);
         if (z < zlast) {
           // Insert at the first entry deeper than z; the entries from there
           // on move back by one and the last one drops out of the core.
-          const int pos = (int)__float_as_uint(st[S_POS]);
+          const int pos = (int)__float_as_uint(f1.w);
           bool c[KMAX];
 #pragma unroll
           for (int i = 0; i < KMAX; ++i) c[i] = z < cz[i];
@@ -274,11 +250,9 @@ __global__ void __launch_bounds__(TW *TH) k_raster_fwd(Ws w, ViewSet vs, KCfg cf
 #pragma unroll
           for (int i = KMAX - 1; i >= 1; --i) {
             cz[i] = c[i - 1] ? cz[i - 1] : (c[i] ? z : cz[i]);
-            ca[i] = c[i - 1] ? ca[i - 1] : (c[i] ? alpha : ca[i]);
             cp[i] = c[i - 1] ? cp[i - 1] : (c[i] ? pos : cp[i]);
           }
           cz[0] = c[0] ? z : cz[0];
-          ca[0] = c[0] ? alpha : ca[0];
           cp[0] = c[0] ? pos : cp[0];
           if (K == KMAX) {
             zlast = cz[KMAX - 1];
@@ -289,6 +263,18 @@ __global__ void __launch_bounds__(TW *TH) k_raster_fwd(Ws w, ViewSet vs, KCfg cf
           }
         }
       }
+    };
+    float ea[4 * S_EVAL4], eb[4 * S_EVAL4];
+    if (nlist > 0) fetch(stage_index(0), ea);
+    for (int q = 0; q < nlist; q += 2) {
+      const int ja = stage_index(q);
+      const bool has_b = q + 1 < nlist;
+      const int jb = has_b ? stage_index(q + 1) : 0;
+      if (has_b) fetch(jb, eb);
+      step(ja, ea);
+      if (!has_b) break;
+      if (q + 2 < nlist) fetch(stage_index(q + 2), ea);
+      step(jb, eb);
     }
   }
   __syncthreads();
@@ -303,14 +289,23 @@ __global__ void __launch_bounds__(TW *TH) k_raster_fwd(Ws w, ViewSet vs, KCfg cf
   float Ac = 0.f, Sc0 = 0.f, Sc1 = 0.f, Sc2 = 0.f;
   uint32_t ncore = 0;
   int gids[KMAX];
+  float ca[KMAX];
 #pragma unroll
   for (int i = 0; i < KMAX; ++i) {
     gids[i] = -1;
+    ca[i] = 0.f;
     if (i < K && cp[i] >= 0) {
       const uint32_t gid = vals[rg.x + (uint32_t)cp[i]];
       gids[i] = (int)gid;
-      const float4 c = *reinterpret_cast<const float4 *>(recs + (int64_t)gid * kRecFloats + R_RGB);
-      const float a = ca[i];
+      float rec[kRecFloats];
+      load_record(recs, gid, rec);
+      float st[S_FLOATS];
+      stage_record(rec, px0, py0, (uint32_t)cp[i], st);
+      float d[3], m[3], dd, mm;
+      eval_ray(st, flx, fly, d, m, dd, mm);
+      const float a = frag_alpha(st[S_O], mm, rcp_fast(dd), amax);
+      ca[i] = a;
+      const float4 c = make_float4(st[S_RGB], st[S_RGB + 1], st[S_RGB + 2], 0.f);
       const float wgt = a * T;
       C0 = fmaf(wgt, c.x, C0);
       C1 = fmaf(wgt, c.y, C1);
@@ -378,33 +373,27 @@ struct PixLayout {
 };
 
 // Gradient contribution of one fragment (lane's splat at pixel Pp) to the
-// lane's moment accumulators.
+// lane's moment accumulators. cslot is the fragment's core index at this
+// pixel, or -1 for a tail fragment.
 template <int KMAX>
 __device__ __forceinline__ void bwd_fragment(const float *st, const float *Pp, const float *tab,
-                                             const float d[3], const float m[3], float dd,
-                                             float mm, int ncore, const uint16_t *ent, int lane,
-                                             float amax, float *acc) {
+                                             float dd, float mm, int cslot, float amax,
+                                             float *acc) {
   using L = PixLayout<KMAX>;
-  int cslot = -1;
-  for (int e = 0; e < ncore; ++e) {
-    const uint32_t en = ent[e];
-    if ((int)(en & 255u) == lane) cslot = (int)(en >> 8);
-  }
   const float inv = rcp_fast(dd);
   const float r2 = mm * inv;
   const float e = exp2_fast(r2 * kNegHalfLog2e);
   const float araw = st[S_O] * e;
   const float alpha = fminf(amax, araw);
   const float G0 = Pp[0], G1 = Pp[1], G2 = Pp[2], w1 = Pp[3];
-  float dLda, wc;
-  if (cslot >= 0) {
-    dLda = Pp[L::kCoef + cslot];
-    wc = alpha * Pp[L::kT + cslot];
-  } else {
-    const float gdc = fmaf(G2, st[S_RGB + 2], fmaf(G1, st[S_RGB + 1], G0 * st[S_RGB]));
-    dLda = fmaf(w1, gdc, -Pp[4]) - Pp[5] * rcp_fast(1.f - alpha);
-    wc = w1 * alpha;
-  }
+  // tail: dC/dalpha = w1 (c - c_tail) - T P (c_bg - c_tail) / (1 - alpha),
+  // dC/dc = w1 alpha; core: the pixel's precomputed T_i (c_i - B_i) and T_i
+  const float gdc = fmaf(G2, st[S_RGB + 2], fmaf(G1, st[S_RGB + 1], G0 * st[S_RGB]));
+  const float tail = fmaf(w1, gdc, -Pp[4]) - Pp[5] * rcp_fast(1.f - alpha);
+  const bool core = cslot >= 0;
+  const int ci = core ? cslot : 0;
+  const float dLda = core ? Pp[L::kCoef + ci] : tail;
+  const float wc = alpha * (core ? Pp[L::kT + ci] : w1);
   acc[13] = fmaf(wc, G0, acc[13]);
   acc[14] = fmaf(wc, G1, acc[14]);
   acc[15] = fmaf(wc, G2, acc[15]);
@@ -428,7 +417,7 @@ __device__ __forceinline__ void bwd_fragment(const float *st, const float *Pp, c
 }
 
 template <int KMAX, int TW, int TH>
-__global__ void __launch_bounds__(256) k_raster_bwd(Ws w, ViewSet vs, KCfg cfg,
+__global__ void __launch_bounds__(256, (TW == 8 && KMAX <= 8) ? 5 : ((TW == 8 && KMAX <= 16) ? 4 : 1)) k_raster_bwd(Ws w, ViewSet vs, KCfg cfg,
                                                     const float *__restrict__ state,
                                                     const uint32_t *__restrict__ vals) {
   constexpr int NT = TW * TH;
@@ -436,8 +425,9 @@ __global__ void __launch_bounds__(256) k_raster_bwd(Ws w, ViewSet vs, KCfg cfg,
   constexpr int BX = TW / 8;
   using L = PixLayout<KMAX>;
   __shared__ float4 s_pix[NT * L::kStride / 4];
-  __shared__ uint8_t s_cnt[4][NT];
-  __shared__ uint16_t s_ent[4][NT][KMAX];
+  // per wave, for the 8x8 block being walked: [block pixel][lane] = core
+  // index + 1 of the lane's instance at that pixel, 0 if not in the core
+  __shared__ uint8_t s_slot[4][64][64];
 
   TileInfo ti;
   if (!tile_info(vs, cfg, w, ti)) return;
@@ -554,26 +544,6 @@ __global__ void __launch_bounds__(256) k_raster_bwd(Ws w, ViewSet vs, KCfg cfg,
       const int4 r = w.rects[(int64_t)ti.v * cfg.n + gid];
       slot = w.offsets[gid] + pre + (uint32_t)((ti.ty - r.y) * (r.z - r.x + 1) + (ti.tx - r.x));
     }
-    // Core members of each pixel that belong to this chunk: (lane, slot).
-    for (int q = 0; q < NB; ++q) {
-      const int p = q * 64 + lane;
-      const float *Pp = sp_all + p * L::kStride;
-      uint32_t n = 0;
-#pragma unroll
-      for (int i = 0; i < KMAX; ++i) {
-        if (i < K) {
-          const int ps = __float_as_int(Pp[L::kPos + i]);
-          const uint32_t dl = (uint32_t)(ps - (int)(c * 64u));
-          if (ps >= 0 && dl < 64u) {
-            s_ent[wave][p][n] = (uint16_t)(dl | ((uint32_t)i << 8));
-            ++n;
-          }
-        }
-      }
-      s_cnt[wave][p] = (uint8_t)n;
-    }
-    __builtin_amdgcn_wave_barrier();
-
     // acc: d-moments (6), m-moments (6), dL/do, dL/drgb (3)
     float acc[16];
 #pragma unroll
@@ -582,22 +552,49 @@ __global__ void __launch_bounds__(256) k_raster_bwd(Ws w, ViewSet vs, KCfg cfg,
       const int bx = (blk % BX) * 8, by = (blk / BX) * 8;
       const bool hitb = active && rect_meets_block(st + S_BB0, bx, by);
       if (__ballot(hitb) == 0ull) continue;
-      // Two pixels per iteration: the pair tests are independent.
-      for (int q = 0; q < 64; q += 2) {
-        const int p0 = (by + (q >> 3)) * TW + bx + (q & 7);
-        const int p1 = p0 + 1;
-        const float *tab0 = pix_entry<TW>(p0);
-        const float *tab1 = pix_entry<TW>(p1);
-        float d0[3], m0[3], dd0, mm0, d1[3], m1[3], dd1, mm1;
-        eval_ray(st, tab0[0], tab0[1], d0, m0, dd0, mm0);
-        eval_ray(st, tab1[0], tab1[1], d1, m1, dd1, mm1);
-        const bool f0 = hitb && is_fragment(dd0, mm0, st[S_RC]);
-        const bool f1 = hitb && is_fragment(dd1, mm1, st[S_RC]);
-        if (f0) bwd_fragment<KMAX>(st, sp_all + p0 * L::kStride, tab0, d0, m0, dd0, mm0,
-                                   s_cnt[wave][p0], s_ent[wave][p0], lane, amax, acc);
-        if (f1) bwd_fragment<KMAX>(st, sp_all + p1 * L::kStride, tab1, d1, m1, dd1, mm1,
-                                   s_cnt[wave][p1], s_ent[wave][p1], lane, amax, acc);
+      // Core table of this block for this chunk: lane = block pixel.
+      {
+        const int p = (by + (lane >> 3)) * TW + bx + (lane & 7);
+        const float *Pp = sp_all + p * L::kStride;
+        uint32_t *row = reinterpret_cast<uint32_t *>(&s_slot[wave][lane][0]);
+#pragma unroll
+        for (int k = 0; k < 16; ++k) row[k] = 0u;
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int i = 0; i < KMAX; ++i) {
+          if (i < K) {
+            const int ps = __float_as_int(Pp[L::kPos + i]);
+            const uint32_t dl = (uint32_t)(ps - (int)(c * 64u));
+            if (ps >= 0 && dl < 64u) s_slot[wave][lane][dl] = (uint8_t)(i + 1);
+          }
+        }
+        __builtin_amdgcn_wave_barrier();
       }
+      // Tile-local pixel coordinates (lx, ly, lx^2, lx ly, ly^2) are
+      // wave-uniform; the columns are unrolled so that they are constants
+      // for 8x8 tiles. Two pixels per step: the pair tests are independent.
+      for (int row = 0; row < 8; ++row) {
+        const float ly = (float)(by + row), ly2 = ly * ly;
+#pragma unroll
+        for (int col = 0; col < 8; col += 2) {
+          const int q = row * 8 + col;
+          const int p0 = (by + row) * TW + bx + col;
+          const int p1 = p0 + 1;
+          const float lx0 = (float)(bx + col), lx1 = (float)(bx + col + 1);
+          const float tab0[5] = {lx0, ly, lx0 * lx0, lx0 * ly, ly2};
+          const float tab1[5] = {lx1, ly, lx1 * lx1, lx1 * ly, ly2};
+          float d0[3], m0[3], dd0, mm0, d1[3], m1[3], dd1, mm1;
+          eval_ray(st, lx0, ly, d0, m0, dd0, mm0);
+          eval_ray(st, lx1, ly, d1, m1, dd1, mm1);
+          const bool f0 = hitb && is_fragment(dd0, mm0, st[S_RC]);
+          const bool f1 = hitb && is_fragment(dd1, mm1, st[S_RC]);
+          if (f0) bwd_fragment<KMAX>(st, sp_all + p0 * L::kStride, tab0, dd0, mm0,
+                                     (int)s_slot[wave][q][lane] - 1, amax, acc);
+          if (f1) bwd_fragment<KMAX>(st, sp_all + p1 * L::kStride, tab1, dd1, mm1,
+                                     (int)s_slot[wave][q + 1][lane] - 1, amax, acc);
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
     }
     if (active && (uint64_t)slot < (uint64_t)w.capacity) {
       // Gradients of the record coefficients in camera coordinates
