@@ -27,10 +27,10 @@ enum RecField {
   R_O = 22,     // opacity
   R_RC = 23,    // rho_c (squared cutoff radius)
   R_RGB = 24,   // colour (3)
-  R_IX = 27, R_IY = 28,  // reference pixel, int32 bit patterns
-  R_BB0 = 29,   // covered pixel rect: x0 | y0 << 16
-  R_BB1 = 30,   //                     x1 | y1 << 16 (inclusive)
-  R_FLAGS = 31  // bit c set: colour channel c was clamped at 0
+  R_FLAGS = 27, // bit c set: colour channel c was clamped at 0
+  R_IX = 28, R_IY = 29,  // reference pixel, int32 bit patterns
+  R_BB0 = 30,   // covered pixel rect: x0 | y0 << 16
+  R_BB1 = 31    //                     x1 | y1 << 16 (inclusive)
 };
 
 // Per-instance backward partials: the gradient of the loss w.r.t. the

@@ -116,6 +116,7 @@ __device__ inline double dot3(const double a[3], const double b[3]) {
 // One Gaussian in one view: cull, box, rect, record. Returns the instance
 // count and writes the tile rect (and the record if the count is non-zero);
 // *packed receives tx0 | ty0 << 10 | width << 20 of a non-empty rect.
+template <int DEG>
 __device__ inline uint32_t preprocess_view(const GaussPtrs &gp, const KCfg &cfg,
                                            const ViewParams &V, const Ws &w, int v,
                                            int64_t g, const Activated &a, uint32_t *packed) {
@@ -171,7 +172,9 @@ __device__ inline uint32_t preprocess_view(const GaussPtrs &gp, const KCfg &cfg,
   cross3(Rv[0], Rv[1], D0);
   cross3(Rv[1], Rv[2], Du);
   cross3(Rv[2], Rv[0], Dv);
-  float rec[kRecFloats];
+  // The geometric part of the record is stored first so that its registers
+  // are free before the colour is evaluated.
+  float rec[24];
   for (int k = 0; k < 3; ++k) {
     const double M0 = mv[0] * Rv[1][k] - mv[1] * Rv[0][k];
     const double Mu = mv[1] * Rv[2][k] - mv[2] * Rv[1][k];
@@ -187,34 +190,48 @@ __device__ inline uint32_t preprocess_view(const GaussPtrs &gp, const KCfg &cfg,
   rec[R_MUZ] = (float)mv[2];
   rec[R_O] = (float)a.o;
   rec[R_RC] = (float)rc;
-  rec[R_IX] = __int_as_float((int)ixd);
-  rec[R_IY] = __int_as_float((int)iyd);
-  rec[R_BB0] = __uint_as_float((uint32_t)x0 | ((uint32_t)y0 << 16));
-  rec[R_BB1] = __uint_as_float((uint32_t)x1 | ((uint32_t)y1 << 16));
+  float4 *dst = reinterpret_cast<float4 *>(w.records + ((int64_t)v * cfg.n + g) * kRecFloats);
+#pragma unroll
+  for (int k = 0; k < 6; ++k)
+    dst[k] = make_float4(rec[4 * k], rec[4 * k + 1], rec[4 * k + 2], rec[4 * k + 3]);
+  dst[R_IX / 4] = make_float4(__int_as_float((int)ixd), __int_as_float((int)iyd),
+                              __uint_as_float((uint32_t)x0 | ((uint32_t)y0 << 16)),
+                              __uint_as_float((uint32_t)x1 | ((uint32_t)y1 << 16)));
 
   // View-dependent colour (Sec. 3.1; 3DGS convention).
   double dv[3] = {a.mu[0] - V.cam_pos[0], a.mu[1] - V.cam_pos[1], a.mu[2] - V.cam_pos[2]};
   const double dn = sqrt(dot3(dv, dv));
+  constexpr int NB = (DEG + 1) * (DEG + 1), NF = 3 * NB;
   float Y[16];
-  sh_basis<float>((float)(dv[0] / dn), (float)(dv[1] / dn), (float)(dv[2] / dn), cfg.sh_degree,
-                  Y);
-  const int nb = (cfg.sh_degree + 1) * (cfg.sh_degree + 1);
-  const float *sh = gp.sh + g * nb * 3;
+  sh_basis<float>((float)(dv[0] / dn), (float)(dv[1] / dn), (float)(dv[2] / dn), DEG, Y);
+  // the Gaussian's coefficients, 16-byte loads where the row is a multiple
+  // of 16 bytes (degrees 1 and 3)
+  float coef[NF];
+  if constexpr (NF % 4 == 0) {
+    const float4 *s4 = reinterpret_cast<const float4 *>(gp.sh + g * NF);
+#pragma unroll
+    for (int i = 0; i < NF / 4; ++i) {
+      const float4 t = s4[i];
+      coef[4 * i] = t.x; coef[4 * i + 1] = t.y; coef[4 * i + 2] = t.z; coef[4 * i + 3] = t.w;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < NF; ++i) coef[i] = gp.sh[g * NF + i];
+  }
   uint32_t flags = 0;
+  float col[3];
+#pragma unroll
   for (int c = 0; c < 3; ++c) {
     float acc = 0.5f;
-    for (int k = 0; k < nb; ++k) acc = fmaf(Y[k], sh[3 * k + c], acc);
+#pragma unroll
+    for (int k = 0; k < NB; ++k) acc = fmaf(Y[k], coef[3 * k + c], acc);
     if (acc < 0.0f) {
       flags |= 1u << c;
       acc = 0.0f;
     }
-    rec[R_RGB + c] = acc;
+    col[c] = acc;
   }
-  rec[R_FLAGS] = __uint_as_float(flags);
-  float4 *dst = reinterpret_cast<float4 *>(w.records + ((int64_t)v * cfg.n + g) * kRecFloats);
-#pragma unroll
-  for (int k = 0; k < kRecFloats / 4; ++k)
-    dst[k] = make_float4(rec[4 * k], rec[4 * k + 1], rec[4 * k + 2], rec[4 * k + 3]);
+  dst[R_RGB / 4] = make_float4(col[0], col[1], col[2], __uint_as_float(flags));
   return count;
 }
 
@@ -224,6 +241,8 @@ __global__ void __launch_bounds__(256) k_fill_zero(uint4 *p, int64_t n16) {
     p[i] = make_uint4(0u, 0u, 0u, 0u);
 }
 
+// MV: more than one view (a single view keeps far fewer values live).
+template <int DEG, bool MV>
 __global__ void __launch_bounds__(kPreThreads) k_preprocess(GaussPtrs gp, KCfg cfg, ViewSet vs,
                                                              Ws w) {
   __shared__ uint32_t s_ticket;
@@ -240,20 +259,21 @@ __global__ void __launch_bounds__(kPreThreads) k_preprocess(GaussPtrs gp, KCfg c
   __syncthreads();
   const int64_t blk = s_ticket;
   const int64_t g = blk * kPreThreads + tid;
+  const int nviews = MV ? vs.n : 1;
 
   uint32_t total = 0;
   if (g < cfg.n) {
     Activated a;
     activate(gp, g, a);
-    for (int v = 0; v < vs.n; ++v) {
+    for (int v = 0; v < nviews; ++v) {
       uint32_t packed = 0;
-      const uint32_t c = preprocess_view(gp, cfg, vs.v[v], w, v, g, a, &packed);
+      const uint32_t c = preprocess_view<DEG>(gp, cfg, vs.v[v], w, v, g, a, &packed);
       s_vcnt[v][tid] = c;
       s_vrect[v][tid] = packed;
       total += c;
     }
   } else {
-    for (int v = 0; v < vs.n; ++v) s_vcnt[v][tid] = 0u;
+    for (int v = 0; v < nviews; ++v) s_vcnt[v][tid] = 0u;
   }
 
   // Workgroup exclusive scan of the counts.
@@ -334,9 +354,11 @@ __global__ void __launch_bounds__(kPreThreads) k_preprocess(GaussPtrs gp, KCfg c
     }
     uint32_t rank = e - s_excl[lo];
     int v = 0;
-    while (rank >= s_vcnt[v][lo]) {
-      rank -= s_vcnt[v][lo];
-      ++v;
+    if constexpr (MV) {
+      while (rank >= s_vcnt[v][lo]) {
+        rank -= s_vcnt[v][lo];
+        ++v;
+      }
     }
     const int64_t gi = blk * kPreThreads + lo;
     const uint32_t pr = s_vrect[v][lo];
@@ -375,6 +397,23 @@ __device__ inline void rot_grad_to_quat(const double qn[4], const double gR[3][3
                y * gR[1][2] + x * gR[2][0] + y * gR[2][1]);
 }
 
+// One step of the wave-wide segmented inclusive scan of the 22 partial
+// values: lanes enabled by ROW_MASK take the DPP-moved value (CTRL) when
+// the source lane holds the same segment id. Lanes with no source lane keep
+// the complement of their own id, which never matches.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ void seg_scan_step(uint32_t seg, float *v) {
+  const uint32_t src = (uint32_t)__builtin_amdgcn_update_dpp((int)~seg, (int)seg, CTRL, ROW_MASK,
+                                                             0xf, false);
+  const bool take = src == seg;
+#pragma unroll
+  for (int k = 0; k < 22; ++k) {
+    const float y = __int_as_float(
+        __builtin_amdgcn_update_dpp(0, __float_as_int(v[k]), CTRL, ROW_MASK, 0xf, false));
+    v[k] += take ? y : 0.f;
+  }
+}
+
 // In-place segmented reduction of the per-instance partials. Slots are
 // processed in 64-aligned blocks, one lane each; a segment is the run of
 // slots of one (Gaussian, view). After the launch, the last slot of every
@@ -404,16 +443,17 @@ __global__ void __launch_bounds__(256) k_segment_reduce(Ws w) {
 #pragma unroll
     for (int k = 0; k < 22; ++k) v[k] = 0.f;
   }
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const uint32_t so = __shfl_up(seg, off, 64);
-    const bool take = (lane >= off) && (so == seg);
-#pragma unroll
-    for (int k = 0; k < 22; ++k) {
-      const float y = __shfl_up(v[k], off, 64);
-      if (take) v[k] += y;
-    }
-  }
+  // Inclusive segmented scan over the wave with DPP lane moves (no LDS):
+  // shifts by 1, 2, 4, 8 inside each row of 16 lanes, then the last lane of
+  // row 0 / row 2 into rows 1 / 3, then lane 31 into rows 2 and 3. A lane
+  // adds the moved value only if it comes from its own segment (segments
+  // are runs of consecutive slots, so equal ids mean one run).
+  seg_scan_step<0x111, 0xf>(seg, v);   // row_shr:1
+  seg_scan_step<0x112, 0xf>(seg, v);   // row_shr:2
+  seg_scan_step<0x114, 0xf>(seg, v);   // row_shr:4
+  seg_scan_step<0x118, 0xf>(seg, v);   // row_shr:8
+  seg_scan_step<0x142, 0xa>(seg, v);   // row_bcast:15 into rows 1, 3
+  seg_scan_step<0x143, 0xc>(seg, v);   // row_bcast:31 into rows 2, 3
   const uint32_t sn = __shfl_down(seg, 1, 64);
   const bool end = valid && (lane == 63 || sn != seg || s + 1 == tot);
   if (end) {
@@ -617,7 +657,22 @@ hipError_t launch_preprocess(const GaussPtrs &gp, const KCfg &cfg, const ViewSet
                              hipStream_t s) {
   if (cfg.n == 0) return hipSuccess;
   const int blocks = (int)((cfg.n + kPreThreads - 1) / kPreThreads);
-  hipLaunchKernelGGL(k_preprocess, dim3(blocks), dim3(kPreThreads), 0, s, gp, cfg, vs, w);
+#define HTGS_PRE(D)                                                                      \
+  do {                                                                                   \
+    if (vs.n > 1)                                                                        \
+      hipLaunchKernelGGL((k_preprocess<D, true>), dim3(blocks), dim3(kPreThreads), 0, s, gp, \
+                         cfg, vs, w);                                                    \
+    else                                                                                 \
+      hipLaunchKernelGGL((k_preprocess<D, false>), dim3(blocks), dim3(kPreThreads), 0, s,    \
+                         gp, cfg, vs, w);                                                \
+  } while (0)
+  switch (cfg.sh_degree) {
+    case 0: HTGS_PRE(0); break;
+    case 1: HTGS_PRE(1); break;
+    case 2: HTGS_PRE(2); break;
+    default: HTGS_PRE(3); break;
+  }
+#undef HTGS_PRE
   return hipGetLastError();
 }
 

@@ -65,12 +65,14 @@ __device__ __forceinline__ void stage_record(const float *__restrict__ rec, int 
   st[S_BB3] = __int_as_float((int)(b1 >> 16) - py0);
 }
 
+// d and m at tile pixel offset (lx, ly); the row term is added first, so a
+// kernel that walks a row can hoist it (same rounding).
 __device__ __forceinline__ void eval_ray(const float *st, float lx, float ly, float d[3], float m[3],
                                          float &dd, float &mm) {
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    d[k] = fmaf(ly, st[S_DV + k], fmaf(lx, st[S_DU + k], st[S_D0 + k]));
-    m[k] = fmaf(ly, st[S_MV + k], fmaf(lx, st[S_MU + k], st[S_M0 + k]));
+    d[k] = fmaf(lx, st[S_DU + k], fmaf(ly, st[S_DV + k], st[S_D0 + k]));
+    m[k] = fmaf(lx, st[S_MU + k], fmaf(ly, st[S_MV + k], st[S_M0 + k]));
   }
   dd = fmaf(d[2], d[2], fmaf(d[1], d[1], d[0] * d[0]));
   mm = fmaf(m[2], m[2], fmaf(m[1], m[1], m[0] * m[0]));
@@ -372,13 +374,14 @@ struct PixLayout {
   static constexpr int kStride = ((8 + 3 * KMAX) + 3) / 4 * 4;
 };
 
-// Gradient contribution of one fragment (lane's splat at pixel Pp) to the
-// lane's moment accumulators. cslot is the fragment's core index at this
-// pixel, or -1 for a tail fragment.
+// Gradient contribution of one fragment (lane's splat at pixel Pp, tile
+// column lx) to the lane's accumulators. cslot is the fragment's core index
+// at this pixel, or -1 for a tail fragment. rs holds this row's sums of the
+// d and m weights times (1, lx, lx^2).
 template <int KMAX>
-__device__ __forceinline__ void bwd_fragment(const float *st, const float *Pp, const float *tab,
+__device__ __forceinline__ void bwd_fragment(const float *st, const float *Pp, float lx,
                                              float dd, float mm, int cslot, float amax,
-                                             float *acc) {
+                                             float *rs, float *acc) {
   using L = PixLayout<KMAX>;
   const float inv = rcp_fast(dd);
   const float r2 = mm * inv;
@@ -401,18 +404,13 @@ __device__ __forceinline__ void bwd_fragment(const float *st, const float *Pp, c
     acc[12] = fmaf(dLda, e, acc[12]);
     const float s1 = -alpha * dLda * inv;   // weight of m: 2 dL/drho^2 / |d|^2
     const float s2 = -s1 * r2;              // weight of d
-    acc[0] += s2;
-    acc[1] = fmaf(tab[0], s2, acc[1]);
-    acc[2] = fmaf(tab[1], s2, acc[2]);
-    acc[3] = fmaf(tab[2], s2, acc[3]);
-    acc[4] = fmaf(tab[3], s2, acc[4]);
-    acc[5] = fmaf(tab[4], s2, acc[5]);
-    acc[6] += s1;
-    acc[7] = fmaf(tab[0], s1, acc[7]);
-    acc[8] = fmaf(tab[1], s1, acc[8]);
-    acc[9] = fmaf(tab[2], s1, acc[9]);
-    acc[10] = fmaf(tab[3], s1, acc[10]);
-    acc[11] = fmaf(tab[4], s1, acc[11]);
+    const float lx2 = lx * lx;
+    rs[0] += s2;
+    rs[1] = fmaf(lx, s2, rs[1]);
+    rs[2] = fmaf(lx2, s2, rs[2]);
+    rs[3] += s1;
+    rs[4] = fmaf(lx, s1, rs[4]);
+    rs[5] = fmaf(lx2, s1, rs[5]);
   }
 }
 
@@ -570,29 +568,57 @@ __global__ void __launch_bounds__(256, (TW == 8 && KMAX <= 8) ? 5 : ((TW == 8 &&
         }
         __builtin_amdgcn_wave_barrier();
       }
-      // Tile-local pixel coordinates (lx, ly, lx^2, lx ly, ly^2) are
-      // wave-uniform; the columns are unrolled so that they are constants
-      // for 8x8 tiles. Two pixels per step: the pair tests are independent.
+      // A row at a time: d and m along the row are (row base) + lx (Du, Mu),
+      // and the moments (1, lx, ly, lx^2, lx ly, ly^2) of the weights follow
+      // from per-row sums over (1, lx, lx^2). The columns are unrolled, so
+      // lx is a constant for 8x8 tiles; two pixels per step.
       for (int row = 0; row < 8; ++row) {
-        const float ly = (float)(by + row), ly2 = ly * ly;
+        const float ly = (float)(by + row);
+        float db[3], mb[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          db[k] = fmaf(ly, st[S_DV + k], st[S_D0 + k]);
+          mb[k] = fmaf(ly, st[S_MV + k], st[S_M0 + k]);
+        }
+        float rs[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int col = 0; col < 8; col += 2) {
           const int q = row * 8 + col;
           const int p0 = (by + row) * TW + bx + col;
           const int p1 = p0 + 1;
           const float lx0 = (float)(bx + col), lx1 = (float)(bx + col + 1);
-          const float tab0[5] = {lx0, ly, lx0 * lx0, lx0 * ly, ly2};
-          const float tab1[5] = {lx1, ly, lx1 * lx1, lx1 * ly, ly2};
-          float d0[3], m0[3], dd0, mm0, d1[3], m1[3], dd1, mm1;
-          eval_ray(st, lx0, ly, d0, m0, dd0, mm0);
-          eval_ray(st, lx1, ly, d1, m1, dd1, mm1);
+          float d0[3], m0[3], d1[3], m1[3];
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            d0[k] = fmaf(lx0, st[S_DU + k], db[k]);
+            m0[k] = fmaf(lx0, st[S_MU + k], mb[k]);
+            d1[k] = fmaf(lx1, st[S_DU + k], db[k]);
+            m1[k] = fmaf(lx1, st[S_MU + k], mb[k]);
+          }
+          const float dd0 = fmaf(d0[2], d0[2], fmaf(d0[1], d0[1], d0[0] * d0[0]));
+          const float mm0 = fmaf(m0[2], m0[2], fmaf(m0[1], m0[1], m0[0] * m0[0]));
+          const float dd1 = fmaf(d1[2], d1[2], fmaf(d1[1], d1[1], d1[0] * d1[0]));
+          const float mm1 = fmaf(m1[2], m1[2], fmaf(m1[1], m1[1], m1[0] * m1[0]));
           const bool f0 = hitb && is_fragment(dd0, mm0, st[S_RC]);
           const bool f1 = hitb && is_fragment(dd1, mm1, st[S_RC]);
-          if (f0) bwd_fragment<KMAX>(st, sp_all + p0 * L::kStride, tab0, dd0, mm0,
-                                     (int)s_slot[wave][q][lane] - 1, amax, acc);
-          if (f1) bwd_fragment<KMAX>(st, sp_all + p1 * L::kStride, tab1, dd1, mm1,
-                                     (int)s_slot[wave][q + 1][lane] - 1, amax, acc);
+          if (f0) bwd_fragment<KMAX>(st, sp_all + p0 * L::kStride, lx0, dd0, mm0,
+                                     (int)s_slot[wave][q][lane] - 1, amax, rs, acc);
+          if (f1) bwd_fragment<KMAX>(st, sp_all + p1 * L::kStride, lx1, dd1, mm1,
+                                     (int)s_slot[wave][q + 1][lane] - 1, amax, rs, acc);
         }
+        const float ly2 = ly * ly;
+        acc[0] += rs[0];
+        acc[1] += rs[1];
+        acc[2] = fmaf(ly, rs[0], acc[2]);
+        acc[3] += rs[2];
+        acc[4] = fmaf(ly, rs[1], acc[4]);
+        acc[5] = fmaf(ly2, rs[0], acc[5]);
+        acc[6] += rs[3];
+        acc[7] += rs[4];
+        acc[8] = fmaf(ly, rs[3], acc[8]);
+        acc[9] += rs[5];
+        acc[10] = fmaf(ly, rs[4], acc[10]);
+        acc[11] = fmaf(ly2, rs[3], acc[11]);
       }
       __builtin_amdgcn_wave_barrier();
     }
