@@ -17,6 +17,7 @@ fwd+bwd; reported under "multiview" (skip with --no-multiview).
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -125,6 +126,8 @@ def run_single(args):
     dev = torch.device("cuda:0")
     params = [torch.tensor(a, device=dev) for a in sc.arrays()]
     st, tune_rep = tune(params, sc, [cam], st, args)
+    # the backward writes the gradients (no separate clearing pass)
+    st = dataclasses.replace(st, grad_overwrite=True)
     target = torch.tensor(scenes.smooth_target(cam.height, cam.width), device=dev)
     n_inst = htgs.count_instances(params, sc.sh_degree, [cam], st)
     ws = htgs.alloc_workspace(sc.n, [cam], st, n_inst, dev)
@@ -141,8 +144,6 @@ def run_single(args):
             return
         torch.sub(img, target, out=gimg)
         gimg.sign_().mul_(inv_n)
-        for g in grads:
-            g.zero_()
         htgs.backward(params, frame, [gimg], grads=grads)
 
     for _ in range(args.warmup):
@@ -290,11 +291,13 @@ def run_multiview(args, steps=3, warmup=1):
     st1 = torch.empty(htgs.state_bytes([cams[big]], st) // 4, dtype=torch.float32, device=dev)
     grads_p = [torch.zeros_like(p) for p in params]
 
+    st_over = dataclasses.replace(st, grad_overwrite=True)
+
     def plain_step():
-        for g in grads_p:
-            g.zero_()
+        # the first view writes the gradients, the others add to them
         for v, c in enumerate(cams):
-            fr = htgs.forward(params, sc.sh_degree, [c], st, ws=ws1, state=st1, images=[imgs[v]])
+            fr = htgs.forward(params, sc.sh_degree, [c], st_over if v == 0 else st, ws=ws1,
+                              state=st1, images=[imgs[v]])
             torch.sub(imgs[v], targets[v], out=gimgs[v])
             gimgs[v].sign_().mul_(1.0 / imgs[v].numel())
             htgs.backward(params, fr, [gimgs[v]], grads=grads_p)
@@ -309,9 +312,7 @@ def run_multiview(args, steps=3, warmup=1):
         f"{n_b} (batched), batched ws {wsb.numel() / 2**30:.1f} GiB")
 
     def batched_step():
-        for g in grads_b:
-            g.zero_()
-        fr = htgs.forward(params, sc.sh_degree, cams, st, ws=wsb, state=stb, images=imgs_b)
+        fr = htgs.forward(params, sc.sh_degree, cams, st_over, ws=wsb, state=stb, images=imgs_b)
         for v in range(len(cams)):
             torch.sub(imgs_b[v], targets[v], out=gimgs_b[v])
             gimgs_b[v].sign_().mul_(1.0 / imgs_b[v].numel())
@@ -342,6 +343,13 @@ def run_multiview(args, steps=3, warmup=1):
 
     ms_plain = timed(plain_step)
     ms_batched = timed(graph.replay)
+    # stage split of one eager batched step
+    htgs.profile_enable(True)
+    htgs.profile_read()
+    batched_step()
+    torch.cuda.synchronize()
+    stages = {k: round(v[0], 3) for k, v in htgs.profile_read().items() if v[1]}
+    htgs.profile_enable(False)
     flags, _ = htgs.read_status(wsb)
     rel = {}
     for name, a, b in zip(("means", "log_scales", "quats", "opacity_logits", "sh"),
@@ -351,7 +359,8 @@ def run_multiview(args, steps=3, warmup=1):
     log(f"bench: multiview plain {ms_plain:.2f} ms, batched {ms_batched:.2f} ms")
     out = dict(workload=desc, views=[[c.width, c.height] for c in cams], steps=steps,
                plain_ms_per_step=round(ms_plain, 3), batched_ms_per_step=round(ms_batched, 3),
-               speedup=round(ms_plain / ms_batched, 3), status_flags=flags,
+               speedup=round(ms_plain / ms_batched, 3), batched_stages_ms=stages,
+               status_flags=flags,
                batched_vs_plain_image_max_abs=img_err, batched_vs_plain_grad_rel=rel,
                instances=n_b, settings=settings_desc(st), autotune=tune_rep)
     del wsb, ws1, stb, st1, params, grads_p, grads_b

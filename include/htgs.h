@@ -50,7 +50,9 @@ enum {
 
 #define HTGS_MAX_VIEWS 16
 
-/* Gaussian parameters (Sec. 3.1). 0 <= n < 2^27.
+/* Gaussian parameters (Sec. 3.1). 0 <= n < 2^27. Every array pointer (and
+ * every gradient pointer of htgs_grads) must be 16-byte aligned; rows are
+ * read and written with 16-byte accesses where their size allows.
  *  means          [n,3]  world-space centres
  *  log_scales     [n,3]  s = exp(log_scale); -INFINITY gives an exact zero axis
  *  quats          [n,4]  (w,x,y,z), normalised internally, must be non-zero
@@ -93,7 +95,10 @@ typedef struct htgs_camera {
  *  lds_batch  records staged per batch in the forward: 0 or the tile's pixel
  *             count (one per thread), or, with 8x8 tiles, twice that
  *  flags      HTGS_FLAG_COST_ORDER: rasterize tiles in descending order of
- *             their instance count (better load balance on uneven scenes) */
+ *             their instance count (better load balance on uneven scenes);
+ *             HTGS_FLAG_GRAD_OVERWRITE: the backward writes the gradients
+ *             instead of adding to them (zeros for Gaussians that no view
+ *             covers), so the caller need not clear them first */
 typedef struct htgs_config {
   int32_t K;
   float tau_alpha;
@@ -107,9 +112,11 @@ typedef struct htgs_config {
 } htgs_config;
 
 #define HTGS_FLAG_COST_ORDER 1u
+#define HTGS_FLAG_GRAD_OVERWRITE 2u
 
 /* Gradient outputs, same shapes as htgs_gaussians. The backward ADDS into
- * them (+=); any pointer may be NULL to skip that parameter. */
+ * them (+=), or overwrites them with HTGS_FLAG_GRAD_OVERWRITE; any pointer
+ * may be NULL to skip that parameter. */
 typedef struct htgs_grads {
   float *means;
   float *log_scales;

@@ -128,15 +128,21 @@ int check_cfg(const htgs_config *cfg) {
   const int np = cfg->tile_w * cfg->tile_h;
   if (cfg->lds_batch != 0 && cfg->lds_batch != np && !(t8 && cfg->lds_batch == 2 * np))
     return HTGS_E_INVAL;
-  if (cfg->flags & ~(uint32_t)HTGS_FLAG_COST_ORDER) return HTGS_E_INVAL;
+  if (cfg->flags & ~(uint32_t)(HTGS_FLAG_COST_ORDER | HTGS_FLAG_GRAD_OVERWRITE))
+    return HTGS_E_INVAL;
   return HTGS_OK;
 }
+
+bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
 int check_gaussians(const htgs_gaussians *g) {
   if (!g) return HTGS_E_INVAL;
   if (g->n < 0 || g->n >= (int64_t)(1 << 27)) return HTGS_E_INVAL;  // segment ids hold 27 bits
   if (g->sh_degree < 0 || g->sh_degree > 3) return HTGS_E_INVAL;
   if (g->n > 0 && (!g->means || !g->log_scales || !g->quats || !g->opacity_logits || !g->sh))
+    return HTGS_E_INVAL;
+  if (!aligned16(g->means) || !aligned16(g->log_scales) || !aligned16(g->quats) ||
+      !aligned16(g->opacity_logits) || !aligned16(g->sh))
     return HTGS_E_INVAL;
   return HTGS_OK;
 }
@@ -218,6 +224,7 @@ KCfg make_kcfg(const htgs_gaussians *g, const htgs_config *cfg) {
   k.tile_h = cfg->tile_h;
   k.batch_mult = (cfg->lds_batch == 2 * cfg->tile_w * cfg->tile_h) ? 2 : 1;
   k.cost_order = (cfg->flags & HTGS_FLAG_COST_ORDER) ? 1 : 0;
+  k.grad_overwrite = (cfg->flags & HTGS_FLAG_GRAD_OVERWRITE) ? 1 : 0;
   return k;
 }
 
@@ -328,6 +335,9 @@ int backward_impl(const htgs_gaussians *g, const htgs_camera *cams, int32_t n_vi
   int e = check_common(g, cams, n_views, cfg);
   if (e) return e;
   if (!ws || !state || !grad_rgb || !grads) return HTGS_E_INVAL;
+  if (!aligned16(grads->means) || !aligned16(grads->log_scales) || !aligned16(grads->quats) ||
+      !aligned16(grads->opacity_logits) || !aligned16(grads->sh))
+    return HTGS_E_INVAL;
   for (int v = 0; v < n_views; ++v)
     if (!grad_rgb[v]) return HTGS_E_INVAL;
   const int64_t tiles = total_tiles_of(cams, n_views, cfg);

@@ -83,6 +83,7 @@ struct KCfg {
   int32_t tile_w, tile_h;
   int32_t batch_mult;   // records staged per forward thread and batch (1 or 2)
   int32_t cost_order;   // raster workgroups take tiles in descending-cost order
+  int32_t grad_overwrite;  // preprocess backward stores gradients instead of adding
 };
 
 struct GaussPtrs {

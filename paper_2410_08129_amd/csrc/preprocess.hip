@@ -113,6 +113,40 @@ __device__ inline double dot3(const double a[3], const double b[3]) {
   return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
 }
 
+// The NF = 3 (DEG+1)^2 SH coefficients of one Gaussian: 16-byte accesses
+// where the row is a multiple of 16 bytes (degrees 1 and 3), so that a
+// wave's loads cover whole cache lines instead of one line per lane.
+template <int NF>
+__device__ __forceinline__ void load_row(const float *__restrict__ src, float *dst) {
+  if constexpr (NF % 4 == 0) {
+    const float4 *s4 = reinterpret_cast<const float4 *>(src);
+#pragma unroll
+    for (int i = 0; i < NF / 4; ++i) {
+      const float4 t = s4[i];
+      dst[4 * i] = t.x; dst[4 * i + 1] = t.y; dst[4 * i + 2] = t.z; dst[4 * i + 3] = t.w;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < NF; ++i) dst[i] = src[i];
+  }
+}
+
+template <int NF>
+__device__ __forceinline__ void add_row(float *dst, const float *v) {
+  if constexpr (NF % 4 == 0) {
+    float4 *d4 = reinterpret_cast<float4 *>(dst);
+#pragma unroll
+    for (int i = 0; i < NF / 4; ++i) {
+      float4 t = d4[i];
+      t.x += v[4 * i]; t.y += v[4 * i + 1]; t.z += v[4 * i + 2]; t.w += v[4 * i + 3];
+      d4[i] = t;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < NF; ++i) dst[i] += v[i];
+  }
+}
+
 // One Gaussian in one view: cull, box, rect, record. Returns the instance
 // count and writes the tile rect (and the record if the count is non-zero);
 // *packed receives tx0 | ty0 << 10 | width << 20 of a non-empty rect.
@@ -204,20 +238,8 @@ __device__ inline uint32_t preprocess_view(const GaussPtrs &gp, const KCfg &cfg,
   constexpr int NB = (DEG + 1) * (DEG + 1), NF = 3 * NB;
   float Y[16];
   sh_basis<float>((float)(dv[0] / dn), (float)(dv[1] / dn), (float)(dv[2] / dn), DEG, Y);
-  // the Gaussian's coefficients, 16-byte loads where the row is a multiple
-  // of 16 bytes (degrees 1 and 3)
   float coef[NF];
-  if constexpr (NF % 4 == 0) {
-    const float4 *s4 = reinterpret_cast<const float4 *>(gp.sh + g * NF);
-#pragma unroll
-    for (int i = 0; i < NF / 4; ++i) {
-      const float4 t = s4[i];
-      coef[4 * i] = t.x; coef[4 * i + 1] = t.y; coef[4 * i + 2] = t.z; coef[4 * i + 3] = t.w;
-    }
-  } else {
-#pragma unroll
-    for (int i = 0; i < NF; ++i) coef[i] = gp.sh[g * NF + i];
-  }
+  load_row<NF>(gp.sh + g * NF, coef);
   uint32_t flags = 0;
   float col[3];
 #pragma unroll
@@ -363,8 +385,14 @@ __global__ void __launch_bounds__(kPreThreads) k_preprocess(GaussPtrs gp, KCfg c
     const int64_t gi = blk * kPreThreads + lo;
     const uint32_t pr = s_vrect[v][lo];
     const uint32_t rw = pr >> 20;
-    const uint32_t ty = ((pr >> 10) & 1023u) + rank / rw;
-    const uint32_t tx = (pr & 1023u) + rank % rw;
+    // rank / rw and rank % rw; rank < 2^20 and rw <= 1024 are exact in
+    // float32, and the quotient estimate is off by at most one
+    int qy = (int)((float)rank * __builtin_amdgcn_rcpf((float)rw));
+    int rx = (int)rank - qy * (int)rw;
+    if (rx < 0) { --qy; rx += (int)rw; }
+    if (rx >= (int)rw) { ++qy; rx -= (int)rw; }
+    const uint32_t ty = ((pr >> 10) & 1023u) + (uint32_t)qy;
+    const uint32_t tx = (pr & 1023u) + (uint32_t)rx;
     const uint32_t key = (uint32_t)vs.v[v].tile_base + ty * (uint32_t)vs.v[v].tiles_x + tx;
     const unsigned long long pos = base + e;
     if (pos < (unsigned long long)w.capacity) {
@@ -463,10 +491,74 @@ __global__ void __launch_bounds__(256) k_segment_reduce(Ws w) {
   }
 }
 
+// ws[k] = sh_k . gc for the NB basis functions of one Gaussian, reading the
+// coefficient row four basis functions (three 16-byte loads) at a time
+// where the row allows it.
+template <int NB>
+__device__ __forceinline__ void sh_dots(const float *__restrict__ row, const double gcd[3],
+                                        float *ws) {
+  const float g0 = (float)gcd[0], g1 = (float)gcd[1], g2 = (float)gcd[2];
+  if constexpr ((3 * NB) % 12 == 0) {
+    const float4 *r4 = reinterpret_cast<const float4 *>(row);
+#pragma unroll
+    for (int j = 0; j < NB / 4; ++j) {
+      const float4 a = r4[3 * j], b = r4[3 * j + 1], c = r4[3 * j + 2];
+      const float t[12] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w};
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        ws[4 * j + q] = fmaf(t[3 * q + 2], g2, fmaf(t[3 * q + 1], g1, t[3 * q] * g0));
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < NB; ++k)
+      ws[k] = fmaf(row[3 * k + 2], g2, fmaf(row[3 * k + 1], g1, row[3 * k] * g0));
+  }
+}
+
+// Writes (overwrite) or adds the gradients of Gaussian g.
+template <int NB>
+__device__ __forceinline__ void emit_grads(const GradPtrs &gr, int64_t g, const float gmu[3],
+                                           const float gls[3], const float gq[4], float glogit,
+                                           const float *gsh, bool overwrite) {
+  if (overwrite) {
+    if (gr.means)
+      for (int k = 0; k < 3; ++k) gr.means[3 * g + k] = gmu[k];
+    if (gr.log_scales)
+      for (int k = 0; k < 3; ++k) gr.log_scales[3 * g + k] = gls[k];
+    if (gr.quats)
+      reinterpret_cast<float4 *>(gr.quats)[g] = make_float4(gq[0], gq[1], gq[2], gq[3]);
+    if (gr.logits) gr.logits[g] = glogit;
+    if (gr.sh) {
+      float *dst = gr.sh + g * NB * 3;
+      if constexpr ((3 * NB) % 4 == 0) {
+        float4 *d4 = reinterpret_cast<float4 *>(dst);
+#pragma unroll
+        for (int i = 0; i < 3 * NB / 4; ++i)
+          d4[i] = make_float4(gsh[4 * i], gsh[4 * i + 1], gsh[4 * i + 2], gsh[4 * i + 3]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < 3 * NB; ++i) dst[i] = gsh[i];
+      }
+    }
+  } else {
+    if (gr.means)
+      for (int k = 0; k < 3; ++k) gr.means[3 * g + k] += gmu[k];
+    if (gr.log_scales)
+      for (int k = 0; k < 3; ++k) gr.log_scales[3 * g + k] += gls[k];
+    if (gr.quats) {
+      float4 t = reinterpret_cast<float4 *>(gr.quats)[g];
+      t.x += gq[0]; t.y += gq[1]; t.z += gq[2]; t.w += gq[3];
+      reinterpret_cast<float4 *>(gr.quats)[g] = t;
+    }
+    if (gr.logits) gr.logits[g] += glogit;
+    if (gr.sh) add_row<3 * NB>(gr.sh + g * NB * 3, gsh);
+  }
+}
+
 // SH backward for one view, straight-line for a fixed degree: adds
-// Y_k(dir) * gc to gsh[k] and sum_k (sh_k . gc) grad Y_k(dir) to gdir.
+// Y_k(dir) * gc to gsh[k] and ws_k grad Y_k(dir) to gdir (ws_k = sh_k . gc).
 template <int DEG>
-__device__ __forceinline__ void sh_backward(const float *__restrict__ sh, const double dir[3],
+__device__ __forceinline__ void sh_backward(const float *wsv, const double dir[3],
                                             const double gc[3], float *gsh, double gdir[3]) {
   const double x = dir[0], y = dir[1], z = dir[2];
 #define HTGS_SH_TERM(k, Yv, gx, gy, gz)                                                     \
@@ -475,8 +567,7 @@ __device__ __forceinline__ void sh_backward(const float *__restrict__ sh, const 
     gsh[3 * (k)] += (float)(Yk * gc[0]);                                                    \
     gsh[3 * (k) + 1] += (float)(Yk * gc[1]);                                                \
     gsh[3 * (k) + 2] += (float)(Yk * gc[2]);                                                \
-    const double ws = (double)sh[3 * (k)] * gc[0] + (double)sh[3 * (k) + 1] * gc[1] +       \
-                      (double)sh[3 * (k) + 2] * gc[2];                                      \
+    const double ws = (double)wsv[k];                                                      \
     gdir[0] += ws * (gx);                                                                   \
     gdir[1] += ws * (gy);                                                                   \
     gdir[2] += ws * (gz);                                                                   \
@@ -515,19 +606,30 @@ __device__ __forceinline__ int rect_count(int4 r) {
   return r.x <= r.z ? (r.z - r.x + 1) * (r.w - r.y + 1) : 0;
 }
 
-template <int DEG>
+template <int DEG, bool MV>
 __global__ void __launch_bounds__(256) k_preprocess_bwd(GaussPtrs gp, GradPtrs gr, KCfg cfg,
                                                          ViewSet vs, Ws w) {
   constexpr int NB = (DEG + 1) * (DEG + 1);
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= cfg.n) return;
   uint32_t total = 0;
-  for (int v = 0; v < vs.n; ++v) total += (uint32_t)rect_count(w.rects[(int64_t)v * cfg.n + g]);
-  if (total == 0) return;
+  const int nviews = MV ? vs.n : 1;
+  for (int v = 0; v < nviews; ++v) total += (uint32_t)rect_count(w.rects[(int64_t)v * cfg.n + g]);
   const unsigned long long I = *w.total;
-  const uint32_t first = w.offsets[g];
-  if (I > (unsigned long long)w.capacity || (unsigned long long)first + total > I)
-    return;  // overflowed forward: status already reports it
+  const uint32_t first = total ? w.offsets[g] : 0u;
+  // No instance in any view (or an overflowed forward, which the status
+  // word reports): zero gradient.
+  if (total == 0 || I > (unsigned long long)w.capacity ||
+      (unsigned long long)first + total > I) {
+    if (cfg.grad_overwrite) {
+      const float z[4] = {0.f, 0.f, 0.f, 0.f};
+      float zsh[3 * NB];
+#pragma unroll
+      for (int k = 0; k < 3 * NB; ++k) zsh[k] = 0.f;
+      emit_grads<NB>(gr, g, z, z, z, 0.f, zsh, true);
+    }
+    return;
+  }
 
   Activated a;
   activate(gp, g, a);
@@ -537,10 +639,10 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(GaussPtrs gp, GradPtrs g
   float gsh[3 * NB];
 #pragma unroll
   for (int k = 0; k < 3 * NB; ++k) gsh[k] = 0.f;
-  const float *sh = gp.sh + g * NB * 3;
+  const float *shrow = gp.sh + g * NB * 3;
 
   uint32_t sa = first;
-  for (int v = 0; v < vs.n; ++v) {
+  for (int v = 0; v < nviews; ++v) {
     const uint32_t cnt = (uint32_t)rect_count(w.rects[(int64_t)v * cfg.n + g]);
     if (cnt == 0) continue;
     const uint32_t sb = sa + cnt;
@@ -613,7 +715,9 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(GaussPtrs gp, GradPtrs g
     const double dn = sqrt(dot3(dv, dv));
     const double dir[3] = {dv[0] / dn, dv[1] / dn, dv[2] / dn};
     double gdir[3] = {0, 0, 0};
-    sh_backward<DEG>(sh, dir, gc, gsh, gdir);
+    float wsv[NB];
+    sh_dots<NB>(shrow, gc, wsv);
+    sh_backward<DEG>(wsv, dir, gc, gsh, gdir);
     const double radial = dot3(gdir, dir);
     for (int j = 0; j < 3; ++j) gmu[j] += (gdir[j] - dir[j] * radial) / dn;
   }
@@ -630,18 +734,14 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(GaussPtrs gp, GradPtrs g
   rot_grad_to_quat(qn, gRot, gqn);
   const double proj = qn[0] * gqn[0] + qn[1] * gqn[1] + qn[2] * gqn[2] + qn[3] * gqn[3];
 
-  if (gr.means)
-    for (int k = 0; k < 3; ++k) gr.means[3 * g + k] += (float)gmu[k];
-  if (gr.log_scales)
-    for (int k = 0; k < 3; ++k) gr.log_scales[3 * g + k] += (float)(gs[k] * a.s[k]);
-  if (gr.quats)
-    for (int k = 0; k < 4; ++k) gr.quats[4 * g + k] += (float)((gqn[k] - qn[k] * proj) / a.qnorm);
-  if (gr.logits) gr.logits[g] += (float)(go * a.o * (1.0 - a.o));
-  if (gr.sh) {
-    float *dst = gr.sh + g * NB * 3;
-#pragma unroll
-    for (int k = 0; k < 3 * NB; ++k) dst[k] += gsh[k];
+  float fmu[3], fls[3], fq[4];
+  for (int k = 0; k < 3; ++k) {
+    fmu[k] = (float)gmu[k];
+    fls[k] = (float)(gs[k] * a.s[k]);
   }
+  for (int k = 0; k < 4; ++k) fq[k] = (float)((gqn[k] - qn[k] * proj) / a.qnorm);
+  emit_grads<NB>(gr, g, fmu, fls, fq, (float)(go * a.o * (1.0 - a.o)), gsh,
+                 cfg.grad_overwrite != 0);
 }
 
 hipError_t launch_fill_zero(void *p, int64_t bytes, hipStream_t s) {
@@ -688,11 +788,21 @@ hipError_t launch_preprocess_bwd(const GaussPtrs &gp, const GradPtrs &gr, const 
   if (cfg.n == 0) return hipSuccess;
   const int blocks = (int)((cfg.n + 255) / 256);
   switch (cfg.sh_degree) {
-    case 0: hipLaunchKernelGGL(k_preprocess_bwd<0>, dim3(blocks), dim3(256), 0, s, gp, gr, cfg, vs, w); break;
-    case 1: hipLaunchKernelGGL(k_preprocess_bwd<1>, dim3(blocks), dim3(256), 0, s, gp, gr, cfg, vs, w); break;
-    case 2: hipLaunchKernelGGL(k_preprocess_bwd<2>, dim3(blocks), dim3(256), 0, s, gp, gr, cfg, vs, w); break;
-    default: hipLaunchKernelGGL(k_preprocess_bwd<3>, dim3(blocks), dim3(256), 0, s, gp, gr, cfg, vs, w); break;
+#define HTGS_PREB(D)                                                                       \
+  do {                                                                                     \
+    if (vs.n > 1)                                                                          \
+      hipLaunchKernelGGL((k_preprocess_bwd<D, true>), dim3(blocks), dim3(256), 0, s, gp, gr, \
+                         cfg, vs, w);                                                      \
+    else                                                                                   \
+      hipLaunchKernelGGL((k_preprocess_bwd<D, false>), dim3(blocks), dim3(256), 0, s, gp,    \
+                         gr, cfg, vs, w);                                                  \
+  } while (0)
+    case 0: HTGS_PREB(0); break;
+    case 1: HTGS_PREB(1); break;
+    case 2: HTGS_PREB(2); break;
+    default: HTGS_PREB(3); break;
   }
+#undef HTGS_PREB
   return hipGetLastError();
 }
 

@@ -125,7 +125,8 @@ __device__ __forceinline__ bool rect_meets_block(const float *bb, int bx, int by
 // ---------------------------------------------------------------------------
 // Forward
 // ---------------------------------------------------------------------------
-template <int KMAX, int TW, int TH, int BM>
+// EXACT: K == KMAX, known at compile time.
+template <int KMAX, int TW, int TH, int BM, bool EXACT>
 __global__ void __launch_bounds__(TW *TH) k_raster_fwd(Ws w, ViewSet vs, KCfg cfg,
                                                        float *__restrict__ state,
                                                        const uint32_t *__restrict__ vals) {
@@ -149,7 +150,7 @@ __global__ void __launch_bounds__(TW *TH) k_raster_fwd(Ws w, ViewSet vs, KCfg cf
   const bool inside = (px < V.width) && (py < V.height);
   const uint2 rg = w.ranges[ti.t];
   const float flx = (float)lx, fly = (float)ly;
-  const int K = cfg.K;
+  const int K = EXACT ? KMAX : cfg.K;
   const float tau_core = cfg.tau_core, amax = cfg.alpha_max;
   const float *recs = w.records + (int64_t)ti.v * cfg.n * kRecFloats;
   const uint64_t lanemask_lt = (1ull << lane) - 1ull;
@@ -414,7 +415,7 @@ __device__ __forceinline__ void bwd_fragment(const float *st, const float *Pp, f
   }
 }
 
-template <int KMAX, int TW, int TH>
+template <int KMAX, int TW, int TH, bool EXACT>
 __global__ void __launch_bounds__(256, (TW == 8 && KMAX <= 8) ? 5 : ((TW == 8 && KMAX <= 16) ? 4 : 1)) k_raster_bwd(Ws w, ViewSet vs, KCfg cfg,
                                                     const float *__restrict__ state,
                                                     const uint32_t *__restrict__ vals) {
@@ -432,7 +433,7 @@ __global__ void __launch_bounds__(256, (TW == 8 && KMAX <= 8) ? 5 : ((TW == 8 &&
   const ViewParams &V = vs.v[ti.v];
   const int tid = threadIdx.x;
   const int px0 = ti.tx * TW, py0 = ti.ty * TH;
-  const int K = cfg.K;
+  const int K = EXACT ? KMAX : cfg.K;
   const float *recs = w.records + (int64_t)ti.v * cfg.n * kRecFloats;
   const int64_t npix = (int64_t)V.width * V.height;
   float *sp_all = reinterpret_cast<float *>(s_pix);
@@ -663,28 +664,28 @@ __global__ void __launch_bounds__(256, (TW == 8 && KMAX <= 8) ? 5 : ((TW == 8 &&
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-template <int KMAX, int TW, int TH>
+template <int KMAX, int TW, int TH, bool EXACT>
 static hipError_t fwd_launch(const Ws &w, const ViewSet &vs, const KCfg &cfg, float *state,
                              const uint32_t *vals, hipStream_t s) {
   const int blocks = 8 * ((vs.total_tiles + 7) / 8);
   if constexpr (TW == 8) {
     if (cfg.batch_mult == 2) {
-      hipLaunchKernelGGL((k_raster_fwd<KMAX, TW, TH, 2>), dim3(blocks), dim3(TW * TH), 0, s, w,
-                         vs, cfg, state, vals);
+      hipLaunchKernelGGL((k_raster_fwd<KMAX, TW, TH, 2, EXACT>), dim3(blocks), dim3(TW * TH), 0,
+                         s, w, vs, cfg, state, vals);
       return hipGetLastError();
     }
   }
-  hipLaunchKernelGGL((k_raster_fwd<KMAX, TW, TH, 1>), dim3(blocks), dim3(TW * TH), 0, s, w, vs,
-                     cfg, state, vals);
+  hipLaunchKernelGGL((k_raster_fwd<KMAX, TW, TH, 1, EXACT>), dim3(blocks), dim3(TW * TH), 0, s,
+                     w, vs, cfg, state, vals);
   return hipGetLastError();
 }
 
-template <int KMAX, int TW, int TH>
+template <int KMAX, int TW, int TH, bool EXACT>
 static hipError_t bwd_launch(const Ws &w, const ViewSet &vs, const KCfg &cfg, const float *state,
                              const uint32_t *vals, hipStream_t s) {
   const int blocks = 8 * ((vs.total_tiles + 7) / 8);
-  hipLaunchKernelGGL((k_raster_bwd<KMAX, TW, TH>), dim3(blocks), dim3(256), 0, s, w, vs, cfg,
-                     state, vals);
+  hipLaunchKernelGGL((k_raster_bwd<KMAX, TW, TH, EXACT>), dim3(blocks), dim3(256), 0, s, w, vs,
+                     cfg, state, vals);
   return hipGetLastError();
 }
 
@@ -697,25 +698,27 @@ int kmax_for(int K) {
   return 32;
 }
 
+#define HTGS_KX(FN, KM, TW_, TH_, ...)                                          \
+  (cfg.K == (KM) ? FN<KM, TW_, TH_, true>(__VA_ARGS__) : FN<KM, TW_, TH_, false>(__VA_ARGS__))
 #define HTGS_DISPATCH(FN, ...)                                                   \
   do {                                                                           \
     const int km = kmax_for(cfg.K);                                              \
     if (cfg.tile_w == 8 && cfg.tile_h == 8) {                                    \
       switch (km) {                                                              \
-        case 1: return FN<1, 8, 8>(__VA_ARGS__);                                 \
-        case 2: return FN<2, 8, 8>(__VA_ARGS__);                                 \
-        case 4: return FN<4, 8, 8>(__VA_ARGS__);                                 \
-        case 8: return FN<8, 8, 8>(__VA_ARGS__);                                 \
-        case 16: return FN<16, 8, 8>(__VA_ARGS__);                               \
-        default: return FN<32, 8, 8>(__VA_ARGS__);                               \
+        case 1: return HTGS_KX(FN, 1, 8, 8, __VA_ARGS__);                                 \
+        case 2: return HTGS_KX(FN, 2, 8, 8, __VA_ARGS__);                                 \
+        case 4: return HTGS_KX(FN, 4, 8, 8, __VA_ARGS__);                                 \
+        case 8: return HTGS_KX(FN, 8, 8, 8, __VA_ARGS__);                                 \
+        case 16: return HTGS_KX(FN, 16, 8, 8, __VA_ARGS__);                               \
+        default: return HTGS_KX(FN, 32, 8, 8, __VA_ARGS__);                               \
       }                                                                          \
     } else {                                                                     \
       switch (km) {                                                              \
-        case 1: return FN<1, 16, 16>(__VA_ARGS__);                               \
-        case 2: return FN<2, 16, 16>(__VA_ARGS__);                               \
-        case 4: return FN<4, 16, 16>(__VA_ARGS__);                               \
-        case 8: return FN<8, 16, 16>(__VA_ARGS__);                               \
-        default: return FN<16, 16, 16>(__VA_ARGS__);                             \
+        case 1: return HTGS_KX(FN, 1, 16, 16, __VA_ARGS__);                               \
+        case 2: return HTGS_KX(FN, 2, 16, 16, __VA_ARGS__);                               \
+        case 4: return HTGS_KX(FN, 4, 16, 16, __VA_ARGS__);                               \
+        case 8: return HTGS_KX(FN, 8, 16, 16, __VA_ARGS__);                               \
+        default: return HTGS_KX(FN, 16, 16, 16, __VA_ARGS__);                             \
       }                                                                          \
     }                                                                            \
   } while (0)

@@ -55,7 +55,7 @@ def test_workspace_and_state_sizes():
 
 @pytest.mark.parametrize("field,value", [
     ("K", 33), ("K", -1), ("tile_w", 12), ("tau_alpha", 0.0), ("alpha_max", 1.0),
-    ("flags", 2), ("lds_batch", 7), ("lds_batch", 512),
+    ("flags", 4), ("lds_batch", 7), ("lds_batch", 512),
 ])
 def test_bad_config_rejected(field, value):
     sc, cams, st = _small()
@@ -119,6 +119,11 @@ def test_forward_argument_errors_before_device_work():
     bad.fx = float("nan")
     assert L.htgs_render_forward(ctypes.byref(g), ctypes.byref(bad), ctypes.byref(cfg), fake,
                                  1 << 30, None, fake, None) == -1
+    # parameter arrays must be 16-byte aligned
+    g4 = _fake_gaussians()
+    g4.sh = 0x2004
+    assert L.htgs_render_forward(ctypes.byref(g4), ctypes.byref(cam), ctypes.byref(cfg), fake,
+                                 1 << 30, None, fake, None) == -1
 
 
 def test_backward_and_batched_argument_errors():
@@ -140,6 +145,11 @@ def test_backward_and_batched_argument_errors():
                                   1 << 30, None, fake, ctypes.byref(gr), None) == -1
     assert L.htgs_render_backward(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(cfg), fake, 64,
                                   fake, fake, ctypes.byref(gr), None) == -2
+    # gradient arrays must be 16-byte aligned
+    gr2 = htgs.Grads()
+    gr2.means = 0x2008
+    assert L.htgs_render_backward(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(cfg), fake,
+                                  1 << 30, fake, fake, ctypes.byref(gr2), None) == -1
     assert L.htgs_read_status(None, 0, None, None, None, None) == -1
     assert L.htgs_profile_read(None, None, 0) == -1
     n = ctypes.c_int64()

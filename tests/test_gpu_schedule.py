@@ -155,3 +155,20 @@ def test_autotune_returns_a_candidate_and_caches(tmp_path, monkeypatch):
                                ref.numpy(), info, st2)
     log(f"  tuned {rep['best']}: {stats}")
     assert stats['max_err_clean'] < 1e-4
+
+
+def test_grad_overwrite_equals_accumulate_from_zero(crop_1080p):
+    sc, cam, st, params, G = crop_1080p
+    base = dataclasses.replace(st, grad_overwrite=False)
+    over = dataclasses.replace(st, grad_overwrite=True)
+    frame = htgs.forward(params, sc.sh_degree, [cam], base)
+    g_acc = htgs.backward(params, frame, [G])            # into zeros
+    g_over = [torch.full_like(p, float("nan")) for p in params]
+    frame2 = htgs.forward(params, sc.sh_degree, [cam], over)
+    htgs.backward(params, frame2, [G], grads=g_over)
+    torch.cuda.synchronize()
+    n_zero = int((g_acc[0].abs().sum(1) == 0).sum())
+    log(f"  {n_zero} of {sc.n} Gaussians without gradient (written as zeros)")
+    assert n_zero > 0
+    for a, b in zip(g_acc, g_over):
+        assert torch.equal(a, b)
