@@ -101,15 +101,18 @@ def cpu_baseline(sc, cam, st, min_seconds=10.0, max_crops=64, size=64):
 
 def settings_desc(st):
     return {"tile": [st.tile_w, st.tile_h], "lds_batch": st.lds_batch or st.tile_w * st.tile_h,
-            "cost_order": bool(st.cost_order)}
+            "cost_order": bool(st.cost_order), "tile_cull": bool(st.tile_cull)}
 
 
 def tune(params, sc, cams, st, args):
     from paper_2410_08129_amd import autotune
+    if args.tile_cull != "auto":
+        st = dataclasses.replace(st, tile_cull=(args.tile_cull == "on"))
     if args.tile:
         st.tile_w = st.tile_h = args.tile
         return st, {"mode": "fixed"}
-    st2, rep = autotune.tune(params, sc.sh_degree, cams, st)
+    st2, rep = autotune.tune(params, sc.sh_degree, cams, st,
+                             cull_choices=None if args.tile_cull == "auto" else (st.tile_cull,))
     log(f"bench: autotune -> {settings_desc(st2)}")
     return st2, rep
 
@@ -376,6 +379,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="1080p")
     ap.add_argument("--tile", type=int, default=0, help="fixed tile size (8 or 16), no autotune")
+    ap.add_argument("--tile-cull", choices=("auto", "on", "off"), default="auto",
+                    help="exact tile culling of small screen boxes (auto: the autotuner decides)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-multiview", action="store_true")
     ap.add_argument("--forward-only", action="store_true")

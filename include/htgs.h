@@ -98,7 +98,14 @@ typedef struct htgs_camera {
  *             their instance count (better load balance on uneven scenes);
  *             HTGS_FLAG_GRAD_OVERWRITE: the backward writes the gradients
  *             instead of adding to them (zeros for Gaussians that no view
- *             covers), so the caller need not clear them first */
+ *             covers), so the caller need not clear them first;
+ *             HTGS_FLAG_TILE_CULL: for screen boxes of at most 64 tiles,
+ *             drop the tiles of the box that the splat's rho_c-ellipse does
+ *             not reach (exact float64 test against the tile's pixel
+ *             centres, with 0.1% slack on rho_c). Images, state and
+ *             gradients are the same as without it; the tile lists are then
+ *             a subset of Sec. 3.2's box lists (forward and backward of one
+ *             frame must use the same flag) */
 typedef struct htgs_config {
   int32_t K;
   float tau_alpha;
@@ -113,6 +120,7 @@ typedef struct htgs_config {
 
 #define HTGS_FLAG_COST_ORDER 1u
 #define HTGS_FLAG_GRAD_OVERWRITE 2u
+#define HTGS_FLAG_TILE_CULL 4u
 
 /* Gradient outputs, same shapes as htgs_gaussians. The backward ADDS into
  * them (+=), or overwrites them with HTGS_FLAG_GRAD_OVERWRITE; any pointer

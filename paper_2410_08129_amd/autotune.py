@@ -20,8 +20,10 @@ import torch
 from . import htgs
 
 CANDIDATES = (
-    # (tile, lds_batch multiplier, cost order)
-    (8, 1, False), (8, 2, False), (8, 1, True), (8, 2, True), (16, 1, False), (16, 1, True),
+    # (tile, lds_batch multiplier, cost order, tile culling)
+    (8, 1, False, False), (8, 2, False, False), (8, 1, True, False), (8, 2, True, False),
+    (16, 1, False, False), (16, 1, True, False),
+    (8, 1, False, True), (8, 1, True, True), (16, 1, False, True), (16, 1, True, True),
 )
 
 
@@ -37,10 +39,10 @@ def _key(n, cams, st, sh_degree):
 
 
 def apply(st, cand):
-    tile, mult, order = cand
+    tile, mult, order, cull = cand
     return dataclasses.replace(st, tile_w=tile, tile_h=tile,
                                lds_batch=(tile * tile * mult) if mult > 1 else 0,
-                               cost_order=bool(order))
+                               cost_order=bool(order), tile_cull=bool(cull))
 
 
 def _time_candidate(params, sh_degree, cams, st, steps):
@@ -67,12 +69,14 @@ def _time_candidate(params, sh_degree, cams, st, steps):
     return e0.elapsed_time(e1) / steps
 
 
-def tune(params, sh_degree, cams, st, steps=3, verbose=False):
-    """Returns (settings, report) for this workload."""
+def tune(params, sh_degree, cams, st, steps=3, verbose=False, cull_choices=None):
+    """Returns (settings, report) for this workload. cull_choices restricts
+    the tile-culling setting of the candidates (None: both)."""
     mode = os.environ.get("HTGS_TUNE", "search")
     if mode == "off":
         return st, {"mode": "off"}
-    key = _key(params[0].shape[0], cams, st, sh_degree)
+    key = _key(params[0].shape[0], cams, st, sh_degree) + (
+        "" if cull_choices is None else f"|cull{sorted(cull_choices)}")
     path = _cache_path()
     cache = {}
     if os.path.exists(path):
@@ -87,8 +91,11 @@ def tune(params, sh_degree, cams, st, steps=3, verbose=False):
     for cand in CANDIDATES:
         if cand[0] == 16 and st.K > 16:
             continue
+        if cull_choices is not None and cand[3] not in cull_choices:
+            continue
         ms = _time_candidate(params, sh_degree, cams, apply(st, cand), steps)
-        name = f"tile{cand[0]}_batch{cand[1]}x_{'cost' if cand[2] else 'xcd'}"
+        name = (f"tile{cand[0]}_batch{cand[1]}x_{'cost' if cand[2] else 'xcd'}"
+                f"{'_cull' if cand[3] else ''}")
         times[name] = ms
         by_name[name] = cand
         if verbose:

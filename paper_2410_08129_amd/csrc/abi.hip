@@ -31,7 +31,7 @@ int64_t align_up(int64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
   int64_t status, total, pp_look, hist, sort_look, ranges, order_hist, zero_end;
-  int64_t records, rects, offsets, order, keys0, keys1, vals0, vals1, partials, bytes;
+  int64_t records, rects, offsets, masks, order, keys0, keys1, vals0, vals1, partials, bytes;
   int64_t capacity, max_chunks;
   int32_t key_bits, passes, key16;
 };
@@ -62,6 +62,7 @@ Layout make_layout(int64_t n, int n_views, int64_t total_tiles, int64_t capacity
   L.records = o; o = align_up(o + (int64_t)n_views * n * kRecFloats * 4);
   L.rects = o; o = align_up(o + (int64_t)n_views * n * 16);
   L.offsets = o; o = align_up(o + 4 * n);
+  L.masks = o; o = align_up(o + (int64_t)n_views * n * 8);
   L.order = o; o = align_up(o + 4 * total_tiles);
   L.keys0 = o; o = align_up(o + kb * capacity);
   L.keys1 = o; o = align_up(o + kb * capacity);
@@ -99,6 +100,7 @@ Ws make_ws(void *base, const Layout &L) {
   w.records = reinterpret_cast<float *>(b + L.records);
   w.rects = reinterpret_cast<int4 *>(b + L.rects);
   w.offsets = reinterpret_cast<uint32_t *>(b + L.offsets);
+  w.masks = reinterpret_cast<unsigned long long *>(b + L.masks);
   w.keys[0] = b + L.keys0;
   w.keys[1] = b + L.keys1;
   w.vals[0] = reinterpret_cast<uint32_t *>(b + L.vals0);
@@ -128,7 +130,8 @@ int check_cfg(const htgs_config *cfg) {
   const int np = cfg->tile_w * cfg->tile_h;
   if (cfg->lds_batch != 0 && cfg->lds_batch != np && !(t8 && cfg->lds_batch == 2 * np))
     return HTGS_E_INVAL;
-  if (cfg->flags & ~(uint32_t)(HTGS_FLAG_COST_ORDER | HTGS_FLAG_GRAD_OVERWRITE))
+  if (cfg->flags &
+      ~(uint32_t)(HTGS_FLAG_COST_ORDER | HTGS_FLAG_GRAD_OVERWRITE | HTGS_FLAG_TILE_CULL))
     return HTGS_E_INVAL;
   return HTGS_OK;
 }
@@ -225,6 +228,7 @@ KCfg make_kcfg(const htgs_gaussians *g, const htgs_config *cfg) {
   k.batch_mult = (cfg->lds_batch == 2 * cfg->tile_w * cfg->tile_h) ? 2 : 1;
   k.cost_order = (cfg->flags & HTGS_FLAG_COST_ORDER) ? 1 : 0;
   k.grad_overwrite = (cfg->flags & HTGS_FLAG_GRAD_OVERWRITE) ? 1 : 0;
+  k.tile_cull = (cfg->flags & HTGS_FLAG_TILE_CULL) ? 1 : 0;
   return k;
 }
 

@@ -84,6 +84,7 @@ struct KCfg {
   int32_t batch_mult;   // records staged per forward thread and batch (1 or 2)
   int32_t cost_order;   // raster workgroups take tiles in descending-cost order
   int32_t grad_overwrite;  // preprocess backward stores gradients instead of adding
+  int32_t tile_cull;       // drop rect tiles that no fragment can reach (rects of <= 64 tiles)
 };
 
 struct GaussPtrs {
@@ -107,6 +108,7 @@ struct Ws {
   uint32_t *order;             // [total_tiles] tiles by descending instance count
   float *records;              // [views][n][32]
   int4 *rects;                 // [views][n] tile rect (tx0, ty0, tx1, ty1), empty if tx0 > tx1
+  unsigned long long *masks;   // [views][n] surviving tiles of the rect (row-major bits), 0 = all
   uint32_t *offsets;           // [n] first instance slot of each Gaussian
   void *keys[2];
   uint32_t *vals[2];
@@ -140,6 +142,19 @@ __device__ __forceinline__ void st_rel_u64(unsigned long long *p, unsigned long 
 }
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Instances of one (view, Gaussian): the rect's tiles, or the surviving
+// ones when a tile mask is set.
+__device__ __forceinline__ int tile_count(int4 r, unsigned long long mask) {
+  if (r.x > r.z || r.y > r.w) return 0;
+  return mask ? __popcll(mask) : (r.z - r.x + 1) * (r.w - r.y + 1);
+}
+
+// Position of tile idx (row-major in the rect) among the instances of its
+// (view, Gaussian).
+__device__ __forceinline__ uint32_t tile_rank(int idx, unsigned long long mask) {
+  return mask ? (uint32_t)__popcll(mask & ((1ull << idx) - 1ull)) : (uint32_t)idx;
+}
 
 // Tile coverage rule shared by the forward and backward launchers: tile ids
 // are handed out so that consecutive workgroups on one XCD (workgroups are

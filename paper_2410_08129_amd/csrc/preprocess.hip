@@ -147,10 +147,88 @@ __device__ __forceinline__ void add_row(float *dst, const float *v) {
   }
 }
 
+// Tiles of a screen box that the splat's rho_c-ellipse reaches. With the
+// Pluecker vectors affine in the pixel offset (p, q) from the reference
+// pixel, d = Dc + p Dx + q Dy and m = Mc + p Mx + q My, a pixel is a fragment
+// iff Q(p, q) = |m|^2 - rho_c |d|^2 <= 0. Q is a quadratic in (p, q); for a
+// splat in front of the camera its quadratic part is positive definite, so
+// its minimum over a tile's rectangle of pixel centres is the free minimum
+// if that lies inside, else the smallest of the four edge minima. A tile is
+// kept if that minimum is <= 0 for rho_c enlarged by 0.1% (float32
+// evaluation in the rasterizer cannot move a pixel across that margin).
+// *valid is false (keep every tile) when the quadratic part is not clearly
+// positive definite.
+struct Conic {
+  double A, B, C, Dpp, Epq, Fqq;  // Q = A + 2Bp + 2Cq + Dpp p^2 + 2Epq pq + Fqq q^2
+};
+
+__device__ inline Conic make_conic(const double Dc[3], const double Dx[3], const double Dy[3],
+                                   const double Mc[3], const double Mx[3], const double My[3],
+                                   double rc) {
+  const double r = rc * 1.001;
+  Conic c;
+  c.A = dot3(Mc, Mc) - r * dot3(Dc, Dc);
+  c.B = dot3(Mc, Mx) - r * dot3(Dc, Dx);
+  c.C = dot3(Mc, My) - r * dot3(Dc, Dy);
+  c.Dpp = dot3(Mx, Mx) - r * dot3(Dx, Dx);
+  c.Epq = dot3(Mx, My) - r * dot3(Dx, Dy);
+  c.Fqq = dot3(My, My) - r * dot3(Dy, Dy);
+  return c;
+}
+
+__device__ __forceinline__ double conic_at(const Conic &c, double p, double q) {
+  return c.A + 2.0 * (c.B * p + c.C * q) + c.Dpp * p * p + 2.0 * c.Epq * p * q + c.Fqq * q * q;
+}
+
+// Bits of the rect's tiles (row-major) that the ellipse Q <= 0 reaches.
+// Tile rows are handled one at a time: over a row's band of pixel-centre
+// rows q in [qa, qb] (offsets from the reference pixel, clipped to the
+// covered pixel rect), the ellipse spans p from its left boundary's minimum
+// to its right boundary's maximum; the left boundary is convex in q, so its
+// minimum over the band is at the band point nearest the ellipse's
+// leftmost point (likewise on the right). The pixel-centre columns in that
+// span give the row's tiles. *valid is false when the quadratic part is not
+// clearly positive definite (then every tile stays).
+__device__ inline unsigned long long cull_mask(const Conic &c, int4 rect, int tw, int th,
+                                               double x0, double x1, double y0, double y1,
+                                               double ixd, double iyd, bool *valid) {
+  const double det = c.Dpp * c.Fqq - c.Epq * c.Epq;
+  *valid = c.Dpp > 0.0 && c.Fqq > 0.0 && det > 1e-9 * c.Dpp * c.Fqq;
+  if (!*valid) return 0ull;
+  const double ps = (c.Epq * c.C - c.Fqq * c.B) / det, qs = (c.Epq * c.B - c.Dpp * c.C) / det;
+  const double Q0 = conic_at(c, ps, qs);
+  if (!(Q0 < 0.0)) return 0ull;  // empty ellipse: no fragment anywhere
+  const double hp = sqrt(-Q0 * c.Fqq / det), hq = sqrt(-Q0 * c.Dpp / det);
+  const double qmin = qs - hq, qmax = qs + hq;
+  const double qL = qs + c.Epq * hp / c.Fqq, qR = qs - c.Epq * hp / c.Fqq;
+  const double idp = 1.0 / c.Dpp;
+  // p extent of the ellipse on the line q: pc(q) +- sqrt(disc(q)) / Dpp
+  auto side = [&](double q, double sgn) {
+    const double b = c.B + c.Epq * q;
+    const double disc = b * b - c.Dpp * (c.A + 2.0 * c.C * q + c.Fqq * q * q);
+    return (-b + sgn * sqrt(fmax(disc, 0.0))) * idp;
+  };
+  const int w = rect.z - rect.x + 1;
+  unsigned long long mask = 0ull;
+  for (int ty = rect.y; ty <= rect.w; ++ty) {
+    const double a = fmax(fmax((double)(ty * th), y0) - iyd, qmin);
+    const double b = fmin(fmin((double)(ty * th + th - 1), y1) - iyd, qmax);
+    if (a > b) continue;
+    const double pl = side(fmin(fmax(qL, a), b), -1.0);
+    const double pr = side(fmin(fmax(qR, a), b), 1.0);
+    const double xlo = fmax(ceil(pl + ixd), x0), xhi = fmin(floor(pr + ixd), x1);
+    if (xlo > xhi) continue;
+    const int t0 = (int)xlo / tw - rect.x, t1 = (int)xhi / tw - rect.x;
+    const unsigned long long run = ((2ull << (t1 - t0)) - 1ull) << t0;
+    mask |= run << ((ty - rect.y) * w);
+  }
+  return mask;
+}
+
 // One Gaussian in one view: cull, box, rect, record. Returns the instance
 // count and writes the tile rect (and the record if the count is non-zero);
 // *packed receives tx0 | ty0 << 10 | width << 20 of a non-empty rect.
-template <int DEG>
+template <int DEG, bool CULL>
 __device__ inline uint32_t preprocess_view(const GaussPtrs &gp, const KCfg &cfg,
                                            const ViewParams &V, const Ws &w, int v,
                                            int64_t g, const Activated &a, uint32_t *packed) {
@@ -194,9 +272,12 @@ __device__ inline uint32_t preprocess_view(const GaussPtrs &gp, const KCfg &cfg,
       count = (uint32_t)((rect.z - rect.x + 1) * (rect.w - rect.y + 1));
     }
   }
-  w.rects[(int64_t)v * cfg.n + g] = rect;
-  if (count == 0) return 0;
-  *packed = (uint32_t)rect.x | ((uint32_t)rect.y << 10) | ((uint32_t)(rect.z - rect.x + 1) << 20);
+  const int64_t vg = (int64_t)v * cfg.n + g;
+  if (count == 0) {
+    w.rects[vg] = rect;
+    w.masks[vg] = 0ull;
+    return 0;
+  }
 
   // Reference point: the centre of the covered pixel nearest the box centre.
   const double ixd = fmin(fmax(floor(p1), x0), x1);
@@ -206,6 +287,25 @@ __device__ inline uint32_t preprocess_view(const GaussPtrs &gp, const KCfg &cfg,
   cross3(Rv[0], Rv[1], D0);
   cross3(Rv[1], Rv[2], Du);
   cross3(Rv[2], Rv[0], Dv);
+  // Tile culling works on the float64 conic of the footprint; the tiles are
+  // tested after the record is written, when few other values are live.
+  const bool cull = CULL && count >= 2u && count <= 64u;
+  Conic conic{};
+  if (cull) {
+    double Dc[3], Dx[3], Dy[3], Mc[3], Mx[3], My[3];
+    for (int k = 0; k < 3; ++k) {
+      const double M0 = mv[0] * Rv[1][k] - mv[1] * Rv[0][k];
+      const double Mu = mv[1] * Rv[2][k] - mv[2] * Rv[1][k];
+      const double Mv = mv[2] * Rv[0][k] - mv[0] * Rv[2][k];
+      Dc[k] = D0[k] + uc * Du[k] + vc * Dv[k];
+      Dx[k] = Du[k] / fx;
+      Dy[k] = Dv[k] / fy;
+      Mc[k] = M0 + uc * Mu + vc * Mv;
+      Mx[k] = Mu / fx;
+      My[k] = Mv / fy;
+    }
+    conic = make_conic(Dc, Dx, Dy, Mc, Mx, My, rc);
+  }
   // The geometric part of the record is stored first so that its registers
   // are free before the colour is evaluated.
   float rec[24];
@@ -254,6 +354,20 @@ __device__ inline uint32_t preprocess_view(const GaussPtrs &gp, const KCfg &cfg,
     col[c] = acc;
   }
   dst[R_RGB / 4] = make_float4(col[0], col[1], col[2], __uint_as_float(flags));
+
+  unsigned long long mask = 0ull;
+  if (cull) {
+    bool valid = false;
+    mask = cull_mask(conic, rect, cfg.tile_w, cfg.tile_h, x0, x1, y0, y1, ixd, iyd, &valid);
+    if (valid) count = (uint32_t)__popcll(mask);
+  }
+  if (count == 0) rect = make_int4(1, 1, 0, 0);
+  w.rects[vg] = rect;
+  w.masks[vg] = mask;
+  if (count) {
+    *packed =
+        (uint32_t)rect.x | ((uint32_t)rect.y << 10) | ((uint32_t)(rect.z - rect.x + 1) << 20);
+  }
   return count;
 }
 
@@ -263,14 +377,17 @@ __global__ void __launch_bounds__(256) k_fill_zero(uint4 *p, int64_t n16) {
     p[i] = make_uint4(0u, 0u, 0u, 0u);
 }
 
-// MV: more than one view (a single view keeps far fewer values live).
-template <int DEG, bool MV>
+// MV: more than one view (a single view keeps far fewer values live);
+// CULL: tile culling of small boxes.
+template <int DEG, bool MV, bool CULL>
 __global__ void __launch_bounds__(kPreThreads) k_preprocess(GaussPtrs gp, KCfg cfg, ViewSet vs,
                                                              Ws w) {
   __shared__ uint32_t s_ticket;
   __shared__ uint32_t s_excl[kPreThreads + 1];
-  __shared__ uint32_t s_vcnt[kMaxViews][kPreThreads];
-  __shared__ uint32_t s_vrect[kMaxViews][kPreThreads];
+  constexpr int NVL = MV ? kMaxViews : 1;
+  __shared__ uint32_t s_vcnt[NVL][kPreThreads];
+  __shared__ uint32_t s_vrect[NVL][kPreThreads];
+  __shared__ unsigned long long s_vmask[NVL][kPreThreads];
   __shared__ uint32_t s_hist[4][256];
   __shared__ uint32_t s_wsum[kPreThreads / 64];
   __shared__ unsigned long long s_base;
@@ -289,9 +406,10 @@ __global__ void __launch_bounds__(kPreThreads) k_preprocess(GaussPtrs gp, KCfg c
     activate(gp, g, a);
     for (int v = 0; v < nviews; ++v) {
       uint32_t packed = 0;
-      const uint32_t c = preprocess_view<DEG>(gp, cfg, vs.v[v], w, v, g, a, &packed);
+      const uint32_t c = preprocess_view<DEG, CULL>(gp, cfg, vs.v[v], w, v, g, a, &packed);
       s_vcnt[v][tid] = c;
       s_vrect[v][tid] = packed;
+      s_vmask[v][tid] = c ? w.masks[(int64_t)v * cfg.n + g] : 0ull;
       total += c;
     }
   } else {
@@ -385,6 +503,22 @@ __global__ void __launch_bounds__(kPreThreads) k_preprocess(GaussPtrs gp, KCfg c
     const int64_t gi = blk * kPreThreads + lo;
     const uint32_t pr = s_vrect[v][lo];
     const uint32_t rw = pr >> 20;
+    // With a tile mask, the rank-th surviving tile is the rank-th set bit.
+    const unsigned long long mk = s_vmask[v][lo];
+    if (mk) {
+      unsigned long long m = mk;
+      uint32_t pos = 0, k = rank;
+#pragma unroll
+      for (int wd = 32; wd >= 1; wd >>= 1) {
+        const uint32_t c = (uint32_t)__popcll(m & ((1ull << wd) - 1ull));
+        if (k >= c) {
+          k -= c;
+          m >>= wd;
+          pos += (uint32_t)wd;
+        }
+      }
+      rank = pos;
+    }
     // rank / rw and rank % rw; rank < 2^20 and rw <= 1024 are exact in
     // float32, and the quotient estimate is off by at most one
     int qy = (int)((float)rank * __builtin_amdgcn_rcpf((float)rw));
@@ -602,9 +736,6 @@ __device__ __forceinline__ void sh_backward(const float *wsv, const double dir[3
 #undef HTGS_SH_TERM
 }
 
-__device__ __forceinline__ int rect_count(int4 r) {
-  return r.x <= r.z ? (r.z - r.x + 1) * (r.w - r.y + 1) : 0;
-}
 
 template <int DEG, bool MV>
 __global__ void __launch_bounds__(256) k_preprocess_bwd(GaussPtrs gp, GradPtrs gr, KCfg cfg,
@@ -614,7 +745,8 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(GaussPtrs gp, GradPtrs g
   if (g >= cfg.n) return;
   uint32_t total = 0;
   const int nviews = MV ? vs.n : 1;
-  for (int v = 0; v < nviews; ++v) total += (uint32_t)rect_count(w.rects[(int64_t)v * cfg.n + g]);
+  for (int v = 0; v < nviews; ++v)
+    total += (uint32_t)tile_count(w.rects[(int64_t)v * cfg.n + g], w.masks[(int64_t)v * cfg.n + g]);
   const unsigned long long I = *w.total;
   const uint32_t first = total ? w.offsets[g] : 0u;
   // No instance in any view (or an overflowed forward, which the status
@@ -643,7 +775,8 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(GaussPtrs gp, GradPtrs g
 
   uint32_t sa = first;
   for (int v = 0; v < nviews; ++v) {
-    const uint32_t cnt = (uint32_t)rect_count(w.rects[(int64_t)v * cfg.n + g]);
+    const uint32_t cnt =
+        (uint32_t)tile_count(w.rects[(int64_t)v * cfg.n + g], w.masks[(int64_t)v * cfg.n + g]);
     if (cnt == 0) continue;
     const uint32_t sb = sa + cnt;
     // Sum of the segment: the block-portion sums left by the segmented reduction.
@@ -757,14 +890,15 @@ hipError_t launch_preprocess(const GaussPtrs &gp, const KCfg &cfg, const ViewSet
                              hipStream_t s) {
   if (cfg.n == 0) return hipSuccess;
   const int blocks = (int)((cfg.n + kPreThreads - 1) / kPreThreads);
-#define HTGS_PRE(D)                                                                      \
-  do {                                                                                   \
-    if (vs.n > 1)                                                                        \
-      hipLaunchKernelGGL((k_preprocess<D, true>), dim3(blocks), dim3(kPreThreads), 0, s, gp, \
-                         cfg, vs, w);                                                    \
-    else                                                                                 \
-      hipLaunchKernelGGL((k_preprocess<D, false>), dim3(blocks), dim3(kPreThreads), 0, s,    \
-                         gp, cfg, vs, w);                                                \
+#define HTGS_PRE3(D, M, C)                                                                 \
+  hipLaunchKernelGGL((k_preprocess<D, M, C>), dim3(blocks), dim3(kPreThreads), 0, s, gp, cfg, vs, w)
+#define HTGS_PRE(D)                                                                        \
+  do {                                                                                     \
+    if (vs.n > 1) {                                                                        \
+      if (cfg.tile_cull) HTGS_PRE3(D, true, true); else HTGS_PRE3(D, true, false);         \
+    } else {                                                                               \
+      if (cfg.tile_cull) HTGS_PRE3(D, false, true); else HTGS_PRE3(D, false, false);       \
+    }                                                                                      \
   } while (0)
   switch (cfg.sh_degree) {
     case 0: HTGS_PRE(0); break;
@@ -773,6 +907,7 @@ hipError_t launch_preprocess(const GaussPtrs &gp, const KCfg &cfg, const ViewSet
     default: HTGS_PRE(3); break;
   }
 #undef HTGS_PRE
+#undef HTGS_PRE3
   return hipGetLastError();
 }
 

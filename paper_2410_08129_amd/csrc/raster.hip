@@ -536,12 +536,13 @@ __global__ void __launch_bounds__(256, (TW == 8 && KMAX <= 8) ? 5 : ((TW == 8 &&
       load_record(recs, gid, rec);
       stage_record(rec, px0, py0, j - rg.x, st);
       uint32_t pre = 0;
-      for (int u = 0; u < ti.v; ++u) {
-        const int4 r = w.rects[(int64_t)u * cfg.n + gid];
-        if (r.x <= r.z) pre += (uint32_t)((r.z - r.x + 1) * (r.w - r.y + 1));
-      }
+      for (int u = 0; u < ti.v; ++u)
+        pre += (uint32_t)tile_count(w.rects[(int64_t)u * cfg.n + gid],
+                                    w.masks[(int64_t)u * cfg.n + gid]);
       const int4 r = w.rects[(int64_t)ti.v * cfg.n + gid];
-      slot = w.offsets[gid] + pre + (uint32_t)((ti.ty - r.y) * (r.z - r.x + 1) + (ti.tx - r.x));
+      const unsigned long long mk = w.masks[(int64_t)ti.v * cfg.n + gid];
+      slot = w.offsets[gid] + pre +
+             tile_rank((ti.ty - r.y) * (r.z - r.x + 1) + (ti.tx - r.x), mk);
     }
     // acc: d-moments (6), m-moments (6), dL/do, dL/drgb (3)
     float acc[16];

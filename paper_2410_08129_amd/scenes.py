@@ -95,6 +95,7 @@ class RenderSettings:
     lds_batch: int = 0          # forward records per batch: 0 = tile pixels, 2x allowed at 8x8
     cost_order: bool = False    # rasterize tiles in descending instance-count order
     grad_overwrite: bool = False  # backward writes gradients instead of adding to them
+    tile_cull: bool = False     # drop box tiles that the rho_c-ellipse does not reach
 
 
 def look_at(eye, target, up_world, fov_x_deg, width, height, z_near=0.2) -> Camera:
