@@ -356,7 +356,10 @@ int backward_impl(const htgs_gaussians *g, const htgs_camera *cams, int32_t n_vi
     StageTimer t(HTGS_STAGE_RASTER_BWD, s);
     HIP_TRY(launch_raster_bwd(w, vs, k, static_cast<const float *>(state), w.vals[w.final_buf], s));
   }
-  if (cap > 0) {
+  // With several views the instance partials are summed per (Gaussian,
+  // view) by a separate pass; with one view the preprocess backward sums
+  // them itself.
+  if (cap > 0 && n_views > 1) {
     StageTimer t(HTGS_STAGE_REDUCE, s);
     HIP_TRY(launch_segment_reduce(w, s));
   }

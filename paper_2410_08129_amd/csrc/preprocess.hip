@@ -737,11 +737,66 @@ __device__ __forceinline__ void sh_backward(const float *wsv, const double dir[3
 }
 
 
-template <int DEG, bool MV>
+// FUSED (one view only): each wave owns 64 consecutive Gaussians, whose
+// instance slots are one contiguous range; the wave walks that range 64
+// slots at a time with the segmented scan and adds each segment's sum for
+// the chunk into its owner's LDS column, so the partials are read once,
+// coalesced, and no separate reduction pass is needed. Otherwise the sums
+// come from the block-portion sums of k_segment_reduce.
+template <int DEG, bool MV, bool FUSED>
 __global__ void __launch_bounds__(256) k_preprocess_bwd(GaussPtrs gp, GradPtrs gr, KCfg cfg,
                                                          ViewSet vs, Ws w) {
+  static_assert(!(MV && FUSED), "the fused sum covers one view");
   constexpr int NB = (DEG + 1) * (DEG + 1);
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ float s_acc[FUSED ? 4 : 1][22][64];
+  if constexpr (FUSED) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t g0 = g - lane;
+    if (g0 >= cfg.n) return;  // uniform over the wave
+#pragma unroll
+    for (int k = 0; k < 22; ++k) s_acc[wave][k][lane] = 0.f;
+    const unsigned long long I = *w.total;
+    if (I <= (unsigned long long)w.capacity) {
+      const uint64_t s_begin = w.offsets[g0];
+      const uint64_t s_end = (g0 + 64 < cfg.n) ? (uint64_t)w.offsets[g0 + 64] : (uint64_t)I;
+      for (uint64_t base = s_begin; base < s_end; base += 64) {
+        const uint64_t sl = base + lane;
+        const bool valid = sl < s_end;
+        float v[22];
+        uint32_t seg = 0xffffffffu;
+        if (valid) {
+          const float4 *P = reinterpret_cast<const float4 *>(w.partials + (int64_t)sl * kPartialFloats);
+#pragma unroll
+          for (int k = 0; k < 5; ++k) {
+            const float4 t = P[k];
+            v[4 * k] = t.x; v[4 * k + 1] = t.y; v[4 * k + 2] = t.z; v[4 * k + 3] = t.w;
+          }
+          const float4 t = P[5];
+          v[20] = t.x; v[21] = t.y;
+          seg = __float_as_uint(t.z);
+        } else {
+#pragma unroll
+          for (int k = 0; k < 22; ++k) v[k] = 0.f;
+        }
+        seg_scan_step<0x111, 0xf>(seg, v);
+        seg_scan_step<0x112, 0xf>(seg, v);
+        seg_scan_step<0x114, 0xf>(seg, v);
+        seg_scan_step<0x118, 0xf>(seg, v);
+        seg_scan_step<0x142, 0xa>(seg, v);
+        seg_scan_step<0x143, 0xc>(seg, v);
+        const uint32_t sn = __shfl_down(seg, 1, 64);
+        const bool end = valid && (lane == 63 || sn != seg || sl + 1 == s_end);
+        if (end) {
+          const int owner = (int)((int64_t)(seg & ((1u << 27) - 1u)) - g0);
+#pragma unroll
+          for (int k = 0; k < 22; ++k) s_acc[wave][k][owner] += v[k];
+        }
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
   if (g >= cfg.n) return;
   uint32_t total = 0;
   const int nviews = MV ? vs.n : 1;
@@ -779,10 +834,14 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(GaussPtrs gp, GradPtrs g
         (uint32_t)tile_count(w.rects[(int64_t)v * cfg.n + g], w.masks[(int64_t)v * cfg.n + g]);
     if (cnt == 0) continue;
     const uint32_t sb = sa + cnt;
-    // Sum of the segment: the block-portion sums left by the segmented reduction.
     float acc[22];
 #pragma unroll
     for (int k = 0; k < 22; ++k) acc[k] = 0.f;
+    if constexpr (FUSED) {
+#pragma unroll
+      for (int k = 0; k < 22; ++k) acc[k] = s_acc[threadIdx.x >> 6][k][threadIdx.x & 63];
+    } else {
+    // Sum of the segment: the block-portion sums left by the segmented reduction.
     for (uint32_t blk = sa >> 6; blk <= (sb - 1) >> 6; ++blk) {
       const uint32_t e = min(sb - 1, blk * 64u + 63u);
       const float4 *P = reinterpret_cast<const float4 *>(w.partials + (int64_t)e * kPartialFloats);
@@ -793,6 +852,7 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(GaussPtrs gp, GradPtrs g
       }
       const float4 t = P[5];
       acc[20] += t.x; acc[21] += t.y;
+    }
     }
     sa = sb;
     const ViewParams &V = vs.v[v];
@@ -926,11 +986,11 @@ hipError_t launch_preprocess_bwd(const GaussPtrs &gp, const GradPtrs &gr, const 
 #define HTGS_PREB(D)                                                                       \
   do {                                                                                     \
     if (vs.n > 1)                                                                          \
-      hipLaunchKernelGGL((k_preprocess_bwd<D, true>), dim3(blocks), dim3(256), 0, s, gp, gr, \
-                         cfg, vs, w);                                                      \
-    else                                                                                   \
-      hipLaunchKernelGGL((k_preprocess_bwd<D, false>), dim3(blocks), dim3(256), 0, s, gp,    \
+      hipLaunchKernelGGL((k_preprocess_bwd<D, true, false>), dim3(blocks), dim3(256), 0, s, gp, \
                          gr, cfg, vs, w);                                                  \
+    else                                                                                   \
+      hipLaunchKernelGGL((k_preprocess_bwd<D, false, true>), dim3(blocks), dim3(256), 0, s,   \
+                         gp, gr, cfg, vs, w);                                              \
   } while (0)
     case 0: HTGS_PREB(0); break;
     case 1: HTGS_PREB(1); break;
