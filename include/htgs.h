@@ -91,7 +91,8 @@ typedef struct htgs_camera {
  *  tau_core   minimum alpha for core membership, tau_K (Sec. 4.2, 0.05)
  *  alpha_max  alpha clamp, alpha = min(alpha_max, o exp(-rho^2/2)), in (0,1)
  *  bg         background colour c_bg of Eq. pixel_color_computation
- *  tile_w/h   8x8 or 16x16 pixels
+ *  tile_w/h   8x8, 16x8, 16x16 or 32x8 pixels (one 64-lane wave per 8x8
+ *             block); K <= 16 for the 256-pixel shapes
  *  lds_batch  records staged per batch in the forward: 0 or the tile's pixel
  *             count (one per thread), or, with 8x8 tiles, twice that
  *  flags      HTGS_FLAG_COST_ORDER: rasterize tiles in descending order of

@@ -20,10 +20,13 @@ import torch
 from . import htgs
 
 CANDIDATES = (
-    # (tile, lds_batch multiplier, cost order, tile culling)
-    (8, 1, False, False), (8, 2, False, False), (8, 1, True, False), (8, 2, True, False),
-    (16, 1, False, False), (16, 1, True, False),
-    (8, 1, False, True), (8, 1, True, True), (16, 1, False, True), (16, 1, True, True),
+    # (tile width, tile height, lds_batch multiplier, cost order, tile culling)
+    (8, 8, 1, False, False), (8, 8, 2, False, False), (8, 8, 1, True, False),
+    (8, 8, 2, True, False), (16, 8, 1, False, False), (16, 16, 1, False, False),
+    (16, 16, 1, True, False), (32, 8, 1, False, False),
+    (8, 8, 1, False, True), (8, 8, 1, True, True), (16, 8, 1, False, True),
+    (16, 8, 1, True, True), (16, 16, 1, False, True), (16, 16, 1, True, True),
+    (32, 8, 1, False, True), (32, 8, 1, True, True),
 )
 
 
@@ -34,14 +37,14 @@ def _cache_path():
 def _key(n, cams, st, sh_degree):
     px = sum(c.width * c.height for c in cams)
     dev = torch.cuda.get_device_name(0) if torch.cuda.is_available() else "cpu"
-    return (f"{dev}|n{int(math.log2(max(n, 1)))}|px{int(math.log2(max(px, 1)))}|v{len(cams)}"
+    return (f"v2|{dev}|n{int(math.log2(max(n, 1)))}|px{int(math.log2(max(px, 1)))}|v{len(cams)}"
             f"|K{st.K}|sh{sh_degree}")
 
 
 def apply(st, cand):
-    tile, mult, order, cull = cand
-    return dataclasses.replace(st, tile_w=tile, tile_h=tile,
-                               lds_batch=(tile * tile * mult) if mult > 1 else 0,
+    tw, th, mult, order, cull = cand
+    return dataclasses.replace(st, tile_w=tw, tile_h=th,
+                               lds_batch=(tw * th * mult) if mult > 1 else 0,
                                cost_order=bool(order), tile_cull=bool(cull))
 
 
@@ -89,13 +92,13 @@ def tune(params, sh_degree, cams, st, steps=3, verbose=False, cull_choices=None)
     times = {}
     by_name = {}
     for cand in CANDIDATES:
-        if cand[0] == 16 and st.K > 16:
+        if cand[0] * cand[1] > 128 and st.K > 16:
             continue
-        if cull_choices is not None and cand[3] not in cull_choices:
+        if cull_choices is not None and cand[4] not in cull_choices:
             continue
         ms = _time_candidate(params, sh_degree, cams, apply(st, cand), steps)
-        name = (f"tile{cand[0]}_batch{cand[1]}x_{'cost' if cand[2] else 'xcd'}"
-                f"{'_cull' if cand[3] else ''}")
+        name = (f"tile{cand[0]}x{cand[1]}_batch{cand[2]}x_{'cost' if cand[3] else 'xcd'}"
+                f"{'_cull' if cand[4] else ''}")
         times[name] = ms
         by_name[name] = cand
         if verbose:

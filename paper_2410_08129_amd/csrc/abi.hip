@@ -124,9 +124,11 @@ int check_cfg(const htgs_config *cfg) {
   for (int c = 0; c < 3; ++c)
     if (!isfinite(cfg->bg[c])) return HTGS_E_INVAL;
   const bool t8 = cfg->tile_w == 8 && cfg->tile_h == 8;
+  const bool t16x8 = cfg->tile_w == 16 && cfg->tile_h == 8;
   const bool t16 = cfg->tile_w == 16 && cfg->tile_h == 16;
-  if (!t8 && !t16) return HTGS_E_INVAL;
-  if (t16 && cfg->K > 16) return HTGS_E_INVAL;
+  const bool t32x8 = cfg->tile_w == 32 && cfg->tile_h == 8;
+  if (!t8 && !t16x8 && !t16 && !t32x8) return HTGS_E_INVAL;
+  if ((t16 || t32x8) && cfg->K > 16) return HTGS_E_INVAL;
   const int np = cfg->tile_w * cfg->tile_h;
   if (cfg->lds_batch != 0 && cfg->lds_batch != np && !(t8 && cfg->lds_batch == 2 * np))
     return HTGS_E_INVAL;

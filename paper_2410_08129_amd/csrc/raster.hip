@@ -706,20 +706,37 @@ int kmax_for(int K) {
     const int km = kmax_for(cfg.K);                                              \
     if (cfg.tile_w == 8 && cfg.tile_h == 8) {                                    \
       switch (km) {                                                              \
-        case 1: return HTGS_KX(FN, 1, 8, 8, __VA_ARGS__);                                 \
-        case 2: return HTGS_KX(FN, 2, 8, 8, __VA_ARGS__);                                 \
-        case 4: return HTGS_KX(FN, 4, 8, 8, __VA_ARGS__);                                 \
-        case 8: return HTGS_KX(FN, 8, 8, 8, __VA_ARGS__);                                 \
-        case 16: return HTGS_KX(FN, 16, 8, 8, __VA_ARGS__);                               \
-        default: return HTGS_KX(FN, 32, 8, 8, __VA_ARGS__);                               \
+        case 1: return HTGS_KX(FN, 1, 8, 8, __VA_ARGS__);                        \
+        case 2: return HTGS_KX(FN, 2, 8, 8, __VA_ARGS__);                        \
+        case 4: return HTGS_KX(FN, 4, 8, 8, __VA_ARGS__);                        \
+        case 8: return HTGS_KX(FN, 8, 8, 8, __VA_ARGS__);                        \
+        case 16: return HTGS_KX(FN, 16, 8, 8, __VA_ARGS__);                      \
+        default: return HTGS_KX(FN, 32, 8, 8, __VA_ARGS__);                      \
+      }                                                                          \
+    } else if (cfg.tile_w == 16 && cfg.tile_h == 8) {                            \
+      switch (km) {                                                              \
+        case 1: return HTGS_KX(FN, 1, 16, 8, __VA_ARGS__);                       \
+        case 2: return HTGS_KX(FN, 2, 16, 8, __VA_ARGS__);                       \
+        case 4: return HTGS_KX(FN, 4, 16, 8, __VA_ARGS__);                       \
+        case 8: return HTGS_KX(FN, 8, 16, 8, __VA_ARGS__);                       \
+        case 16: return HTGS_KX(FN, 16, 16, 8, __VA_ARGS__);                     \
+        default: return HTGS_KX(FN, 32, 16, 8, __VA_ARGS__);                     \
+      }                                                                          \
+    } else if (cfg.tile_w == 32 && cfg.tile_h == 8) {                            \
+      switch (km) {                                                              \
+        case 1: return HTGS_KX(FN, 1, 32, 8, __VA_ARGS__);                       \
+        case 2: return HTGS_KX(FN, 2, 32, 8, __VA_ARGS__);                       \
+        case 4: return HTGS_KX(FN, 4, 32, 8, __VA_ARGS__);                       \
+        case 8: return HTGS_KX(FN, 8, 32, 8, __VA_ARGS__);                       \
+        default: return HTGS_KX(FN, 16, 32, 8, __VA_ARGS__);                     \
       }                                                                          \
     } else {                                                                     \
       switch (km) {                                                              \
-        case 1: return HTGS_KX(FN, 1, 16, 16, __VA_ARGS__);                               \
-        case 2: return HTGS_KX(FN, 2, 16, 16, __VA_ARGS__);                               \
-        case 4: return HTGS_KX(FN, 4, 16, 16, __VA_ARGS__);                               \
-        case 8: return HTGS_KX(FN, 8, 16, 16, __VA_ARGS__);                               \
-        default: return HTGS_KX(FN, 16, 16, 16, __VA_ARGS__);                             \
+        case 1: return HTGS_KX(FN, 1, 16, 16, __VA_ARGS__);                      \
+        case 2: return HTGS_KX(FN, 2, 16, 16, __VA_ARGS__);                      \
+        case 4: return HTGS_KX(FN, 4, 16, 16, __VA_ARGS__);                      \
+        case 8: return HTGS_KX(FN, 8, 16, 16, __VA_ARGS__);                      \
+        default: return HTGS_KX(FN, 16, 16, 16, __VA_ARGS__);                    \
       }                                                                          \
     }                                                                            \
   } while (0)

@@ -76,6 +76,12 @@ def test_large_core_needs_small_tiles():
     cfg = htgs.config_struct(scenes.RenderSettings(K=20, tile_w=8, tile_h=8))
     assert htgs.lib().htgs_workspace_bytes(sc.n, htgs.cameras_array(cams), 1, ctypes.byref(cfg), 0,
                                            ctypes.byref(out)) == 0
+    for (tw, th, k, ok) in [(16, 8, 32, True), (32, 8, 16, True), (32, 8, 17, False),
+                            (8, 16, 4, False), (32, 32, 4, False)]:
+        cfg = htgs.config_struct(scenes.RenderSettings(K=k, tile_w=tw, tile_h=th))
+        code = htgs.lib().htgs_workspace_bytes(sc.n, htgs.cameras_array(cams), 1,
+                                               ctypes.byref(cfg), 0, ctypes.byref(out))
+        assert code == (0 if ok else -1), (tw, th, k)
 
 
 def _fake_gaussians(n=10, deg=0):

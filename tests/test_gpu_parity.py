@@ -41,10 +41,14 @@ def core_of(frame, view=0):
 # Small workload: 4,096 Gaussians, 128x128
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("tile", [16, 8])
+def _shape(tile):
+    return tile if isinstance(tile, tuple) else (tile, tile)
+
+
+@pytest.mark.parametrize("tile", [16, 8, (16, 8), (32, 8)])
 def test_small_tile_lists_bit_exact(tile):
     sc, cams, st = scenes.workload_small()
-    st.tile_w = st.tile_h = tile
+    st.tile_w, st.tile_h = _shape(tile)
     log(f"small bins tile={tile}")
     params, frame = gpu_forward(sc, cams, st)
     keys, vals, rects, flags = htgs.export_bins(params, sc.sh_degree, cams, st, frame.ws)
@@ -66,10 +70,12 @@ def test_small_image_parity_default():
 @pytest.mark.parametrize("K,tile,bg", [
     (0, 16, (0.2, 0.5, 0.1)), (1, 8, (0.0, 0.0, 0.0)), (8, 8, (0.3, 0.3, 0.9)),
     (16, 8, (0.0, 0.0, 0.0)), (32, 8, (0.1, 0.0, 0.4)), (16, 16, (0.0, 0.7, 0.0)),
+    (8, (16, 8), (0.2, 0.2, 0.2)), (32, (16, 8), (0.0, 0.0, 0.0)), (5, (32, 8), (0.4, 0.1, 0.0)),
 ])
 def test_small_image_parity_variants(K, tile, bg):
     sc, cams, st = scenes.workload_small()
-    st = scenes.RenderSettings(K=K, tile_w=tile, tile_h=tile, bg=bg)
+    tw, th = _shape(tile)
+    st = scenes.RenderSettings(K=K, tile_w=tw, tile_h=th, bg=bg)
     cam = cams[0].crop(21, 37, 77, 53)      # ragged in both directions
     log(f"small crop K={K} tile={tile}")
     params, frame = gpu_forward(sc, [cam], st)
@@ -170,10 +176,10 @@ def _gpu_grads(sub, cam, st, G):
 NAMES = ("means", "log_scales", "quats", "opacity_logits", "sh")
 
 
-@pytest.mark.parametrize("seed,tile", [(7, 8), (11, 16), (13, 8)])
+@pytest.mark.parametrize("seed,tile", [(7, 8), (11, 16), (13, 8), (17, (16, 8)), (19, (32, 8))])
 def test_gradients_match_oracle_on_subcrop(seed, tile):
     sub, cam, st, target = _subcrop(seed)
-    st.tile_w = st.tile_h = tile
+    st.tile_w, st.tile_h = _shape(tile)
     log(f"gradients: 256 Gaussians, 32x32, seed {seed}, tile {tile}")
     ref_img = oracle.render.render_scene(sub, cam, st, cull=False).numpy()
     G = np.sign(ref_img - target) / (3 * cam.width * cam.height)
