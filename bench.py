@@ -101,7 +101,8 @@ def cpu_baseline(sc, cam, st, min_seconds=10.0, max_crops=64, size=64):
 
 def settings_desc(st):
     return {"tile": [st.tile_w, st.tile_h], "lds_batch": st.lds_batch or st.tile_w * st.tile_h,
-            "cost_order": bool(st.cost_order), "tile_cull": bool(st.tile_cull)}
+            "cost_order": bool(st.cost_order), "tile_cull": bool(st.tile_cull),
+            "persistent": bool(st.persistent)}
 
 
 def tune(params, sc, cams, st, args):

@@ -106,7 +106,11 @@ typedef struct htgs_camera {
  *             centres, with 0.1% slack on rho_c). Images, state and
  *             gradients are the same as without it; the tile lists are then
  *             a subset of Sec. 3.2's box lists (forward and backward of one
- *             frame must use the same flag) */
+ *             frame must use the same flag);
+ *             HTGS_FLAG_PERSISTENT: the raster launches hold as many
+ *             workgroups as fit on the device at once, each pulling tiles
+ *             from an atomic queue (in descending-cost order with
+ *             HTGS_FLAG_COST_ORDER) until it runs out */
 typedef struct htgs_config {
   int32_t K;
   float tau_alpha;
@@ -122,6 +126,7 @@ typedef struct htgs_config {
 #define HTGS_FLAG_COST_ORDER 1u
 #define HTGS_FLAG_GRAD_OVERWRITE 2u
 #define HTGS_FLAG_TILE_CULL 4u
+#define HTGS_FLAG_PERSISTENT 8u
 
 /* Gradient outputs, same shapes as htgs_gaussians. The backward ADDS into
  * them (+=), or overwrites them with HTGS_FLAG_GRAD_OVERWRITE; any pointer

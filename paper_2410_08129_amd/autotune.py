@@ -20,13 +20,18 @@ import torch
 from . import htgs
 
 CANDIDATES = (
-    # (tile width, tile height, lds_batch multiplier, cost order, tile culling)
-    (8, 8, 1, False, False), (8, 8, 2, False, False), (8, 8, 1, True, False),
-    (8, 8, 2, True, False), (16, 8, 1, False, False), (16, 16, 1, False, False),
-    (16, 16, 1, True, False), (32, 8, 1, False, False),
-    (8, 8, 1, False, True), (8, 8, 1, True, True), (16, 8, 1, False, True),
-    (16, 8, 1, True, True), (16, 16, 1, False, True), (16, 16, 1, True, True),
-    (32, 8, 1, False, True), (32, 8, 1, True, True),
+    # (tile width, tile height, lds_batch multiplier, cost order, tile culling,
+    #  persistent tile queue)
+    (8, 8, 1, False, False, False), (8, 8, 2, False, False, False),
+    (8, 8, 1, True, False, False), (8, 8, 2, True, False, False),
+    (16, 8, 1, False, False, False), (16, 16, 1, False, False, False),
+    (16, 16, 1, True, False, False), (32, 8, 1, False, False, False),
+    (8, 8, 1, False, True, False), (8, 8, 1, True, True, False),
+    (16, 8, 1, False, True, False), (16, 8, 1, True, True, False),
+    (16, 16, 1, False, True, False), (16, 16, 1, True, True, False),
+    (32, 8, 1, False, True, False), (32, 8, 1, True, True, False),
+    (8, 8, 1, False, True, True), (8, 8, 1, True, True, True),
+    (16, 8, 1, True, True, True), (16, 16, 1, True, True, True),
 )
 
 
@@ -37,15 +42,16 @@ def _cache_path():
 def _key(n, cams, st, sh_degree):
     px = sum(c.width * c.height for c in cams)
     dev = torch.cuda.get_device_name(0) if torch.cuda.is_available() else "cpu"
-    return (f"v2|{dev}|n{int(math.log2(max(n, 1)))}|px{int(math.log2(max(px, 1)))}|v{len(cams)}"
+    return (f"v3|{dev}|n{int(math.log2(max(n, 1)))}|px{int(math.log2(max(px, 1)))}|v{len(cams)}"
             f"|K{st.K}|sh{sh_degree}")
 
 
 def apply(st, cand):
-    tw, th, mult, order, cull = cand
+    tw, th, mult, order, cull, persist = cand
     return dataclasses.replace(st, tile_w=tw, tile_h=th,
                                lds_batch=(tw * th * mult) if mult > 1 else 0,
-                               cost_order=bool(order), tile_cull=bool(cull))
+                               cost_order=bool(order), tile_cull=bool(cull),
+                               persistent=bool(persist))
 
 
 def _time_candidate(params, sh_degree, cams, st, steps):
@@ -98,7 +104,7 @@ def tune(params, sh_degree, cams, st, steps=3, verbose=False, cull_choices=None)
             continue
         ms = _time_candidate(params, sh_degree, cams, apply(st, cand), steps)
         name = (f"tile{cand[0]}x{cand[1]}_batch{cand[2]}x_{'cost' if cand[3] else 'xcd'}"
-                f"{'_cull' if cand[4] else ''}")
+                f"{'_cull' if cand[4] else ''}{'_queue' if cand[5] else ''}")
         times[name] = ms
         by_name[name] = cand
         if verbose:

@@ -133,7 +133,8 @@ int check_cfg(const htgs_config *cfg) {
   if (cfg->lds_batch != 0 && cfg->lds_batch != np && !(t8 && cfg->lds_batch == 2 * np))
     return HTGS_E_INVAL;
   if (cfg->flags &
-      ~(uint32_t)(HTGS_FLAG_COST_ORDER | HTGS_FLAG_GRAD_OVERWRITE | HTGS_FLAG_TILE_CULL))
+      ~(uint32_t)(HTGS_FLAG_COST_ORDER | HTGS_FLAG_GRAD_OVERWRITE | HTGS_FLAG_TILE_CULL |
+                  HTGS_FLAG_PERSISTENT))
     return HTGS_E_INVAL;
   return HTGS_OK;
 }
@@ -231,6 +232,7 @@ KCfg make_kcfg(const htgs_gaussians *g, const htgs_config *cfg) {
   k.cost_order = (cfg->flags & HTGS_FLAG_COST_ORDER) ? 1 : 0;
   k.grad_overwrite = (cfg->flags & HTGS_FLAG_GRAD_OVERWRITE) ? 1 : 0;
   k.tile_cull = (cfg->flags & HTGS_FLAG_TILE_CULL) ? 1 : 0;
+  k.persistent = (cfg->flags & HTGS_FLAG_PERSISTENT) ? 1 : 0;
   return k;
 }
 
@@ -330,6 +332,8 @@ int forward_impl(const htgs_gaussians *g, const htgs_camera *cams, int32_t n_vie
   if ((e = run_front(g, vs, cfg, L, ws, s, true))) return e;
   const Ws w = make_ws(ws, L);
   StageTimer t(HTGS_STAGE_RASTER_FWD, s);
+  if (cfg->flags & HTGS_FLAG_PERSISTENT)
+    HIP_TRY(launch_fill_zero(static_cast<char *>(ws) + L.status + 4 * kQueueFwd, 16, s));
   HIP_TRY(launch_raster_fwd(w, vs, make_kcfg(g, cfg), static_cast<float *>(state),
                             w.vals[w.final_buf], s));
   return HTGS_OK;
@@ -356,6 +360,8 @@ int backward_impl(const htgs_gaussians *g, const htgs_camera *cams, int32_t n_vi
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (cap > 0) {
     StageTimer t(HTGS_STAGE_RASTER_BWD, s);
+    if (cfg->flags & HTGS_FLAG_PERSISTENT)
+      HIP_TRY(launch_fill_zero(static_cast<char *>(ws) + L.status + 4 * kQueueBwd, 16, s));
     HIP_TRY(launch_raster_bwd(w, vs, k, static_cast<const float *>(state), w.vals[w.final_buf], s));
   }
   // With several views the instance partials are summed per (Gaussian,

@@ -85,6 +85,7 @@ struct KCfg {
   int32_t cost_order;   // raster workgroups take tiles in descending-cost order
   int32_t grad_overwrite;  // preprocess backward stores gradients instead of adding
   int32_t tile_cull;       // drop rect tiles that no fragment can reach (rects of <= 64 tiles)
+  int32_t persistent;      // raster workgroups pull tiles from an atomic queue
 };
 
 struct GaussPtrs {
@@ -127,6 +128,9 @@ constexpr int kSpinLimit = 1 << 22;
 constexpr int kLookWindow = 4;   // look-back words read per round trip
 
 enum StatusBits : uint32_t { ST_OVERFLOW = 1u, ST_SPIN = 2u };
+// status words of the persistent raster queues (16-byte aligned, cleared
+// before each raster launch)
+constexpr int kQueueFwd = 8, kQueueBwd = 12;
 
 __device__ __forceinline__ uint32_t ld_acq_u32(const uint32_t *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -117,6 +117,40 @@ __device__ __forceinline__ bool tile_info(const ViewSet &vs, const KCfg &cfg, co
   return true;
 }
 
+// Tile of queue slot q in persistent mode: descending-cost order when the
+// cost order is on, else row-major.
+__device__ __forceinline__ void tile_of_slot(const ViewSet &vs, const KCfg &cfg, const Ws &w, int q,
+                                             TileInfo &ti) {
+  ti.t = cfg.cost_order ? (int)w.order[q] : q;
+  ti.v = view_of_tile(vs, ti.t);
+  const int lt = ti.t - vs.v[ti.v].tile_base;
+  ti.tx = lt % vs.v[ti.v].tiles_x;
+  ti.ty = lt / vs.v[ti.v].tiles_x;
+}
+
+// Runs BODY(ti) for the workgroup's tile, or, in persistent mode, for tiles
+// taken from the atomic queue w.status[QSLOT] until it is exhausted (every
+// workgroup leaves when the queue passes the tile count).
+#define HTGS_FOR_TILES(QSLOT, BODY)                                              \
+  do {                                                                           \
+    if (!cfg.persistent) {                                                       \
+      TileInfo ti_;                                                              \
+      if (tile_info(vs, cfg, w, ti_)) BODY(ti_);                                 \
+    } else {                                                                     \
+      __shared__ int s_next_;                                                    \
+      for (;;) {                                                                 \
+        __syncthreads();                                                         \
+        if (threadIdx.x == 0) s_next_ = (int)atomicAdd(&w.status[QSLOT], 1u);    \
+        __syncthreads();                                                         \
+        const int q_ = s_next_;                                                  \
+        if (q_ >= vs.total_tiles) break;                                         \
+        TileInfo ti_;                                                            \
+        tile_of_slot(vs, cfg, w, q_, ti_);                                       \
+        BODY(ti_);                                                               \
+      }                                                                          \
+    }                                                                            \
+  } while (0)
+
 __device__ __forceinline__ bool rect_meets_block(const float *bb, int bx, int by) {
   return (__float_as_int(bb[2]) >= bx) && (__float_as_int(bb[0]) <= bx + 7) &&
          (__float_as_int(bb[3]) >= by) && (__float_as_int(bb[1]) <= by + 7);
@@ -125,11 +159,11 @@ __device__ __forceinline__ bool rect_meets_block(const float *bb, int bx, int by
 // ---------------------------------------------------------------------------
 // Forward
 // ---------------------------------------------------------------------------
-// EXACT: K == KMAX, known at compile time.
+// One tile. EXACT: K == KMAX, known at compile time.
 template <int KMAX, int TW, int TH, int BM, bool EXACT>
-__global__ void __launch_bounds__(TW *TH) k_raster_fwd(Ws w, ViewSet vs, KCfg cfg,
-                                                       float *__restrict__ state,
-                                                       const uint32_t *__restrict__ vals) {
+__device__ __forceinline__ void fwd_tile(const TileInfo &ti, const Ws &w, const ViewSet &vs,
+                                         const KCfg &cfg, float *__restrict__ state,
+                                         const uint32_t *__restrict__ vals) {
   constexpr int NT = TW * TH;
   constexpr int NBATCH = NT * BM;   // records staged per batch
   constexpr int NW = NT / 64;       // waves, one 8x8 block each
@@ -139,8 +173,6 @@ __global__ void __launch_bounds__(TW *TH) k_raster_fwd(Ws w, ViewSet vs, KCfg cf
   __shared__ uint16_t s_list[NW][NBATCH];
   __shared__ uint32_t s_nfrag;
 
-  TileInfo ti;
-  if (!tile_info(vs, cfg, w, ti)) return;
   const ViewParams &V = vs.v[ti.v];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int bx = (wave % BX) * 8, by = (wave / BX) * 8;
@@ -416,9 +448,9 @@ __device__ __forceinline__ void bwd_fragment(const float *st, const float *Pp, f
 }
 
 template <int KMAX, int TW, int TH, bool EXACT>
-__global__ void __launch_bounds__(256, (TW == 8 && KMAX <= 8) ? 5 : ((TW == 8 && KMAX <= 16) ? 4 : 1)) k_raster_bwd(Ws w, ViewSet vs, KCfg cfg,
-                                                    const float *__restrict__ state,
-                                                    const uint32_t *__restrict__ vals) {
+__device__ __forceinline__ void bwd_tile(const TileInfo &ti, const Ws &w, const ViewSet &vs,
+                                         const KCfg &cfg, const float *__restrict__ state,
+                                         const uint32_t *__restrict__ vals) {
   constexpr int NT = TW * TH;
   constexpr int NB = NT / 64;
   constexpr int BX = TW / 8;
@@ -428,8 +460,6 @@ __global__ void __launch_bounds__(256, (TW == 8 && KMAX <= 8) ? 5 : ((TW == 8 &&
   // index + 1 of the lane's instance at that pixel, 0 if not in the core
   __shared__ uint8_t s_slot[4][64][64];
 
-  TileInfo ti;
-  if (!tile_info(vs, cfg, w, ti)) return;
   const ViewParams &V = vs.v[ti.v];
   const int tid = threadIdx.x;
   const int px0 = ti.tx * TW, py0 = ti.ty * TH;
@@ -662,31 +692,68 @@ __global__ void __launch_bounds__(256, (TW == 8 && KMAX <= 8) ? 5 : ((TW == 8 &&
   }
 }
 
+template <int KMAX, int TW, int TH, int BM, bool EXACT>
+__global__ void __launch_bounds__(TW *TH) k_raster_fwd(Ws w, ViewSet vs, KCfg cfg,
+                                                       float *__restrict__ state,
+                                                       const uint32_t *__restrict__ vals) {
+#define HTGS_FWD_BODY(T) fwd_tile<KMAX, TW, TH, BM, EXACT>(T, w, vs, cfg, state, vals)
+  HTGS_FOR_TILES(kQueueFwd, HTGS_FWD_BODY);
+#undef HTGS_FWD_BODY
+}
+
+template <int KMAX, int TW, int TH, bool EXACT>
+__global__ void __launch_bounds__(256, (TW == 8 && KMAX <= 8) ? 5 : ((TW == 8 && KMAX <= 16) ? 4 : 1))
+    k_raster_bwd(Ws w, ViewSet vs, KCfg cfg, const float *__restrict__ state,
+                 const uint32_t *__restrict__ vals) {
+#define HTGS_BWD_BODY(T) bwd_tile<KMAX, TW, TH, EXACT>(T, w, vs, cfg, state, vals)
+  HTGS_FOR_TILES(kQueueBwd, HTGS_BWD_BODY);
+#undef HTGS_BWD_BODY
+}
+
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
+// Workgroups of a persistent launch: as many as can be resident at once.
+static int resident_blocks(const void *kernel, int threads, int tiles) {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      cus = 256;
+  }
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  const int n = per_cu * cus;
+  return n < tiles ? n : (tiles > 0 ? tiles : 1);
+}
 template <int KMAX, int TW, int TH, bool EXACT>
 static hipError_t fwd_launch(const Ws &w, const ViewSet &vs, const KCfg &cfg, float *state,
                              const uint32_t *vals, hipStream_t s) {
-  const int blocks = 8 * ((vs.total_tiles + 7) / 8);
+  int blocks = 8 * ((vs.total_tiles + 7) / 8);
   if constexpr (TW == 8) {
     if (cfg.batch_mult == 2) {
-      hipLaunchKernelGGL((k_raster_fwd<KMAX, TW, TH, 2, EXACT>), dim3(blocks), dim3(TW * TH), 0,
-                         s, w, vs, cfg, state, vals);
+      auto *kern = k_raster_fwd<KMAX, TW, TH, 2, EXACT>;
+      if (cfg.persistent) blocks = resident_blocks((const void *)kern, TW * TH, vs.total_tiles);
+      hipLaunchKernelGGL(kern, dim3(blocks), dim3(TW * TH), 0, s, w, vs, cfg, state, vals);
       return hipGetLastError();
     }
   }
-  hipLaunchKernelGGL((k_raster_fwd<KMAX, TW, TH, 1, EXACT>), dim3(blocks), dim3(TW * TH), 0, s,
-                     w, vs, cfg, state, vals);
+  auto *kern = k_raster_fwd<KMAX, TW, TH, 1, EXACT>;
+  if (cfg.persistent) blocks = resident_blocks((const void *)kern, TW * TH, vs.total_tiles);
+  hipLaunchKernelGGL(kern, dim3(blocks), dim3(TW * TH), 0, s, w, vs, cfg, state, vals);
   return hipGetLastError();
 }
 
 template <int KMAX, int TW, int TH, bool EXACT>
 static hipError_t bwd_launch(const Ws &w, const ViewSet &vs, const KCfg &cfg, const float *state,
                              const uint32_t *vals, hipStream_t s) {
-  const int blocks = 8 * ((vs.total_tiles + 7) / 8);
-  hipLaunchKernelGGL((k_raster_bwd<KMAX, TW, TH, EXACT>), dim3(blocks), dim3(256), 0, s, w, vs,
-                     cfg, state, vals);
+  int blocks = 8 * ((vs.total_tiles + 7) / 8);
+  auto *kern = k_raster_bwd<KMAX, TW, TH, EXACT>;
+  if (cfg.persistent) blocks = resident_blocks((const void *)kern, 256, vs.total_tiles);
+  hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), 0, s, w, vs, cfg, state, vals);
   return hipGetLastError();
 }
 

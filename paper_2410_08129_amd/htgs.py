@@ -21,6 +21,7 @@ HTGS_STATUS_SPIN_TIMEOUT = 2
 HTGS_FLAG_COST_ORDER = 1
 HTGS_FLAG_GRAD_OVERWRITE = 2
 HTGS_FLAG_TILE_CULL = 4
+HTGS_FLAG_PERSISTENT = 8
 MAX_VIEWS = 16
 
 EXPORTED = (
@@ -140,7 +141,8 @@ def config_struct(st) -> Config:
     c.lds_batch = int(getattr(st, "lds_batch", 0))
     c.flags = ((HTGS_FLAG_COST_ORDER if getattr(st, "cost_order", False) else 0)
                | (HTGS_FLAG_GRAD_OVERWRITE if getattr(st, "grad_overwrite", False) else 0)
-               | (HTGS_FLAG_TILE_CULL if getattr(st, "tile_cull", False) else 0))
+               | (HTGS_FLAG_TILE_CULL if getattr(st, "tile_cull", False) else 0)
+               | (HTGS_FLAG_PERSISTENT if getattr(st, "persistent", False) else 0))
     return c
 
 

@@ -55,7 +55,7 @@ def test_workspace_and_state_sizes():
 
 @pytest.mark.parametrize("field,value", [
     ("K", 33), ("K", -1), ("tile_w", 12), ("tau_alpha", 0.0), ("alpha_max", 1.0),
-    ("flags", 8), ("lds_batch", 7), ("lds_batch", 512),
+    ("flags", 16), ("lds_batch", 7), ("lds_batch", 512),
 ])
 def test_bad_config_rejected(field, value):
     sc, cams, st = _small()

@@ -44,15 +44,20 @@ def crop_1080p():
     return sc, cam, st, to_dev(sc), G
 
 
-@pytest.mark.parametrize("tile,lds_batch,cost_order,cull", [
-    (8, 128, False, False), (8, 0, True, False), (8, 128, True, False), (16, 0, True, False),
-    (8, 0, False, True), (16, 0, False, True),
+@pytest.mark.parametrize("tile,lds_batch,cost_order,cull,persist", [
+    (8, 128, False, False, False), (8, 0, True, False, False), (8, 128, True, False, False),
+    (16, 0, True, False, False), (8, 0, False, True, False), (16, 0, False, True, False),
+    (8, 0, False, False, True), (8, 0, True, False, True), (16, 0, True, False, True),
+    ((16, 8), 0, True, False, True),
 ])
-def test_schedule_options_bit_identical(crop_1080p, tile, lds_batch, cost_order, cull):
+def test_schedule_options_bit_identical(crop_1080p, tile, lds_batch, cost_order, cull, persist):
     sc, cam, st, params, G = crop_1080p
-    base = dataclasses.replace(st, tile_w=tile, tile_h=tile, lds_batch=0, cost_order=False)
-    var = dataclasses.replace(base, lds_batch=lds_batch, cost_order=cost_order, tile_cull=cull)
-    log(f"schedule tile={tile} lds_batch={lds_batch} cost_order={cost_order} cull={cull}")
+    tw, th = tile if isinstance(tile, tuple) else (tile, tile)
+    base = dataclasses.replace(st, tile_w=tw, tile_h=th, lds_batch=0, cost_order=False)
+    var = dataclasses.replace(base, lds_batch=lds_batch, cost_order=cost_order, tile_cull=cull,
+                              persistent=persist)
+    log(f"schedule tile={tile} lds_batch={lds_batch} cost_order={cost_order} cull={cull} "
+        f"persistent={persist}")
     f0, g0, p0 = fwd_bwd(params, sc.sh_degree, [cam], base, [G])
     f1, g1, p1 = fwd_bwd(params, sc.sh_degree, [cam], var, [G])
     assert torch.equal(f0.images[0], f1.images[0])
@@ -85,7 +90,7 @@ def test_graph_replay_matches_eager():
     sc, cams, st = scenes.workload_small()
     views = [cams[0], cams[0].crop(10, 20, 100, 60),
              scenes.look_at((1.5, -1.0, -2.5), (0, 0, 0), (0, -1, 0), 50.0, 90, 70)]
-    st = scenes.RenderSettings(K=4, tile_w=8, tile_h=8, cost_order=True)
+    st = scenes.RenderSettings(K=4, tile_w=8, tile_h=8, cost_order=True, persistent=True)
     params = to_dev(sc)
     n_inst = htgs.count_instances(params, sc.sh_degree, views, st)
     ws = htgs.alloc_workspace(sc.n, views, st, n_inst, torch.device("cuda"))
