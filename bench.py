@@ -109,6 +109,9 @@ def tune(params, sc, cams, st, args):
     from paper_2410_08129_amd import autotune
     if args.tile_cull != "auto":
         st = dataclasses.replace(st, tile_cull=(args.tile_cull == "on"))
+    if args.schedule:
+        st = autotune.apply(st, autotune.by_name(args.schedule))
+        return st, {"mode": "fixed", "best": args.schedule}
     if args.tile:
         st.tile_w = st.tile_h = args.tile
         return st, {"mode": "fixed"}
@@ -382,6 +385,8 @@ def main():
     ap.add_argument("--tile", type=int, default=0, help="fixed tile size (8 or 16), no autotune")
     ap.add_argument("--tile-cull", choices=("auto", "on", "off"), default="auto",
                     help="exact tile culling of small screen boxes (auto: the autotuner decides)")
+    ap.add_argument("--schedule", default="",
+                    help="fixed schedule by autotune name (e.g. tile8x8_batch1x_xcd_cull_queue)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-multiview", action="store_true")
     ap.add_argument("--forward-only", action="store_true")

@@ -46,6 +46,20 @@ def _key(n, cams, st, sh_degree):
             f"|K{st.K}|sh{sh_degree}")
 
 
+def candidate_name(cand):
+    return (f"tile{cand[0]}x{cand[1]}_batch{cand[2]}x_{'cost' if cand[3] else 'xcd'}"
+            f"{'_cull' if cand[4] else ''}{'_queue' if cand[5] else ''}")
+
+
+def by_name(name):
+    """The candidate called ``name`` (as in the tuning reports)."""
+    for cand in CANDIDATES:
+        if candidate_name(cand) == name:
+            return cand
+    raise KeyError(f"unknown schedule {name!r}; one of "
+                   + ", ".join(candidate_name(c) for c in CANDIDATES))
+
+
 def apply(st, cand):
     tw, th, mult, order, cull, persist = cand
     return dataclasses.replace(st, tile_w=tw, tile_h=th,
@@ -96,21 +110,20 @@ def tune(params, sh_degree, cams, st, steps=3, verbose=False, cull_choices=None)
     if mode == "cache" and key in cache:
         return apply(st, tuple(cache[key]["choice"])), {"mode": "cache", **cache[key]}
     times = {}
-    by_name = {}
+    named = {}
     for cand in CANDIDATES:
         if cand[0] * cand[1] > 128 and st.K > 16:
             continue
         if cull_choices is not None and cand[4] not in cull_choices:
             continue
         ms = _time_candidate(params, sh_degree, cams, apply(st, cand), steps)
-        name = (f"tile{cand[0]}x{cand[1]}_batch{cand[2]}x_{'cost' if cand[3] else 'xcd'}"
-                f"{'_cull' if cand[4] else ''}{'_queue' if cand[5] else ''}")
+        name = candidate_name(cand)
         times[name] = ms
-        by_name[name] = cand
+        named[name] = cand
         if verbose:
             print(f"autotune {name}: {ms:.3f} ms", flush=True)
     best = min(times, key=times.get)
-    choice = by_name[best]
+    choice = named[best]
     entry = {"choice": list(choice), "best": best, "ms": times}
     cache[key] = entry
     try:

@@ -184,16 +184,44 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_pass(Ws w, int pass, int 
   }
 }
 
+// Per-tile [start, end): each thread takes 8 consecutive sorted keys (one
+// or two 16-byte loads) plus the key before them, and marks the key changes.
 template <typename KeyT>
 __global__ void __launch_bounds__(256) k_ranges(Ws w, const KeyT *__restrict__ keys) {
   const unsigned long long tot = *w.total;
   if (tot > (unsigned long long)w.capacity) return;  // overflow: every tile stays empty
   const uint64_t I = tot;
+  const uint64_t ngroups = (I + 7) / 8;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < I; i += stride) {
-    const uint32_t k = keys[i];
-    if (i == 0 || (uint32_t)keys[i - 1] != k) w.ranges[k].x = (uint32_t)i;
-    if (i + 1 == I || (uint32_t)keys[i + 1] != k) w.ranges[k].y = (uint32_t)(i + 1);
+  for (uint64_t gi = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; gi < ngroups; gi += stride) {
+    const uint64_t i0 = gi * 8;
+    uint32_t k[8];
+    if (i0 + 8 <= I) {
+      if constexpr (sizeof(KeyT) == 2) {
+        const uint4 t = *reinterpret_cast<const uint4 *>(keys + i0);
+        const uint32_t u[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) { k[2 * j] = u[j] & 0xffffu; k[2 * j + 1] = u[j] >> 16; }
+      } else {
+        const uint4 a = *reinterpret_cast<const uint4 *>(keys + i0);
+        const uint4 b = *reinterpret_cast<const uint4 *>(keys + i0 + 4);
+        k[0] = a.x; k[1] = a.y; k[2] = a.z; k[3] = a.w; k[4] = b.x; k[5] = b.y; k[6] = b.z; k[7] = b.w;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) k[j] = (i0 + j < I) ? (uint32_t)keys[i0 + j] : 0u;
+    }
+    uint32_t prev = i0 > 0 ? (uint32_t)keys[i0 - 1] : 0xffffffffu;
+    const uint32_t next = (i0 + 8 < I) ? (uint32_t)keys[i0 + 8] : 0xffffffffu;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const uint64_t i = i0 + j;
+      if (i >= I) break;
+      const uint32_t nk = (j < 7 && i + 1 < I) ? k[j + 1] : (j == 7 ? next : 0xffffffffu);
+      if (i == 0 || k[j] != prev) w.ranges[k[j]].x = (uint32_t)i;
+      if (i + 1 == I || k[j] != nk) w.ranges[k[j]].y = (uint32_t)(i + 1);
+      prev = k[j];
+    }
   }
 }
 
@@ -205,22 +233,42 @@ __device__ __forceinline__ uint32_t cost_bucket(uint2 r) {
   return c == 0 ? 31u : (uint32_t)__clz(c) - 1u;
 }
 
+// Counting sort of the tiles by bucket: each workgroup counts its tiles in
+// LDS and adds one total per bucket to the global histogram; the placing
+// pass reserves one run per (workgroup, bucket) with one atomic and fills
+// it from LDS cursors.
 __global__ void __launch_bounds__(256) k_tile_order_count(Ws w, int total_tiles) {
+  __shared__ uint32_t s_cnt[32];
+  if (threadIdx.x < 32) s_cnt[threadIdx.x] = 0u;
+  __syncthreads();
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < total_tiles; t += gridDim.x * blockDim.x)
-    atomicAdd(&w.order_hist[cost_bucket(w.ranges[t])], 1u);
+    atomicAdd(&s_cnt[cost_bucket(w.ranges[t])], 1u);
+  __syncthreads();
+  if (threadIdx.x < 32 && s_cnt[threadIdx.x]) atomicAdd(&w.order_hist[threadIdx.x], s_cnt[threadIdx.x]);
 }
 
 __global__ void __launch_bounds__(256) k_tile_order_place(Ws w, int total_tiles) {
-  __shared__ uint32_t s_base[32];
+  __shared__ uint32_t s_base[32], s_cnt[32], s_run[32];
   if (threadIdx.x < 32) {
     uint32_t b = 0;
     for (uint32_t k = 0; k < threadIdx.x; ++k) b += w.order_hist[k];
     s_base[threadIdx.x] = b;
+    s_cnt[threadIdx.x] = 0u;
+  }
+  __syncthreads();
+  // this workgroup's tiles: same grid-stride set as the counting pass
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < total_tiles; t += gridDim.x * blockDim.x)
+    atomicAdd(&s_cnt[cost_bucket(w.ranges[t])], 1u);
+  __syncthreads();
+  if (threadIdx.x < 32) {
+    const uint32_t c = s_cnt[threadIdx.x];
+    s_run[threadIdx.x] = c ? s_base[threadIdx.x] + atomicAdd(&w.order_hist[32 + threadIdx.x], c) : 0u;
+    s_cnt[threadIdx.x] = 0u;
   }
   __syncthreads();
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < total_tiles; t += gridDim.x * blockDim.x) {
     const uint32_t b = cost_bucket(w.ranges[t]);
-    w.order[s_base[b] + atomicAdd(&w.order_hist[32 + b], 1u)] = (uint32_t)t;
+    w.order[s_run[b] + atomicAdd(&s_cnt[b], 1u)] = (uint32_t)t;
   }
 }
 
@@ -253,7 +301,7 @@ static hipError_t sort_impl(const Ws &w, hipStream_t s) {
 template <typename KeyT>
 static hipError_t ranges_impl(const Ws &w, hipStream_t s) {
   const KeyT *sorted = reinterpret_cast<const KeyT *>(w.keys[w.passes & 1]);
-  int rb = (int)((w.capacity + 255) / 256);
+  int rb = (int)((w.capacity + 8 * 256 - 1) / (8 * 256));
   if (rb < 1) rb = 1;
   if (rb > 8192) rb = 8192;
   hipLaunchKernelGGL(k_ranges<KeyT>, dim3(rb), dim3(256), 0, s, w, sorted);
