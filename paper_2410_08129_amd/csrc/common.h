@@ -109,7 +109,7 @@ struct Ws {
   uint32_t *order;             // [total_tiles] tiles by descending instance count
   float *records;              // [views][n][32]
   int4 *rects;                 // [views][n] tile rect (tx0, ty0, tx1, ty1), empty if tx0 > tx1
-  unsigned long long *masks;   // [views][n] surviving tiles of the rect (row-major bits), 0 = all
+  uint4 *tslots;               // [views][n] tile-slot descriptor (see below)
   uint32_t *offsets;           // [n] first instance slot of each Gaussian
   void *keys[2];
   uint32_t *vals[2];
@@ -149,6 +149,14 @@ __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
 // Instances of one (view, Gaussian): the rect's tiles, or the surviving
 // ones when a tile mask is set.
+// Tile-slot descriptor of one (view, Gaussian): x = first instance slot
+// (offset of the Gaussian plus the counts of its earlier views), y = tile
+// rect origin and width packed as tx0 | ty0 << 10 | width << 20, (z, w) =
+// the 64-bit mask of surviving tiles of the rect (row-major bits, 0 = all).
+__device__ __forceinline__ unsigned long long tslot_mask(uint4 d) {
+  return (unsigned long long)d.z | ((unsigned long long)d.w << 32);
+}
+
 __device__ __forceinline__ int tile_count(int4 r, unsigned long long mask) {
   if (r.x > r.z || r.y > r.w) return 0;
   return mask ? __popcll(mask) : (r.z - r.x + 1) * (r.w - r.y + 1);
@@ -158,6 +166,11 @@ __device__ __forceinline__ int tile_count(int4 r, unsigned long long mask) {
 // (view, Gaussian).
 __device__ __forceinline__ uint32_t tile_rank(int idx, unsigned long long mask) {
   return mask ? (uint32_t)__popcll(mask & ((1ull << idx) - 1ull)) : (uint32_t)idx;
+}
+
+__device__ __forceinline__ uint32_t tslot_slot(uint4 d, int tx, int ty) {
+  const int x0 = (int)(d.y & 1023u), y0 = (int)((d.y >> 10) & 1023u), wdt = (int)(d.y >> 20);
+  return d.x + tile_rank((ty - y0) * wdt + (tx - x0), tslot_mask(d));
 }
 
 // Tile coverage rule shared by the forward and backward launchers: tile ids

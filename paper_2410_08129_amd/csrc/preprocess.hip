@@ -227,11 +227,13 @@ __device__ inline unsigned long long cull_mask(const Conic &c, int4 rect, int tw
 
 // One Gaussian in one view: cull, box, rect, record. Returns the instance
 // count and writes the tile rect (and the record if the count is non-zero);
-// *packed receives tx0 | ty0 << 10 | width << 20 of a non-empty rect.
+// *packed receives tx0 | ty0 << 10 | width << 20 of a non-empty rect and
+// *mask the surviving tiles of the rect (0 = all).
 template <int DEG, bool CULL>
 __device__ inline uint32_t preprocess_view(const GaussPtrs &gp, const KCfg &cfg,
                                            const ViewParams &V, const Ws &w, int v,
-                                           int64_t g, const Activated &a, uint32_t *packed) {
+                                           int64_t g, const Activated &a, uint32_t *packed,
+                                           unsigned long long *mask_out) {
   double Rv[3][3], mv[3];
   view_rows(V, a, Rv, mv);
   const double fx = V.fx, fy = V.fy, cx = V.cx, cy = V.cy;
@@ -275,7 +277,7 @@ __device__ inline uint32_t preprocess_view(const GaussPtrs &gp, const KCfg &cfg,
   const int64_t vg = (int64_t)v * cfg.n + g;
   if (count == 0) {
     w.rects[vg] = rect;
-    w.masks[vg] = 0ull;
+    *mask_out = 0ull;
     return 0;
   }
 
@@ -363,7 +365,7 @@ __device__ inline uint32_t preprocess_view(const GaussPtrs &gp, const KCfg &cfg,
   }
   if (count == 0) rect = make_int4(1, 1, 0, 0);
   w.rects[vg] = rect;
-  w.masks[vg] = mask;
+  *mask_out = mask;
   if (count) {
     *packed =
         (uint32_t)rect.x | ((uint32_t)rect.y << 10) | ((uint32_t)(rect.z - rect.x + 1) << 20);
@@ -406,10 +408,11 @@ __global__ void __launch_bounds__(kPreThreads) k_preprocess(GaussPtrs gp, KCfg c
     activate(gp, g, a);
     for (int v = 0; v < nviews; ++v) {
       uint32_t packed = 0;
-      const uint32_t c = preprocess_view<DEG, CULL>(gp, cfg, vs.v[v], w, v, g, a, &packed);
+      unsigned long long mk = 0ull;
+      const uint32_t c = preprocess_view<DEG, CULL>(gp, cfg, vs.v[v], w, v, g, a, &packed, &mk);
       s_vcnt[v][tid] = c;
       s_vrect[v][tid] = packed;
-      s_vmask[v][tid] = c ? w.masks[(int64_t)v * cfg.n + g] : 0ull;
+      s_vmask[v][tid] = c ? mk : 0ull;
       total += c;
     }
   } else {
@@ -481,7 +484,22 @@ __global__ void __launch_bounds__(kPreThreads) k_preprocess(GaussPtrs gp, KCfg c
   }
   __syncthreads();
   const unsigned long long base = s_base;
-  if (g < cfg.n) w.offsets[g] = (uint32_t)(base + s_excl[tid]);
+  if (g < cfg.n) {
+    const unsigned long long first = base + s_excl[tid];
+    w.offsets[g] = (uint32_t)first;
+    // Tile-slot descriptors: first slot of each view's instances, clamped
+    // at 2^31 so that base + rank cannot wrap (slots at or past the
+    // capacity are never written).
+    unsigned long long sv = first;
+    for (int v = 0; v < nviews; ++v) {
+      const uint32_t c = s_vcnt[v][tid];
+      const unsigned long long m = s_vmask[v][tid];
+      w.tslots[(int64_t)v * cfg.n + g] =
+          make_uint4((uint32_t)min(sv, 0x80000000ull), c ? s_vrect[v][tid] : 0u, (uint32_t)m,
+                     (uint32_t)(m >> 32));
+      sv += c;
+    }
+  }
 
   // Emit instances, one per loop iteration, balanced over the workgroup.
   uint16_t *k16 = reinterpret_cast<uint16_t *>(w.keys[0]);
@@ -801,7 +819,8 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(GaussPtrs gp, GradPtrs g
   uint32_t total = 0;
   const int nviews = MV ? vs.n : 1;
   for (int v = 0; v < nviews; ++v)
-    total += (uint32_t)tile_count(w.rects[(int64_t)v * cfg.n + g], w.masks[(int64_t)v * cfg.n + g]);
+    total += (uint32_t)tile_count(w.rects[(int64_t)v * cfg.n + g],
+                                  tslot_mask(w.tslots[(int64_t)v * cfg.n + g]));
   const unsigned long long I = *w.total;
   const uint32_t first = total ? w.offsets[g] : 0u;
   // No instance in any view (or an overflowed forward, which the status
@@ -831,7 +850,8 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(GaussPtrs gp, GradPtrs g
   uint32_t sa = first;
   for (int v = 0; v < nviews; ++v) {
     const uint32_t cnt =
-        (uint32_t)tile_count(w.rects[(int64_t)v * cfg.n + g], w.masks[(int64_t)v * cfg.n + g]);
+        (uint32_t)tile_count(w.rects[(int64_t)v * cfg.n + g],
+                             tslot_mask(w.tslots[(int64_t)v * cfg.n + g]));
     if (cnt == 0) continue;
     const uint32_t sb = sa + cnt;
     float acc[22];

@@ -565,14 +565,7 @@ __device__ __forceinline__ void bwd_tile(const TileInfo &ti, const Ws &w, const 
       float rec[kRecFloats];
       load_record(recs, gid, rec);
       stage_record(rec, px0, py0, j - rg.x, st);
-      uint32_t pre = 0;
-      for (int u = 0; u < ti.v; ++u)
-        pre += (uint32_t)tile_count(w.rects[(int64_t)u * cfg.n + gid],
-                                    w.masks[(int64_t)u * cfg.n + gid]);
-      const int4 r = w.rects[(int64_t)ti.v * cfg.n + gid];
-      const unsigned long long mk = w.masks[(int64_t)ti.v * cfg.n + gid];
-      slot = w.offsets[gid] + pre +
-             tile_rank((ti.ty - r.y) * (r.z - r.x + 1) + (ti.tx - r.x), mk);
+      slot = tslot_slot(w.tslots[(int64_t)ti.v * cfg.n + gid], ti.tx, ti.ty);
     }
     // acc: d-moments (6), m-moments (6), dL/do, dL/drgb (3)
     float acc[16];
