@@ -208,7 +208,8 @@ int htgs_read_status(const void *ws, int64_t ws_bytes, uint32_t *flags_out,
  * Host-side state, not thread-safe; keep it disabled during graph capture. */
 enum {
   HTGS_STAGE_FILL = 0, HTGS_STAGE_PREPROCESS = 1, HTGS_STAGE_SORT = 2, HTGS_STAGE_RANGES = 3,
-  HTGS_STAGE_RASTER_FWD = 4, HTGS_STAGE_RASTER_BWD = 5, HTGS_STAGE_REDUCE = 6,
+  HTGS_STAGE_RASTER_FWD = 4, HTGS_STAGE_RASTER_BWD = 5,
+  HTGS_STAGE_REDUCE = 6, /* kept for numbering; no separate reduction pass is launched */
   HTGS_STAGE_PREPROCESS_BWD = 7, HTGS_NUM_STAGES = 8
 };
 int htgs_profile_enable(int on);

@@ -13,7 +13,6 @@ hipError_t launch_preprocess(const GaussPtrs &gp, const KCfg &cfg, const ViewSet
                              hipStream_t s);
 hipError_t launch_preprocess_bwd(const GaussPtrs &gp, const GradPtrs &gr, const KCfg &cfg,
                                  const ViewSet &vs, const Ws &w, hipStream_t s);
-hipError_t launch_segment_reduce(const Ws &w, hipStream_t s);
 hipError_t launch_sort_passes(const Ws &w, hipStream_t s);
 hipError_t launch_ranges(const Ws &w, hipStream_t s);
 hipError_t launch_tile_order(const Ws &w, int total_tiles, hipStream_t s);
@@ -31,7 +30,7 @@ int64_t align_up(int64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
   int64_t status, total, pp_look, hist, sort_look, ranges, order_hist, zero_end;
-  int64_t records, rects, offsets, tslots, order, keys0, keys1, vals0, vals1, partials, bytes;
+  int64_t records, rects, tslots, order, keys0, keys1, vals0, vals1, partials, bytes;
   int64_t capacity, max_chunks;
   int32_t key_bits, passes, key16;
 };
@@ -61,7 +60,6 @@ Layout make_layout(int64_t n, int n_views, int64_t total_tiles, int64_t capacity
   L.zero_end = o;
   L.records = o; o = align_up(o + (int64_t)n_views * n * kRecFloats * 4);
   L.rects = o; o = align_up(o + (int64_t)n_views * n * 16);
-  L.offsets = o; o = align_up(o + 4 * n);
   L.tslots = o; o = align_up(o + (int64_t)n_views * n * 16);
   L.order = o; o = align_up(o + 4 * total_tiles);
   L.keys0 = o; o = align_up(o + kb * capacity);
@@ -99,7 +97,6 @@ Ws make_ws(void *base, const Layout &L) {
   w.order = reinterpret_cast<uint32_t *>(b + L.order);
   w.records = reinterpret_cast<float *>(b + L.records);
   w.rects = reinterpret_cast<int4 *>(b + L.rects);
-  w.offsets = reinterpret_cast<uint32_t *>(b + L.offsets);
   w.tslots = reinterpret_cast<uint4 *>(b + L.tslots);
   w.keys[0] = b + L.keys0;
   w.keys[1] = b + L.keys1;
@@ -364,13 +361,8 @@ int backward_impl(const htgs_gaussians *g, const htgs_camera *cams, int32_t n_vi
       HIP_TRY(launch_fill_zero(static_cast<char *>(ws) + L.status + 4 * kQueueBwd, 16, s));
     HIP_TRY(launch_raster_bwd(w, vs, k, static_cast<const float *>(state), w.vals[w.final_buf], s));
   }
-  // With several views the instance partials are summed per (Gaussian,
-  // view) by a separate pass; with one view the preprocess backward sums
-  // them itself.
-  if (cap > 0 && n_views > 1) {
-    StageTimer t(HTGS_STAGE_REDUCE, s);
-    HIP_TRY(launch_segment_reduce(w, s));
-  }
+  // The preprocess backward sums the instance partials per (Gaussian, view)
+  // itself.
   const GradPtrs gr{grads->means, grads->log_scales, grads->quats, grads->opacity_logits,
                     grads->sh};
   StageTimer t(HTGS_STAGE_PREPROCESS_BWD, s);

@@ -110,7 +110,6 @@ struct Ws {
   float *records;              // [views][n][32]
   int4 *rects;                 // [views][n] tile rect (tx0, ty0, tx1, ty1), empty if tx0 > tx1
   uint4 *tslots;               // [views][n] tile-slot descriptor (see below)
-  uint32_t *offsets;           // [n] first instance slot of each Gaussian
   void *keys[2];
   uint32_t *vals[2];
   float *partials;             // [capacity][24]

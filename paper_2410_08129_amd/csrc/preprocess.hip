@@ -385,9 +385,8 @@ template <int DEG, bool MV, bool CULL>
 __global__ void __launch_bounds__(kPreThreads) k_preprocess(GaussPtrs gp, KCfg cfg, ViewSet vs,
                                                              Ws w) {
   __shared__ uint32_t s_ticket;
-  __shared__ uint32_t s_excl[kPreThreads + 1];
   constexpr int NVL = MV ? kMaxViews : 1;
-  __shared__ uint32_t s_vcnt[NVL][kPreThreads];
+  __shared__ uint32_t s_start[NVL * kPreThreads + 1];
   __shared__ uint32_t s_vrect[NVL][kPreThreads];
   __shared__ unsigned long long s_vmask[NVL][kPreThreads];
   __shared__ uint32_t s_hist[4][256];
@@ -402,7 +401,12 @@ __global__ void __launch_bounds__(kPreThreads) k_preprocess(GaussPtrs gp, KCfg c
   const int64_t g = blk * kPreThreads + tid;
   const int nviews = MV ? vs.n : 1;
 
-  uint32_t total = 0;
+  // Slot layout: the workgroup's 64-Gaussian groups (one per wave) in
+  // order; inside a group view by view, inside a view Gaussian by Gaussian,
+  // inside a (view, Gaussian) tile by tile. s_start holds the workgroup-
+  // relative first slot of every (group, view, lane), in slot order, plus
+  // the workgroup total at the end; it first holds the counts.
+  const int lane = tid & 63, wave = tid >> 6;
   if (g < cfg.n) {
     Activated a;
     activate(gp, g, a);
@@ -410,32 +414,41 @@ __global__ void __launch_bounds__(kPreThreads) k_preprocess(GaussPtrs gp, KCfg c
       uint32_t packed = 0;
       unsigned long long mk = 0ull;
       const uint32_t c = preprocess_view<DEG, CULL>(gp, cfg, vs.v[v], w, v, g, a, &packed, &mk);
-      s_vcnt[v][tid] = c;
+      s_start[(wave * nviews + v) * 64 + lane] = c;
       s_vrect[v][tid] = packed;
       s_vmask[v][tid] = c ? mk : 0ull;
-      total += c;
     }
   } else {
-    for (int v = 0; v < nviews; ++v) s_vcnt[v][tid] = 0u;
+    for (int v = 0; v < nviews; ++v) s_start[(wave * nviews + v) * 64 + lane] = 0u;
   }
 
-  // Workgroup exclusive scan of the counts.
-  const int lane = tid & 63, wave = tid >> 6;
-  uint32_t x = total;
+  // Group-relative starts: a wave scan per view, the views one after
+  // another (each lane reads and writes only its own entries).
+  uint32_t gsum = 0;
+  for (int v = 0; v < nviews; ++v) {
+    uint32_t *e = &s_start[(wave * nviews + v) * 64 + lane];
+    const uint32_t c = *e;
+    uint32_t x = c;
 #pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const uint32_t y = __shfl_up(x, off, 64);
-    if (lane >= off) x += y;
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t y = __shfl_up(x, off, 64);
+      if (lane >= off) x += y;
+    }
+    *e = gsum + x - c;
+    gsum += (uint32_t)__shfl(x, 63, 64);
   }
-  if (lane == 63) s_wsum[wave] = x;
+  if (lane == 0) s_wsum[wave] = gsum;
   __syncthreads();
-  uint32_t woff = 0;
-  for (int k = 0; k < wave; ++k) woff += s_wsum[k];
-  const uint32_t incl = x + woff;
-  s_excl[tid] = incl - total;
-  if (tid == kPreThreads - 1) s_excl[kPreThreads] = incl;
+  uint32_t goff = 0, block_total = 0;
+#pragma unroll
+  for (int k = 0; k < kPreThreads / 64; ++k) {
+    if (k < wave) goff += s_wsum[k];
+    block_total += s_wsum[k];
+  }
+  for (int v = 0; v < nviews; ++v) s_start[(wave * nviews + v) * 64 + lane] += goff;
+  const int nent = kPreThreads * nviews;
+  if (tid == 0) s_start[nent] = block_total;
   __syncthreads();
-  const uint32_t block_total = s_excl[kPreThreads];
 
   // Decoupled look-back across workgroups (in ticket order).
   if (tid == 0) {
@@ -485,19 +498,16 @@ __global__ void __launch_bounds__(kPreThreads) k_preprocess(GaussPtrs gp, KCfg c
   __syncthreads();
   const unsigned long long base = s_base;
   if (g < cfg.n) {
-    const unsigned long long first = base + s_excl[tid];
-    w.offsets[g] = (uint32_t)first;
-    // Tile-slot descriptors: first slot of each view's instances, clamped
+    // Tile-slot descriptors: first slot of each (view, Gaussian), clamped
     // at 2^31 so that base + rank cannot wrap (slots at or past the
     // capacity are never written).
-    unsigned long long sv = first;
     for (int v = 0; v < nviews; ++v) {
-      const uint32_t c = s_vcnt[v][tid];
+      const int f = (wave * nviews + v) * 64 + lane;
+      const uint32_t c = s_start[f + 1] - s_start[f];
       const unsigned long long m = s_vmask[v][tid];
       w.tslots[(int64_t)v * cfg.n + g] =
-          make_uint4((uint32_t)min(sv, 0x80000000ull), c ? s_vrect[v][tid] : 0u, (uint32_t)m,
-                     (uint32_t)(m >> 32));
-      sv += c;
+          make_uint4((uint32_t)min(base + s_start[f], 0x80000000ull), c ? s_vrect[v][tid] : 0u,
+                     (uint32_t)m, (uint32_t)(m >> 32));
     }
   }
 
@@ -505,24 +515,21 @@ __global__ void __launch_bounds__(kPreThreads) k_preprocess(GaussPtrs gp, KCfg c
   uint16_t *k16 = reinterpret_cast<uint16_t *>(w.keys[0]);
   uint32_t *k32 = reinterpret_cast<uint32_t *>(w.keys[0]);
   for (uint32_t e = tid; e < block_total; e += kPreThreads) {
-    int lo = 0, hi = kPreThreads;
+    // the last (group, view, lane) entry starting at or before e owns it
+    int lo = 0, hi = nent;
     while (hi - lo > 1) {
       const int mid = (lo + hi) >> 1;
-      if (s_excl[mid] <= e) lo = mid; else hi = mid;
+      if (s_start[mid] <= e) lo = mid; else hi = mid;
     }
-    uint32_t rank = e - s_excl[lo];
-    int v = 0;
-    if constexpr (MV) {
-      while (rank >= s_vcnt[v][lo]) {
-        rank -= s_vcnt[v][lo];
-        ++v;
-      }
-    }
-    const int64_t gi = blk * kPreThreads + lo;
-    const uint32_t pr = s_vrect[v][lo];
+    uint32_t rank = e - s_start[lo];
+    const int grp = lo / (64 * nviews);
+    const int v = MV ? (lo >> 6) - grp * nviews : 0;
+    const int owner = grp * 64 + (lo & 63);
+    const int64_t gi = blk * kPreThreads + owner;
+    const uint32_t pr = s_vrect[v][owner];
     const uint32_t rw = pr >> 20;
     // With a tile mask, the rank-th surviving tile is the rank-th set bit.
-    const unsigned long long mk = s_vmask[v][lo];
+    const unsigned long long mk = s_vmask[v][owner];
     if (mk) {
       unsigned long long m = mk;
       uint32_t pos = 0, k = rank;
@@ -591,55 +598,6 @@ __device__ __forceinline__ void seg_scan_step(uint32_t seg, float *v) {
     const float y = __int_as_float(
         __builtin_amdgcn_update_dpp(0, __float_as_int(v[k]), CTRL, ROW_MASK, 0xf, false));
     v[k] += take ? y : 0.f;
-  }
-}
-
-// In-place segmented reduction of the per-instance partials. Slots are
-// processed in 64-aligned blocks, one lane each; a segment is the run of
-// slots of one (Gaussian, view). After the launch, the last slot of every
-// segment portion inside a block holds the sum of that portion. The scan
-// tree is fixed, so the result is deterministic.
-__global__ void __launch_bounds__(256) k_segment_reduce(Ws w) {
-  const unsigned long long tot = *w.total;
-  if (tot > (unsigned long long)w.capacity) return;
-  const uint64_t first = (uint64_t)blockIdx.x * blockDim.x;
-  if (first >= tot) return;
-  const uint64_t s = first + threadIdx.x;
-  const int lane = threadIdx.x & 63;
-  const bool valid = s < tot;
-  float v[22];
-  uint32_t seg = 0xffffffffu;
-  float4 *slot = reinterpret_cast<float4 *>(w.partials + (int64_t)s * kPartialFloats);
-  if (valid) {
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      const float4 t = slot[k];
-      v[4 * k] = t.x; v[4 * k + 1] = t.y; v[4 * k + 2] = t.z; v[4 * k + 3] = t.w;
-    }
-    const float4 t = slot[5];
-    v[20] = t.x; v[21] = t.y;
-    seg = __float_as_uint(t.z);
-  } else {
-#pragma unroll
-    for (int k = 0; k < 22; ++k) v[k] = 0.f;
-  }
-  // Inclusive segmented scan over the wave with DPP lane moves (no LDS):
-  // shifts by 1, 2, 4, 8 inside each row of 16 lanes, then the last lane of
-  // row 0 / row 2 into rows 1 / 3, then lane 31 into rows 2 and 3. A lane
-  // adds the moved value only if it comes from its own segment (segments
-  // are runs of consecutive slots, so equal ids mean one run).
-  seg_scan_step<0x111, 0xf>(seg, v);   // row_shr:1
-  seg_scan_step<0x112, 0xf>(seg, v);   // row_shr:2
-  seg_scan_step<0x114, 0xf>(seg, v);   // row_shr:4
-  seg_scan_step<0x118, 0xf>(seg, v);   // row_shr:8
-  seg_scan_step<0x142, 0xa>(seg, v);   // row_bcast:15 into rows 1, 3
-  seg_scan_step<0x143, 0xc>(seg, v);   // row_bcast:31 into rows 2, 3
-  const uint32_t sn = __shfl_down(seg, 1, 64);
-  const bool end = valid && (lane == 63 || sn != seg || s + 1 == tot);
-  if (end) {
-#pragma unroll
-    for (int k = 0; k < 5; ++k) slot[k] = make_float4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
-    slot[5] = make_float4(v[20], v[21], __uint_as_float(seg), 0.f);
   }
 }
 
@@ -755,90 +713,35 @@ __device__ __forceinline__ void sh_backward(const float *wsv, const double dir[3
 }
 
 
-// FUSED (one view only): each wave owns 64 consecutive Gaussians, whose
-// instance slots are one contiguous range; the wave walks that range 64
-// slots at a time with the segmented scan and adds each segment's sum for
-// the chunk into its owner's LDS column, so the partials are read once,
-// coalesced, and no separate reduction pass is needed. Otherwise the sums
-// come from the block-portion sums of k_segment_reduce.
-template <int DEG, bool MV, bool FUSED>
+// Each wave owns 64 consecutive Gaussians (one slot group: their instance
+// slots are one contiguous range, view by view). For each view the wave
+// walks that view's part of the range 64 slots at a time with the
+// segmented scan and adds each segment's sum into its owner's LDS column,
+// so the partials are read once, coalesced; then every lane turns its
+// Gaussian's sums for the view into parameter gradients.
+template <int DEG, bool MV>
 __global__ void __launch_bounds__(256) k_preprocess_bwd(GaussPtrs gp, GradPtrs gr, KCfg cfg,
                                                          ViewSet vs, Ws w) {
-  static_assert(!(MV && FUSED), "the fused sum covers one view");
   constexpr int NB = (DEG + 1) * (DEG + 1);
+  __shared__ float s_acc[4][22][64];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  __shared__ float s_acc[FUSED ? 4 : 1][22][64];
-  if constexpr (FUSED) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t g0 = g - lane;
-    if (g0 >= cfg.n) return;  // uniform over the wave
-#pragma unroll
-    for (int k = 0; k < 22; ++k) s_acc[wave][k][lane] = 0.f;
-    const unsigned long long I = *w.total;
-    if (I <= (unsigned long long)w.capacity) {
-      const uint64_t s_begin = w.offsets[g0];
-      const uint64_t s_end = (g0 + 64 < cfg.n) ? (uint64_t)w.offsets[g0 + 64] : (uint64_t)I;
-      for (uint64_t base = s_begin; base < s_end; base += 64) {
-        const uint64_t sl = base + lane;
-        const bool valid = sl < s_end;
-        float v[22];
-        uint32_t seg = 0xffffffffu;
-        if (valid) {
-          const float4 *P = reinterpret_cast<const float4 *>(w.partials + (int64_t)sl * kPartialFloats);
-#pragma unroll
-          for (int k = 0; k < 5; ++k) {
-            const float4 t = P[k];
-            v[4 * k] = t.x; v[4 * k + 1] = t.y; v[4 * k + 2] = t.z; v[4 * k + 3] = t.w;
-          }
-          const float4 t = P[5];
-          v[20] = t.x; v[21] = t.y;
-          seg = __float_as_uint(t.z);
-        } else {
-#pragma unroll
-          for (int k = 0; k < 22; ++k) v[k] = 0.f;
-        }
-        seg_scan_step<0x111, 0xf>(seg, v);
-        seg_scan_step<0x112, 0xf>(seg, v);
-        seg_scan_step<0x114, 0xf>(seg, v);
-        seg_scan_step<0x118, 0xf>(seg, v);
-        seg_scan_step<0x142, 0xa>(seg, v);
-        seg_scan_step<0x143, 0xc>(seg, v);
-        const uint32_t sn = __shfl_down(seg, 1, 64);
-        const bool end = valid && (lane == 63 || sn != seg || sl + 1 == s_end);
-        if (end) {
-          const int owner = (int)((int64_t)(seg & ((1u << 27) - 1u)) - g0);
-#pragma unroll
-          for (int k = 0; k < 22; ++k) s_acc[wave][k][owner] += v[k];
-        }
-        __builtin_amdgcn_wave_barrier();
-      }
-    }
-    __builtin_amdgcn_wave_barrier();
-  }
-  if (g >= cfg.n) return;
-  uint32_t total = 0;
+  const int64_t g0 = g - lane;
+  if (g0 >= cfg.n) return;  // uniform over the wave
+  const bool live = g < cfg.n;
   const int nviews = MV ? vs.n : 1;
-  for (int v = 0; v < nviews; ++v)
-    total += (uint32_t)tile_count(w.rects[(int64_t)v * cfg.n + g],
-                                  tslot_mask(w.tslots[(int64_t)v * cfg.n + g]));
   const unsigned long long I = *w.total;
-  const uint32_t first = total ? w.offsets[g] : 0u;
-  // No instance in any view (or an overflowed forward, which the status
-  // word reports): zero gradient.
-  if (total == 0 || I > (unsigned long long)w.capacity ||
-      (unsigned long long)first + total > I) {
-    if (cfg.grad_overwrite) {
-      const float z[4] = {0.f, 0.f, 0.f, 0.f};
-      float zsh[3 * NB];
-#pragma unroll
-      for (int k = 0; k < 3 * NB; ++k) zsh[k] = 0.f;
-      emit_grads<NB>(gr, g, z, z, z, 0.f, zsh, true);
-    }
-    return;
-  }
+  // An overflowed forward (reported by the status word) leaves no usable
+  // partials: zero gradient.
+  const bool ok = I <= (unsigned long long)w.capacity;
+  uint32_t total = 0;
+  if (live && ok)
+    for (int v = 0; v < nviews; ++v)
+      total += (uint32_t)tile_count(w.rects[(int64_t)v * cfg.n + g],
+                                    tslot_mask(w.tslots[(int64_t)v * cfg.n + g]));
 
   Activated a;
-  activate(gp, g, a);
+  if (total) activate(gp, g, a);
   double gA[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
   double gmu[3] = {0, 0, 0};
   double go = 0.0;
@@ -847,92 +750,134 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(GaussPtrs gp, GradPtrs g
   for (int k = 0; k < 3 * NB; ++k) gsh[k] = 0.f;
   const float *shrow = gp.sh + g * NB * 3;
 
-  uint32_t sa = first;
-  for (int v = 0; v < nviews; ++v) {
-    const uint32_t cnt =
-        (uint32_t)tile_count(w.rects[(int64_t)v * cfg.n + g],
-                             tslot_mask(w.tslots[(int64_t)v * cfg.n + g]));
-    if (cnt == 0) continue;
-    const uint32_t sb = sa + cnt;
-    float acc[22];
+  if (ok && __ballot(total != 0) != 0ull) {
+    const uint64_t group_end = (g0 + 64 < cfg.n) ? (uint64_t)w.tslots[g0 + 64].x : (uint64_t)I;
+    for (int v = 0; v < nviews; ++v) {
+      const uint64_t lo = w.tslots[(int64_t)v * cfg.n + g0].x;
+      const uint64_t hi = (v + 1 < nviews) ? (uint64_t)w.tslots[(int64_t)(v + 1) * cfg.n + g0].x
+                                           : group_end;
+      if (lo >= hi) continue;  // no instance of this group in view v
 #pragma unroll
-    for (int k = 0; k < 22; ++k) acc[k] = 0.f;
-    if constexpr (FUSED) {
+      for (int k = 0; k < 22; ++k) s_acc[wave][k][lane] = 0.f;
+      __builtin_amdgcn_wave_barrier();
+      for (uint64_t base = lo; base < hi; base += 64) {
+        const uint64_t sl = base + lane;
+        const bool valid = sl < hi;
+        float v22[22];
+        uint32_t seg = 0xffffffffu;
+        if (valid) {
+          const float4 *P = reinterpret_cast<const float4 *>(w.partials + (int64_t)sl * kPartialFloats);
 #pragma unroll
-      for (int k = 0; k < 22; ++k) acc[k] = s_acc[threadIdx.x >> 6][k][threadIdx.x & 63];
-    } else {
-    // Sum of the segment: the block-portion sums left by the segmented reduction.
-    for (uint32_t blk = sa >> 6; blk <= (sb - 1) >> 6; ++blk) {
-      const uint32_t e = min(sb - 1, blk * 64u + 63u);
-      const float4 *P = reinterpret_cast<const float4 *>(w.partials + (int64_t)e * kPartialFloats);
+          for (int k = 0; k < 5; ++k) {
+            const float4 t = P[k];
+            v22[4 * k] = t.x; v22[4 * k + 1] = t.y; v22[4 * k + 2] = t.z; v22[4 * k + 3] = t.w;
+          }
+          const float4 t = P[5];
+          v22[20] = t.x; v22[21] = t.y;
+          seg = __float_as_uint(t.z);
+        } else {
 #pragma unroll
-      for (int k = 0; k < 5; ++k) {
-        const float4 t = P[k];
-        acc[4 * k] += t.x; acc[4 * k + 1] += t.y; acc[4 * k + 2] += t.z; acc[4 * k + 3] += t.w;
+          for (int k = 0; k < 22; ++k) v22[k] = 0.f;
+        }
+        // Inclusive segmented scan over the wave with DPP lane moves (no
+        // LDS): shifts by 1, 2, 4, 8 inside each row of 16 lanes, then the
+        // last lane of row 0 / row 2 into rows 1 / 3, then lane 31 into rows
+        // 2 and 3. Segments are runs of consecutive slots, so equal ids mean
+        // one run; the fixed tree makes the sums deterministic.
+        seg_scan_step<0x111, 0xf>(seg, v22);   // row_shr:1
+        seg_scan_step<0x112, 0xf>(seg, v22);   // row_shr:2
+        seg_scan_step<0x114, 0xf>(seg, v22);   // row_shr:4
+        seg_scan_step<0x118, 0xf>(seg, v22);   // row_shr:8
+        seg_scan_step<0x142, 0xa>(seg, v22);   // row_bcast:15 into rows 1, 3
+        seg_scan_step<0x143, 0xc>(seg, v22);   // row_bcast:31 into rows 2, 3
+        const uint32_t sn = __shfl_down(seg, 1, 64);
+        const bool end = valid && (lane == 63 || sn != seg || sl + 1 == hi);
+        if (end) {
+          const int owner = (int)((int64_t)(seg & ((1u << 27) - 1u)) - g0);
+#pragma unroll
+          for (int k = 0; k < 22; ++k) s_acc[wave][k][owner] += v22[k];
+        }
+        __builtin_amdgcn_wave_barrier();
       }
-      const float4 t = P[5];
-      acc[20] += t.x; acc[21] += t.y;
-    }
-    }
-    sa = sb;
-    const ViewParams &V = vs.v[v];
-    double gD0[3], gDu[3], gDv[3], gM0[3], gMu[3], gMv[3], gc[3];
-    for (int k = 0; k < 3; ++k) {
-      gD0[k] = acc[P_D0 + k]; gDu[k] = acc[P_DX + k]; gDv[k] = acc[P_DY + k];
-      gM0[k] = acc[P_M0 + k]; gMu[k] = acc[P_MX + k]; gMv[k] = acc[P_MY + k];
-      gc[k] = acc[P_C + k];
-    }
-    go += acc[P_O];
-    // Pluecker coefficients -> view rows of M T.
-    double Rv[3][3], mv[3];
-    view_rows(V, a, Rv, mv);
-    double gR[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-    double gm[3] = {0, 0, 0};
-    double t[3];
-    // D0 = R1 x R2, Du = R2 x R3, Dv = R3 x R1 (rows R1..R3 of Rv)
-    cross3(Rv[1], gD0, t); for (int k = 0; k < 3; ++k) gR[0][k] += t[k];
-    cross3(gD0, Rv[0], t); for (int k = 0; k < 3; ++k) gR[1][k] += t[k];
-    cross3(Rv[2], gDu, t); for (int k = 0; k < 3; ++k) gR[1][k] += t[k];
-    cross3(gDu, Rv[1], t); for (int k = 0; k < 3; ++k) gR[2][k] += t[k];
-    cross3(Rv[0], gDv, t); for (int k = 0; k < 3; ++k) gR[2][k] += t[k];
-    cross3(gDv, Rv[2], t); for (int k = 0; k < 3; ++k) gR[0][k] += t[k];
-    // M0 = m0 R2 - m1 R1, Mu = m1 R3 - m2 R2, Mv = m2 R1 - m0 R3
-    for (int k = 0; k < 3; ++k) {
-      gR[1][k] += mv[0] * gM0[k];
-      gR[0][k] -= mv[1] * gM0[k];
-      gR[2][k] += mv[1] * gMu[k];
-      gR[1][k] -= mv[2] * gMu[k];
-      gR[0][k] += mv[2] * gMv[k];
-      gR[2][k] -= mv[0] * gMv[k];
-    }
-    gm[0] += dot3(gM0, Rv[1]) - dot3(gMv, Rv[2]);
-    gm[1] += dot3(gMu, Rv[2]) - dot3(gM0, Rv[0]);
-    gm[2] += dot3(gMv, Rv[0]) - dot3(gMu, Rv[1]);
-    // Rv = W3 A (A = R diag(s)), mv = W3 mu + t
-    for (int i = 0; i < 3; ++i) {
-      for (int j = 0; j < 3; ++j) {
-        double s_ = 0.0;
-        for (int k = 0; k < 3; ++k) s_ += (double)V.w2c[4 * k + i] * gR[k][j];
-        gA[i][j] += s_;
+      __builtin_amdgcn_wave_barrier();
+      const bool mine = total != 0 &&
+          tile_count(w.rects[(int64_t)v * cfg.n + g], tslot_mask(w.tslots[(int64_t)v * cfg.n + g])) > 0;
+      if (mine) {
+        float acc[22];
+#pragma unroll
+        for (int k = 0; k < 22; ++k) acc[k] = s_acc[wave][k][lane];
+        const ViewParams &V = vs.v[v];
+        double gD0[3], gDu[3], gDv[3], gM0[3], gMu[3], gMv[3], gc[3];
+        for (int k = 0; k < 3; ++k) {
+          gD0[k] = acc[P_D0 + k]; gDu[k] = acc[P_DX + k]; gDv[k] = acc[P_DY + k];
+          gM0[k] = acc[P_M0 + k]; gMu[k] = acc[P_MX + k]; gMv[k] = acc[P_MY + k];
+          gc[k] = acc[P_C + k];
+        }
+        go += acc[P_O];
+        // Pluecker coefficients -> view rows of M T.
+        double Rv[3][3], mv[3];
+        view_rows(V, a, Rv, mv);
+        double gR[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+        double gm[3] = {0, 0, 0};
+        double t[3];
+        // D0 = R1 x R2, Du = R2 x R3, Dv = R3 x R1 (rows R1..R3 of Rv)
+        cross3(Rv[1], gD0, t); for (int k = 0; k < 3; ++k) gR[0][k] += t[k];
+        cross3(gD0, Rv[0], t); for (int k = 0; k < 3; ++k) gR[1][k] += t[k];
+        cross3(Rv[2], gDu, t); for (int k = 0; k < 3; ++k) gR[1][k] += t[k];
+        cross3(gDu, Rv[1], t); for (int k = 0; k < 3; ++k) gR[2][k] += t[k];
+        cross3(Rv[0], gDv, t); for (int k = 0; k < 3; ++k) gR[2][k] += t[k];
+        cross3(gDv, Rv[2], t); for (int k = 0; k < 3; ++k) gR[0][k] += t[k];
+        // M0 = m0 R2 - m1 R1, Mu = m1 R3 - m2 R2, Mv = m2 R1 - m0 R3
+        for (int k = 0; k < 3; ++k) {
+          gR[1][k] += mv[0] * gM0[k];
+          gR[0][k] -= mv[1] * gM0[k];
+          gR[2][k] += mv[1] * gMu[k];
+          gR[1][k] -= mv[2] * gMu[k];
+          gR[0][k] += mv[2] * gMv[k];
+          gR[2][k] -= mv[0] * gMv[k];
+        }
+        gm[0] += dot3(gM0, Rv[1]) - dot3(gMv, Rv[2]);
+        gm[1] += dot3(gMu, Rv[2]) - dot3(gM0, Rv[0]);
+        gm[2] += dot3(gMv, Rv[0]) - dot3(gMu, Rv[1]);
+        // Rv = W3 A (A = R diag(s)), mv = W3 mu + t
+        for (int i = 0; i < 3; ++i) {
+          for (int j = 0; j < 3; ++j) {
+            double s_ = 0.0;
+            for (int k = 0; k < 3; ++k) s_ += (double)V.w2c[4 * k + i] * gR[k][j];
+            gA[i][j] += s_;
+          }
+          double sm = 0.0;
+          for (int k = 0; k < 3; ++k) sm += (double)V.w2c[4 * k + i] * gm[k];
+          gmu[i] += sm;
+        }
+        // Colour: SH coefficients and the viewing direction.
+        const uint32_t flags =
+            __float_as_uint(w.records[((int64_t)v * cfg.n + g) * kRecFloats + R_FLAGS]);
+        for (int c = 0; c < 3; ++c)
+          if (flags & (1u << c)) gc[c] = 0.0;
+        double dv[3] = {a.mu[0] - V.cam_pos[0], a.mu[1] - V.cam_pos[1], a.mu[2] - V.cam_pos[2]};
+        const double dn = sqrt(dot3(dv, dv));
+        const double dir[3] = {dv[0] / dn, dv[1] / dn, dv[2] / dn};
+        double gdir[3] = {0, 0, 0};
+        float wsv[NB];
+        sh_dots<NB>(shrow, gc, wsv);
+        sh_backward<DEG>(wsv, dir, gc, gsh, gdir);
+        const double radial = dot3(gdir, dir);
+        for (int j = 0; j < 3; ++j) gmu[j] += (gdir[j] - dir[j] * radial) / dn;
       }
-      double sm = 0.0;
-      for (int k = 0; k < 3; ++k) sm += (double)V.w2c[4 * k + i] * gm[k];
-      gmu[i] += sm;
+      __builtin_amdgcn_wave_barrier();
     }
-    // Colour: SH coefficients and the viewing direction.
-    const uint32_t flags =
-        __float_as_uint(w.records[((int64_t)v * cfg.n + g) * kRecFloats + R_FLAGS]);
-    for (int c = 0; c < 3; ++c)
-      if (flags & (1u << c)) gc[c] = 0.0;
-    double dv[3] = {a.mu[0] - V.cam_pos[0], a.mu[1] - V.cam_pos[1], a.mu[2] - V.cam_pos[2]};
-    const double dn = sqrt(dot3(dv, dv));
-    const double dir[3] = {dv[0] / dn, dv[1] / dn, dv[2] / dn};
-    double gdir[3] = {0, 0, 0};
-    float wsv[NB];
-    sh_dots<NB>(shrow, gc, wsv);
-    sh_backward<DEG>(wsv, dir, gc, gsh, gdir);
-    const double radial = dot3(gdir, dir);
-    for (int j = 0; j < 3; ++j) gmu[j] += (gdir[j] - dir[j] * radial) / dn;
+  }
+  if (!live) return;
+  if (total == 0) {
+    if (cfg.grad_overwrite) {
+      const float z[4] = {0.f, 0.f, 0.f, 0.f};
+      float zsh[3 * NB];
+#pragma unroll
+      for (int k = 0; k < 3 * NB; ++k) zsh[k] = 0.f;
+      emit_grads<NB>(gr, g, z, z, z, 0.f, zsh, true);
+    }
+    return;
   }
   // A = R diag(s): to rotation, scales and quaternion.
   double gRot[3][3], gs[3] = {0, 0, 0};
@@ -991,13 +936,6 @@ hipError_t launch_preprocess(const GaussPtrs &gp, const KCfg &cfg, const ViewSet
   return hipGetLastError();
 }
 
-hipError_t launch_segment_reduce(const Ws &w, hipStream_t s) {
-  if (w.capacity == 0) return hipSuccess;
-  const int64_t blocks = (w.capacity + 255) / 256;
-  hipLaunchKernelGGL(k_segment_reduce, dim3((unsigned)blocks), dim3(256), 0, s, w);
-  return hipGetLastError();
-}
-
 hipError_t launch_preprocess_bwd(const GaussPtrs &gp, const GradPtrs &gr, const KCfg &cfg,
                                  const ViewSet &vs, const Ws &w, hipStream_t s) {
   if (cfg.n == 0) return hipSuccess;
@@ -1006,11 +944,11 @@ hipError_t launch_preprocess_bwd(const GaussPtrs &gp, const GradPtrs &gr, const 
 #define HTGS_PREB(D)                                                                       \
   do {                                                                                     \
     if (vs.n > 1)                                                                          \
-      hipLaunchKernelGGL((k_preprocess_bwd<D, true, false>), dim3(blocks), dim3(256), 0, s, gp, \
-                         gr, cfg, vs, w);                                                  \
+      hipLaunchKernelGGL((k_preprocess_bwd<D, true>), dim3(blocks), dim3(256), 0, s, gp, gr, \
+                         cfg, vs, w);                                                      \
     else                                                                                   \
-      hipLaunchKernelGGL((k_preprocess_bwd<D, false, true>), dim3(blocks), dim3(256), 0, s,   \
-                         gp, gr, cfg, vs, w);                                              \
+      hipLaunchKernelGGL((k_preprocess_bwd<D, false>), dim3(blocks), dim3(256), 0, s, gp, gr, \
+                         cfg, vs, w);                                                      \
   } while (0)
     case 0: HTGS_PREB(0); break;
     case 1: HTGS_PREB(1); break;

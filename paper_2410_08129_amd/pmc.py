@@ -28,7 +28,6 @@ KERNEL_SOURCES = {
     "k_raster_bwd": ("raster.hip", "common.h"),
     "k_preprocess": ("preprocess.hip", "common.h"),
     "k_preprocess_bwd": ("preprocess.hip", "common.h"),
-    "k_segment_reduce": ("preprocess.hip", "common.h"),
     "k_sort_pass": ("sort.hip", "common.h"),
     "k_ranges": ("sort.hip", "common.h"),
     "k_fill_zero": ("preprocess.hip", "common.h"),
