@@ -21,7 +21,11 @@
 // fragment of the pixel (Sec. 3.3, last paragraph). Then each wave takes 64
 // of the tile's instances, one per lane, and loops over the tile's pixels
 // (skipping 8x8 blocks no lane's rect touches), recomputing rho^2 and alpha
-// exactly as the forward did. Because d and m are affine in the pixel
+// (|d|^2 and |m|^2 as quadratics along each pixel row, which rounds a
+// little differently from the forward's vector form: a fragment within
+// rounding of the cutoff, whose alpha is tau_alpha, may be judged
+// differently; core members, with alpha >= tau_K, never are). Because d and
+// m are affine in the pixel
 // offset (lx, ly), the gradient w.r.t. their 18 affine coefficients follows
 // from six moments of dL/d(rho^2)-weights per vector (sum of w, w lx, w ly,
 // w lx^2, w lx ly, w ly^2), accumulated in registers. Each lane writes one
@@ -407,12 +411,13 @@ struct PixLayout {
   static constexpr int kStride = ((8 + 3 * KMAX) + 3) / 4 * 4;
 };
 
-// Gradient contribution of one fragment (lane's splat at pixel Pp, tile
-// column lx) to the lane's accumulators. cslot is the fragment's core index
-// at this pixel, or -1 for a tail fragment. rs holds this row's sums of the
-// d and m weights times (1, lx, lx^2).
+// Gradient contribution of one fragment (lane's splat at pixel Pp, column c
+// of its 8x8 block; c is a constant after unrolling) to the lane's
+// accumulators. cslot is the fragment's core index at this pixel, or -1 for
+// a tail fragment. rs holds this row's sums of the d and m weights times
+// (1, c, c^2).
 template <int KMAX>
-__device__ __forceinline__ void bwd_fragment(const float *st, const float *Pp, float lx,
+__device__ __forceinline__ void bwd_fragment(const float *st, const float *Pp, int c,
                                              float dd, float mm, int cslot, float amax,
                                              float *rs, float *acc) {
   using L = PixLayout<KMAX>;
@@ -437,13 +442,18 @@ __device__ __forceinline__ void bwd_fragment(const float *st, const float *Pp, f
     acc[12] = fmaf(dLda, e, acc[12]);
     const float s1 = -alpha * dLda * inv;   // weight of m: 2 dL/drho^2 / |d|^2
     const float s2 = -s1 * r2;              // weight of d
-    const float lx2 = lx * lx;
     rs[0] += s2;
-    rs[1] = fmaf(lx, s2, rs[1]);
-    rs[2] = fmaf(lx2, s2, rs[2]);
     rs[3] += s1;
-    rs[4] = fmaf(lx, s1, rs[4]);
-    rs[5] = fmaf(lx2, s1, rs[5]);
+    if (c == 1) {
+      rs[1] += s2; rs[2] += s2;
+      rs[4] += s1; rs[5] += s1;
+    } else if (c > 1) {
+      const float fc = (float)c, fc2 = (float)(c * c);
+      rs[1] = fmaf(fc, s2, rs[1]);
+      rs[2] = fmaf(fc2, s2, rs[2]);
+      rs[4] = fmaf(fc, s1, rs[4]);
+      rs[5] = fmaf(fc2, s1, rs[5]);
+    }
   }
 }
 
@@ -571,6 +581,11 @@ __device__ __forceinline__ void bwd_tile(const TileInfo &ti, const Ws &w, const 
     float acc[16];
 #pragma unroll
     for (int k = 0; k < 16; ++k) acc[k] = 0.f;
+    // |Du|^2 and |Mu|^2: the c^2 coefficients of |d|^2 and |m|^2 along a row
+    const float Cd = fmaf(st[S_DU + 2], st[S_DU + 2],
+                          fmaf(st[S_DU + 1], st[S_DU + 1], st[S_DU] * st[S_DU]));
+    const float Cm = fmaf(st[S_MU + 2], st[S_MU + 2],
+                          fmaf(st[S_MU + 1], st[S_MU + 1], st[S_MU] * st[S_MU]));
     for (int blk = 0; blk < NB; ++blk) {
       const int bx = (blk % BX) * 8, by = (blk / BX) * 8;
       const bool hitb = active && rect_meets_block(st + S_BB0, bx, by);
@@ -593,10 +608,13 @@ __device__ __forceinline__ void bwd_tile(const TileInfo &ti, const Ws &w, const 
         }
         __builtin_amdgcn_wave_barrier();
       }
-      // A row at a time: d and m along the row are (row base) + lx (Du, Mu),
-      // and the moments (1, lx, ly, lx^2, lx ly, ly^2) of the weights follow
-      // from per-row sums over (1, lx, lx^2). The columns are unrolled, so
-      // lx is a constant for 8x8 tiles; two pixels per step.
+      // A row at a time: along the row d and m are (row base) + c (Du, Mu)
+      // for the block column c, so |d|^2 and |m|^2 are quadratics in c whose
+      // coefficients are formed once per row (the backward needs only the
+      // two squared norms, not the vectors); the moments (1, lx, ly, lx^2,
+      // lx ly, ly^2) of the weights follow from per-row sums over
+      // (1, c, c^2). The columns are unrolled, so c is a constant.
+      const float fbx = (float)bx;
       for (int row = 0; row < 8; ++row) {
         const float ly = (float)(by + row);
         float db[3], mb[3];
@@ -604,32 +622,41 @@ __device__ __forceinline__ void bwd_tile(const TileInfo &ti, const Ws &w, const 
         for (int k = 0; k < 3; ++k) {
           db[k] = fmaf(ly, st[S_DV + k], st[S_D0 + k]);
           mb[k] = fmaf(ly, st[S_MV + k], st[S_M0 + k]);
+          if constexpr (BX > 1) {
+            db[k] = fmaf(fbx, st[S_DU + k], db[k]);
+            mb[k] = fmaf(fbx, st[S_MU + k], mb[k]);
+          }
         }
+        const float Ad = fmaf(db[2], db[2], fmaf(db[1], db[1], db[0] * db[0]));
+        const float Am = fmaf(mb[2], mb[2], fmaf(mb[1], mb[1], mb[0] * mb[0]));
+        const float Bd =
+            2.f * fmaf(db[2], st[S_DU + 2], fmaf(db[1], st[S_DU + 1], db[0] * st[S_DU]));
+        const float Bm =
+            2.f * fmaf(mb[2], st[S_MU + 2], fmaf(mb[1], st[S_MU + 1], mb[0] * st[S_MU]));
         float rs[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int col = 0; col < 8; col += 2) {
           const int q = row * 8 + col;
           const int p0 = (by + row) * TW + bx + col;
           const int p1 = p0 + 1;
-          const float lx0 = (float)(bx + col), lx1 = (float)(bx + col + 1);
-          float d0[3], m0[3], d1[3], m1[3];
-#pragma unroll
-          for (int k = 0; k < 3; ++k) {
-            d0[k] = fmaf(lx0, st[S_DU + k], db[k]);
-            m0[k] = fmaf(lx0, st[S_MU + k], mb[k]);
-            d1[k] = fmaf(lx1, st[S_DU + k], db[k]);
-            m1[k] = fmaf(lx1, st[S_MU + k], mb[k]);
-          }
-          const float dd0 = fmaf(d0[2], d0[2], fmaf(d0[1], d0[1], d0[0] * d0[0]));
-          const float mm0 = fmaf(m0[2], m0[2], fmaf(m0[1], m0[1], m0[0] * m0[0]));
-          const float dd1 = fmaf(d1[2], d1[2], fmaf(d1[1], d1[1], d1[0] * d1[0]));
-          const float mm1 = fmaf(m1[2], m1[2], fmaf(m1[1], m1[1], m1[0] * m1[0]));
+          const float f0c = (float)col, f1c = (float)(col + 1);
+          const float dd0 = col == 0 ? Ad : fmaf(f0c, fmaf(f0c, Cd, Bd), Ad);
+          const float mm0 = col == 0 ? Am : fmaf(f0c, fmaf(f0c, Cm, Bm), Am);
+          const float dd1 = fmaf(f1c, fmaf(f1c, Cd, Bd), Ad);
+          const float mm1 = fmaf(f1c, fmaf(f1c, Cm, Bm), Am);
           const bool f0 = hitb && is_fragment(dd0, mm0, st[S_RC]);
           const bool f1 = hitb && is_fragment(dd1, mm1, st[S_RC]);
-          if (f0) bwd_fragment<KMAX>(st, sp_all + p0 * L::kStride, lx0, dd0, mm0,
+          if (f0) bwd_fragment<KMAX>(st, sp_all + p0 * L::kStride, col, dd0, mm0,
                                      (int)s_slot[wave][q][lane] - 1, amax, rs, acc);
-          if (f1) bwd_fragment<KMAX>(st, sp_all + p1 * L::kStride, lx1, dd1, mm1,
+          if (f1) bwd_fragment<KMAX>(st, sp_all + p1 * L::kStride, col + 1, dd1, mm1,
                                      (int)s_slot[wave][q + 1][lane] - 1, amax, rs, acc);
+        }
+        if constexpr (BX > 1) {
+          // sums over (1, c, c^2) -> over (1, lx, lx^2), lx = bx + c
+          rs[2] = fmaf(fbx, fmaf(fbx, rs[0], 2.f * rs[1]), rs[2]);
+          rs[1] = fmaf(fbx, rs[0], rs[1]);
+          rs[5] = fmaf(fbx, fmaf(fbx, rs[3], 2.f * rs[4]), rs[5]);
+          rs[4] = fmaf(fbx, rs[3], rs[4]);
         }
         const float ly2 = ly * ly;
         acc[0] += rs[0];
