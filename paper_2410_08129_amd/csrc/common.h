@@ -44,15 +44,14 @@ enum PartialField {
   P_SEG = 22
 };
 
-// Staged record in the raster kernels: tile-centred coefficients, the
-// instance's position in the tile list and its pixel rect relative to the
-// tile (32 floats). The first 20 floats are what the ray test and alpha
-// need; the next 8 are read only for fragments.
+// Record as the raster backward holds it in registers: tile-centred affine
+// coefficients of d and m, cutoff, opacity, colour and the pixel rect
+// relative to the tile (the forward stages quadratic forms instead).
 enum StageField {
   S_D0 = 0, S_DU = 3, S_DV = 6, S_M0 = 9, S_MU = 12, S_MV = 15, S_RC = 18, S_O = 19,
-  S_R3 = 20, S_MUZ = 23, S_RGB = 24, S_POS = 27,
+  S_RGB = 24,
   S_BB0 = 28, S_BB1 = 29, S_BB2 = 30, S_BB3 = 31,  // tile-local x0, y0, x1, y1 (int bits)
-  S_FLOATS = 32, S_EVAL4 = 5                       // float4s read for the ray test
+  S_FLOATS = 32
 };
 
 struct ViewParams {

@@ -3,13 +3,15 @@
 // Forward: one workgroup per tile; each wave owns an 8x8 pixel block, one
 // lane per pixel. The tile's instances are staged through LDS in batches of
 // one record per lane; each wave then keeps only the staged splats whose
-// covered pixel rect meets its block and walks them: Pluecker direction d
-// and moment m of its pixel ray in splat space (affine in the pixel offset,
-// tile-centred), rho^2 = |m|^2/|d|^2 (Eq. rho-pluecker), alpha =
-// min(alpha_max, o exp(-rho^2/2)), and for fragments with alpha >= tau_K the
-// view depth of the maximum-density point z = (M T [(d x m)/|d|^2; 1])_z
-// (Sec. 3.3). Those enter a register core of K (depth, alpha, list
-// position) entries kept sorted by a select-based shift. Every fragment is
+// covered pixel rect meets its block and walks them. For the Pluecker
+// direction d and moment m of its pixel ray in splat space, rho^2 =
+// |m|^2/|d|^2 (Eq. rho-pluecker), alpha = min(alpha_max, o exp(-rho^2/2)),
+// and for fragments with alpha >= tau_K the view depth of the
+// maximum-density point z = (M T [(d x m)/|d|^2; 1])_z (Sec. 3.3); since d
+// and m are affine in the pixel offset, |d|^2, |m|^2 and R3 . (d x m) are
+// quadratics in it, staged per (tile, splat) and evaluated per pixel. The
+// fragments enter a register core of K (depth, list position) entries kept
+// sorted by a median-of-three / select shift. Every fragment is
 // added to running sums (sum alpha, sum alpha rgb, prod (1 - alpha)); at
 // the end the core members are taken back out of them, which leaves the
 // order-independent tail of everything that never entered the core or fell
@@ -41,10 +43,10 @@ constexpr float kNegHalfLog2e = -0.72134752044448170368f;  // -1 / (2 ln 2)
 __device__ __forceinline__ float exp2_fast(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ float rcp_fast(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// Tile-centred staged record: d = D0t + lx Du + ly Dv with (lx, ly) the
-// pixel's integer offset from the tile's first pixel.
+// Tile-centred record for the backward: d = D0t + lx Du + ly Dv with
+// (lx, ly) the pixel's integer offset from the tile's first pixel.
 __device__ __forceinline__ void stage_record(const float *__restrict__ rec, int px0, int py0,
-                                             uint32_t pos, float *st) {
+                                             float *st) {
   const float dx0 = (float)(px0 - __float_as_int(rec[R_IX]));
   const float dy0 = (float)(py0 - __float_as_int(rec[R_IY]));
 #pragma unroll
@@ -55,13 +57,10 @@ __device__ __forceinline__ void stage_record(const float *__restrict__ rec, int 
     st[S_M0 + k] = fmaf(dy0, rec[R_MV + k], fmaf(dx0, rec[R_MU + k], rec[R_M0 + k]));
     st[S_MU + k] = rec[R_MU + k];
     st[S_MV + k] = rec[R_MV + k];
-    st[S_R3 + k] = rec[R_R3 + k];
     st[S_RGB + k] = rec[R_RGB + k];
   }
-  st[S_MUZ] = rec[R_MUZ];
   st[S_O] = rec[R_O];
   st[S_RC] = rec[R_RC];
-  st[S_POS] = __uint_as_float(pos);
   const uint32_t b0 = __float_as_uint(rec[R_BB0]), b1 = __float_as_uint(rec[R_BB1]);
   st[S_BB0] = __int_as_float((int)(b0 & 0xffffu) - px0);
   st[S_BB1] = __int_as_float((int)(b0 >> 16) - py0);
@@ -69,22 +68,154 @@ __device__ __forceinline__ void stage_record(const float *__restrict__ rec, int 
   st[S_BB3] = __int_as_float((int)(b1 >> 16) - py0);
 }
 
-// d and m at tile pixel offset (lx, ly); the row term is added first, so a
-// kernel that walks a row can hoist it (same rounding).
-__device__ __forceinline__ void eval_ray(const float *st, float lx, float ly, float d[3], float m[3],
-                                         float &dd, float &mm) {
+// Forward staging. The forward needs, per pixel ray, only |d|^2 and |m|^2
+// (the cutoff test and alpha) and R3 . (d x m) (the depth of the maximum
+// point). With d and m affine in the pixel offset (X, Y) from the tile
+// centre (|X|, |Y| <= (tile size - 1) / 2), |d|^2 and R3 . (d x m) are
+// quadratics in (X, Y) whose coefficients (1, X, Y, X^2, XY, Y^2) are
+// formed per (tile, splat); a pixel evaluates each with five FMAs. |m|^2
+// vanishes at the splat's centre, where its expanded quadratic would lose
+// precision to cancellation, so it is staged as a sum of squares instead:
+// with an orthonormal basis (q1, q2) of a plane holding Mu and Mv (q1
+// along Mu), m = s1 q1 + s2 q2 + r with s1 = R11 X + R12 Y + k1,
+// s2 = R22 Y + k2 and r constant and orthogonal to both, so
+// |m|^2 = s1^2 + s2^2 + |r|^2 (five FMAs, cancellation only inside s1, s2,
+// as in the vector form).
+enum FwdStage {
+  F_QD = 0,           // |d|^2
+  F_QM = 6,           // |m|^2: |r|^2, R11, R12, k1, R22, k2
+  F_RC = 12, F_O = 13, F_MUZ = 14, F_R = 15,
+  F_QZ = 16,          // R3 . (d x m)
+  F_G = 22, F_B = 23,
+  F_BB = 24,          // covered pixel rect relative to the tile's first pixel
+  F_FLOATS = 28, F_TEST4 = 4   // float4s read for the cutoff test and alpha
+};
+
+__device__ __forceinline__ void cross_f(const float a[3], const float b[3], float c[3]) {
+  c[0] = fmaf(a[1], b[2], -a[2] * b[1]);
+  c[1] = fmaf(a[2], b[0], -a[0] * b[2]);
+  c[2] = fmaf(a[0], b[1], -a[1] * b[0]);
+}
+
+__device__ __forceinline__ float dot_f(const float a[3], const float b[3]) {
+  return fmaf(a[2], b[2], fmaf(a[1], b[1], a[0] * b[0]));
+}
+
+// R3 . (a x b + e x f)
+__device__ __forceinline__ float triple2(const float r[3], const float a[3], const float b[3],
+                                         const float e[3], const float f[3]) {
+  float c[3], g[3];
+  cross_f(a, b, c);
+  cross_f(e, f, g);
+  return fmaf(r[2], c[2] + g[2], fmaf(r[1], c[1] + g[1], r[0] * (c[0] + g[0])));
+}
+
+// (cx2, cy2): twice the tile centre in pixel-index units (an integer).
+__device__ __forceinline__ void stage_fwd(const float *__restrict__ rec, int cx2, int cy2,
+                                          float *q) {
+  const float dx = 0.5f * (float)(cx2 - 2 * __float_as_int(rec[R_IX]));
+  const float dy = 0.5f * (float)(cy2 - 2 * __float_as_int(rec[R_IY]));
+  float D0[3], Du[3], Dv[3], M0[3], Mu[3], Mv[3], R3[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    d[k] = fmaf(lx, st[S_DU + k], fmaf(ly, st[S_DV + k], st[S_D0 + k]));
-    m[k] = fmaf(lx, st[S_MU + k], fmaf(ly, st[S_MV + k], st[S_M0 + k]));
+    Du[k] = rec[R_DU + k]; Dv[k] = rec[R_DV + k];
+    Mu[k] = rec[R_MU + k]; Mv[k] = rec[R_MV + k];
+    D0[k] = fmaf(dy, Dv[k], fmaf(dx, Du[k], rec[R_D0 + k]));
+    M0[k] = fmaf(dy, Mv[k], fmaf(dx, Mu[k], rec[R_M0 + k]));
+    R3[k] = rec[R_R3 + k];
   }
-  dd = fmaf(d[2], d[2], fmaf(d[1], d[1], d[0] * d[0]));
-  mm = fmaf(m[2], m[2], fmaf(m[1], m[1], m[0] * m[0]));
+  q[F_QD + 0] = dot_f(D0, D0);
+  q[F_QD + 1] = 2.f * dot_f(D0, Du);
+  q[F_QD + 2] = 2.f * dot_f(D0, Dv);
+  q[F_QD + 3] = dot_f(Du, Du);
+  q[F_QD + 4] = 2.f * dot_f(Du, Dv);
+  q[F_QD + 5] = dot_f(Dv, Dv);
+  {
+    // Gram-Schmidt (q1 along Mu; other unit vectors where Mu, or the part of
+    // Mv orthogonal to it, vanishes). Float rounding of the basis only
+    // perturbs |m|^2 relatively, by ~1e-7.
+    float q1[3], q2[3];
+    const float na2 = dot_f(Mu, Mu), nb2 = dot_f(Mv, Mv);
+    if (na2 > 0.f) {
+      const float s = __builtin_amdgcn_rsqf(na2);
+      for (int k = 0; k < 3; ++k) q1[k] = Mu[k] * s;
+    } else if (nb2 > 0.f) {
+      const float s = __builtin_amdgcn_rsqf(nb2);
+      for (int k = 0; k < 3; ++k) q1[k] = Mv[k] * s;
+    } else {
+      q1[0] = 1.f; q1[1] = 0.f; q1[2] = 0.f;
+    }
+    const float r12 = dot_f(q1, Mv);
+    float v[3];
+    for (int k = 0; k < 3; ++k) v[k] = fmaf(-r12, q1[k], Mv[k]);
+    const float nv2 = dot_f(v, v);
+    if (nv2 > 1e-12f * nb2 && nv2 > 0.f) {
+      const float s = __builtin_amdgcn_rsqf(nv2);
+      for (int k = 0; k < 3; ++k) q2[k] = v[k] * s;
+    } else {
+      // q1 x (the axis q1 is least along), normalised
+      const float a0 = fabsf(q1[0]), a1 = fabsf(q1[1]), a2 = fabsf(q1[2]);
+      float e[3] = {0.f, 0.f, 0.f};
+      e[(a0 <= a1 && a0 <= a2) ? 0 : (a1 <= a2 ? 1 : 2)] = 1.f;
+      cross_f(q1, e, q2);
+      const float s = __builtin_amdgcn_rsqf(dot_f(q2, q2));
+      for (int k = 0; k < 3; ++k) q2[k] *= s;
+    }
+    const float k1 = dot_f(q1, M0), k2 = dot_f(q2, M0);
+    float r[3];
+    for (int k = 0; k < 3; ++k) r[k] = fmaf(-k2, q2[k], fmaf(-k1, q1[k], M0[k]));
+    q[F_QM + 0] = dot_f(r, r);
+    q[F_QM + 1] = dot_f(q1, Mu);
+    q[F_QM + 2] = r12;
+    q[F_QM + 3] = k1;
+    q[F_QM + 4] = dot_f(q2, Mv);
+    q[F_QM + 5] = k2;
+  }
+  // d x m = D0xM0 + X (D0xMu + DuxM0) + Y (D0xMv + DvxM0) + X^2 DuxMu
+  //         + XY (DuxMv + DvxMu) + Y^2 DvxMv
+  float c[3];
+  cross_f(D0, M0, c);
+  q[F_QZ + 0] = dot_f(R3, c);
+  q[F_QZ + 1] = triple2(R3, D0, Mu, Du, M0);
+  q[F_QZ + 2] = triple2(R3, D0, Mv, Dv, M0);
+  cross_f(Du, Mu, c);
+  q[F_QZ + 3] = dot_f(R3, c);
+  q[F_QZ + 4] = triple2(R3, Du, Mv, Dv, Mu);
+  cross_f(Dv, Mv, c);
+  q[F_QZ + 5] = dot_f(R3, c);
+  q[F_RC] = rec[R_RC];
+  q[F_O] = rec[R_O];
+  q[F_MUZ] = rec[R_MUZ];
+  q[F_R] = rec[R_RGB];
+  q[F_G] = rec[R_RGB + 1];
+  q[F_B] = rec[R_RGB + 2];
+}
+
+// Per-pixel constants of the quadratics: X, Y, X^2, XY, Y^2.
+struct PixQ {
+  float x, y, xx, xy, yy;
+};
+
+__device__ __forceinline__ float eval_q(const float *c, const PixQ &u) {
+  return fmaf(u.yy, c[5], fmaf(u.xy, c[4], fmaf(u.xx, c[3], fmaf(u.y, c[2], fmaf(u.x, c[1], c[0])))));
+}
+
+// |m|^2 = s1^2 + s2^2 + |r|^2 (see FwdStage).
+__device__ __forceinline__ float eval_mm(const float *c, const PixQ &u) {
+  const float s1 = fmaf(c[1], u.x, fmaf(c[2], u.y, c[3]));
+  const float s2 = fmaf(c[4], u.y, c[5]);
+  return fmaf(s1, s1, fmaf(s2, s2, c[0]));
+}
+
+// min(x, a) as one median-of-three with -inf (fminf would first
+// canonicalize both operands).
+__device__ __forceinline__ float min_med3(float x, float a) {
+  return __builtin_amdgcn_fmed3f(x, a, -INFINITY);
 }
 
 // alpha = min(alpha_max, o exp(-rho^2 / 2)) with rho^2 = mm / dd.
 __device__ __forceinline__ float frag_alpha(float o, float mm, float inv, float amax) {
-  return fminf(amax, o * exp2_fast((mm * inv) * kNegHalfLog2e));
+  return min_med3(o * exp2_fast((mm * inv) * kNegHalfLog2e), amax);
 }
 
 __device__ __forceinline__ bool is_fragment(float dd, float mm, float rc) {
@@ -172,7 +303,7 @@ __device__ __forceinline__ void fwd_tile(const TileInfo &ti, const Ws &w, const 
   constexpr int NBATCH = NT * BM;   // records staged per batch
   constexpr int NW = NT / 64;       // waves, one 8x8 block each
   constexpr int BX = TW / 8;
-  constexpr int SV = S_FLOATS / 4;
+  constexpr int SV = F_FLOATS / 4;
   __shared__ float4 s_stage[NBATCH * SV];
   __shared__ uint16_t s_list[NW][NBATCH];
   __shared__ uint32_t s_nfrag;
@@ -185,7 +316,11 @@ __device__ __forceinline__ void fwd_tile(const TileInfo &ti, const Ws &w, const 
   const int px = px0 + lx, py = py0 + ly;
   const bool inside = (px < V.width) && (py < V.height);
   const uint2 rg = w.ranges[ti.t];
-  const float flx = (float)lx, fly = (float)ly;
+  PixQ u;
+  u.x = (float)lx - 0.5f * (float)(TW - 1);
+  u.y = (float)ly - 0.5f * (float)(TH - 1);
+  u.xx = u.x * u.x; u.xy = u.x * u.y; u.yy = u.y * u.y;   // exact (half-integers)
+  const int cx2 = 2 * px0 + TW - 1, cy2 = 2 * py0 + TH - 1;
   const int K = EXACT ? KMAX : cfg.K;
   const float tau_core = cfg.tau_core, amax = cfg.alpha_max;
   const float *recs = w.records + (int64_t)ti.v * cfg.n * kRecFloats;
@@ -218,8 +353,13 @@ __device__ __forceinline__ void fwd_tile(const TileInfo &ti, const Ws &w, const 
         const uint32_t gid = vals[base + r];
         float rec[kRecFloats];
         load_record(recs, gid, rec);
-        float st[S_FLOATS];
-        stage_record(rec, px0, py0, base - rg.x + r, st);
+        float st[F_FLOATS];
+        stage_fwd(rec, cx2, cy2, st);
+        const uint32_t b0 = __float_as_uint(rec[R_BB0]), b1 = __float_as_uint(rec[R_BB1]);
+        st[F_BB + 0] = __int_as_float((int)(b0 & 0xffffu) - px0);
+        st[F_BB + 1] = __int_as_float((int)(b0 >> 16) - py0);
+        st[F_BB + 2] = __int_as_float((int)(b1 & 0xffffu) - px0);
+        st[F_BB + 3] = __int_as_float((int)(b1 >> 16) - py0);
 #pragma unroll
         for (int k = 0; k < SV; ++k)
           s_stage[r * SV + k] = make_float4(st[4 * k], st[4 * k + 1], st[4 * k + 2], st[4 * k + 3]);
@@ -234,7 +374,7 @@ __device__ __forceinline__ void fwd_tile(const TileInfo &ti, const Ws &w, const 
         const int j = j0 + lane;
         bool hit = false;
         if (j < cnt) {
-          const float4 b = s_stage[j * SV + S_BB0 / 4];
+          const float4 b = s_stage[j * SV + F_BB / 4];
           const float bb[4] = {b.x, b.y, b.z, b.w};
           hit = rect_meets_block(bb, bx, by);
         }
@@ -253,34 +393,34 @@ __device__ __forceinline__ void fwd_tile(const TileInfo &ti, const Ws &w, const 
     };
     auto fetch = [&](int j, float *e) {
 #pragma unroll
-      for (int k = 0; k < S_EVAL4; ++k) {
+      for (int k = 0; k < F_TEST4; ++k) {
         const float4 t = s_stage[j * SV + k];
         e[4 * k] = t.x; e[4 * k + 1] = t.y; e[4 * k + 2] = t.z; e[4 * k + 3] = t.w;
       }
     };
     auto step = [&](int j, const float *e) {
-      float d[3], m[3], dd, mm;
-      eval_ray(e, flx, fly, d, m, dd, mm);
-      if (!is_fragment(dd, mm, e[S_RC])) return;
+      const float dd = eval_q(e + F_QD, u);
+      const float mm = eval_mm(e + F_QM, u);
+      if (!is_fragment(dd, mm, e[F_RC])) return;
       ++nfrag;
       const float inv = rcp_fast(dd);
-      const float alpha = frag_alpha(e[S_O], mm, inv, amax);
-      const float4 f0 = s_stage[j * SV + S_R3 / 4];    // R3, depth of the mean
-      const float4 f1 = s_stage[j * SV + S_RGB / 4];   // rgb, list position
+      const float alpha = frag_alpha(e[F_O], mm, inv, amax);
+      const float4 f5 = s_stage[j * SV + F_QZ / 4 + 1];   // qz4, qz5, g, b
       A += alpha;
-      S0 = fmaf(alpha, f1.x, S0);
-      S1 = fmaf(alpha, f1.y, S1);
-      S2 = fmaf(alpha, f1.z, S2);
+      S0 = fmaf(alpha, e[F_R], S0);
+      S1 = fmaf(alpha, f5.z, S1);
+      S2 = fmaf(alpha, f5.w, S2);
       P *= 1.f - alpha;
       if (alpha >= tau_core && K > 0) {
-        const float r = fmaf(f0.z, fmaf(d[0], m[1], -d[1] * m[0]),
-                             fmaf(f0.y, fmaf(d[2], m[0], -d[0] * m[2]),
-                                  f0.x * fmaf(d[1], m[2], -d[2] * m[1])));
-        const float z = fmaf(r, inv, f0.w);
+        const float4 f4 = s_stage[j * SV + F_QZ / 4];     // qz0..qz3
+        const float qz[6] = {f4.x, f4.y, f4.z, f4.w, f5.x, f5.y};
+        const float z = fmaf(eval_q(qz, u), inv, e[F_MUZ]);
         if (z < zlast) {
           // Insert at the first entry deeper than z; the entries from there
-          // on move back by one and the last one drops out of the core.
-          const int pos = (int)__float_as_uint(f1.w);
+          // on move back by one and the last one drops out of the core. On
+          // the sorted depths that is new[i] = median(old[i-1], old[i], z)
+          // (one instruction); the positions follow the comparisons.
+          const int pos = (int)(base - rg.x) + j;
           bool c[KMAX];
 #pragma unroll
           for (int i = 0; i < KMAX; ++i) c[i] = z < cz[i];
@@ -288,11 +428,11 @@ __device__ __forceinline__ void fwd_tile(const TileInfo &ti, const Ws &w, const 
           // read.)
 #pragma unroll
           for (int i = KMAX - 1; i >= 1; --i) {
-            cz[i] = c[i - 1] ? cz[i - 1] : (c[i] ? z : cz[i]);
             cp[i] = c[i - 1] ? cp[i - 1] : (c[i] ? pos : cp[i]);
+            cz[i] = __builtin_amdgcn_fmed3f(cz[i - 1], cz[i], z);
           }
-          cz[0] = c[0] ? z : cz[0];
           cp[0] = c[0] ? pos : cp[0];
+          cz[0] = c[0] ? z : cz[0];
           if (K == KMAX) {
             zlast = cz[KMAX - 1];
           } else {
@@ -303,7 +443,7 @@ __device__ __forceinline__ void fwd_tile(const TileInfo &ti, const Ws &w, const 
         }
       }
     };
-    float ea[4 * S_EVAL4], eb[4 * S_EVAL4];
+    float ea[4 * F_TEST4], eb[4 * F_TEST4];
     if (nlist > 0) fetch(stage_index(0), ea);
     for (int q = 0; q < nlist; q += 2) {
       const int ja = stage_index(q);
@@ -338,13 +478,13 @@ __device__ __forceinline__ void fwd_tile(const TileInfo &ti, const Ws &w, const 
       gids[i] = (int)gid;
       float rec[kRecFloats];
       load_record(recs, gid, rec);
-      float st[S_FLOATS];
-      stage_record(rec, px0, py0, (uint32_t)cp[i], st);
-      float d[3], m[3], dd, mm;
-      eval_ray(st, flx, fly, d, m, dd, mm);
-      const float a = frag_alpha(st[S_O], mm, rcp_fast(dd), amax);
+      // the same staging and arithmetic as in the list walk: the same alpha
+      float st[F_FLOATS];
+      stage_fwd(rec, cx2, cy2, st);
+      const float dd = eval_q(st + F_QD, u), mm = eval_mm(st + F_QM, u);
+      const float a = frag_alpha(st[F_O], mm, rcp_fast(dd), amax);
       ca[i] = a;
-      const float4 c = make_float4(st[S_RGB], st[S_RGB + 1], st[S_RGB + 2], 0.f);
+      const float4 c = make_float4(st[F_R], st[F_G], st[F_B], 0.f);
       const float wgt = a * T;
       C0 = fmaf(wgt, c.x, C0);
       C1 = fmaf(wgt, c.y, C1);
@@ -425,7 +565,7 @@ __device__ __forceinline__ void bwd_fragment(const float *st, const float *Pp, i
   const float r2 = mm * inv;
   const float e = exp2_fast(r2 * kNegHalfLog2e);
   const float araw = st[S_O] * e;
-  const float alpha = fminf(amax, araw);
+  const float alpha = min_med3(araw, amax);
   const float G0 = Pp[0], G1 = Pp[1], G2 = Pp[2], w1 = Pp[3];
   // tail: dC/dalpha = w1 (c - c_tail) - T P (c_bg - c_tail) / (1 - alpha),
   // dC/dc = w1 alpha; core: the pixel's precomputed T_i (c_i - B_i) and T_i
@@ -574,7 +714,7 @@ __device__ __forceinline__ void bwd_tile(const TileInfo &ti, const Ws &w, const 
       const uint32_t gid = vals[j];
       float rec[kRecFloats];
       load_record(recs, gid, rec);
-      stage_record(rec, px0, py0, j - rg.x, st);
+      stage_record(rec, px0, py0, st);
       slot = tslot_slot(w.tslots[(int64_t)ti.v * cfg.n + gid], ti.tx, ti.ty);
     }
     // acc: d-moments (6), m-moments (6), dL/do, dL/drgb (3)
