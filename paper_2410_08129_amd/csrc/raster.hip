@@ -23,12 +23,12 @@
 // fragment of the pixel (Sec. 3.3, last paragraph). Then each wave takes 64
 // of the tile's instances, one per lane, and loops over the tile's pixels
 // (skipping 8x8 blocks no lane's rect touches), recomputing rho^2 and alpha
-// (|d|^2 and |m|^2 as quadratics along each pixel row, which rounds a
-// little differently from the forward's vector form: a fragment within
+// (|d|^2 and |m|^2 as sums of squares along each pixel row, which round a
+// little differently from the forward's per-tile forms: a fragment within
 // rounding of the cutoff, whose alpha is tau_alpha, may be judged
-// differently; core members, with alpha >= tau_K, never are). Because d and
-// m are affine in the pixel
-// offset (lx, ly), the gradient w.r.t. their 18 affine coefficients follows
+// differently; core members, with alpha >= tau_K, never are). Because d
+// and m are affine in the pixel offset (lx, ly), the gradient w.r.t. their
+// 18 affine coefficients follows
 // from six moments of dL/d(rho^2)-weights per vector (sum of w, w lx, w ly,
 // w lx^2, w lx ly, w ly^2), accumulated in registers. Each lane writes one
 // partial per instance: no floating-point atomics, deterministic results.
@@ -571,16 +571,21 @@ __device__ __forceinline__ void bwd_fragment(const float *st, const float *Pp, i
   // dC/dc = w1 alpha; core: the pixel's precomputed T_i (c_i - B_i) and T_i
   const float gdc = fmaf(G2, st[S_RGB + 2], fmaf(G1, st[S_RGB + 1], G0 * st[S_RGB]));
   const float tail = fmaf(w1, gdc, -Pp[4]) - Pp[5] * rcp_fast(1.f - alpha);
+  // Branch-free: every lane reads a core entry (entry 0 for tail
+  // fragments) and selects.
   const bool core = cslot >= 0;
   const int ci = core ? cslot : 0;
-  const float dLda = core ? Pp[L::kCoef + ci] : tail;
-  const float wc = alpha * (core ? Pp[L::kT + ci] : w1);
+  const float cf = Pp[L::kCoef + ci], cT = Pp[L::kT + ci];
+  const float dLda = core ? cf : tail;
+  const float wc = alpha * (core ? cT : w1);
   acc[13] = fmaf(wc, G0, acc[13]);
   acc[14] = fmaf(wc, G1, acc[14]);
   acc[15] = fmaf(wc, G2, acc[15]);
-  if (araw <= amax) {
-    acc[12] = fmaf(dLda, e, acc[12]);
-    const float s1 = -alpha * dLda * inv;   // weight of m: 2 dL/drho^2 / |d|^2
+  // Where alpha is clamped, o and rho^2 receive no gradient.
+  const float g = (araw <= amax) ? dLda : 0.f;
+  {
+    acc[12] = fmaf(g, e, acc[12]);
+    const float s1 = -alpha * g * inv;      // weight of m: 2 dL/drho^2 / |d|^2
     const float s2 = -s1 * r2;              // weight of d
     rs[0] += s2;
     rs[3] += s1;
@@ -721,11 +726,23 @@ __device__ __forceinline__ void bwd_tile(const TileInfo &ti, const Ws &w, const 
     float acc[16];
 #pragma unroll
     for (int k = 0; k < 16; ++k) acc[k] = 0.f;
-    // |Du|^2 and |Mu|^2: the c^2 coefficients of |d|^2 and |m|^2 along a row
-    const float Cd = fmaf(st[S_DU + 2], st[S_DU + 2],
-                          fmaf(st[S_DU + 1], st[S_DU + 1], st[S_DU] * st[S_DU]));
-    const float Cm = fmaf(st[S_MU + 2], st[S_MU + 2],
-                          fmaf(st[S_MU + 1], st[S_MU + 1], st[S_MU] * st[S_MU]));
+    // Unit vectors along Du and Mu and their lengths (zero stays zero).
+    float ud[3], um[3], nD, nM;
+    {
+      const float nd2 = fmaf(st[S_DU + 2], st[S_DU + 2],
+                             fmaf(st[S_DU + 1], st[S_DU + 1], st[S_DU] * st[S_DU]));
+      const float nm2 = fmaf(st[S_MU + 2], st[S_MU + 2],
+                             fmaf(st[S_MU + 1], st[S_MU + 1], st[S_MU] * st[S_MU]));
+      const float rd = nd2 > 0.f ? __builtin_amdgcn_rsqf(nd2) : 0.f;
+      const float rm = nm2 > 0.f ? __builtin_amdgcn_rsqf(nm2) : 0.f;
+      nD = nd2 * rd;
+      nM = nm2 * rm;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        ud[k] = st[S_DU + k] * rd;
+        um[k] = st[S_MU + k] * rm;
+      }
+    }
     for (int blk = 0; blk < NB; ++blk) {
       const int bx = (blk % BX) * 8, by = (blk / BX) * 8;
       const bool hitb = active && rect_meets_block(st + S_BB0, bx, by);
@@ -749,11 +766,12 @@ __device__ __forceinline__ void bwd_tile(const TileInfo &ti, const Ws &w, const 
         __builtin_amdgcn_wave_barrier();
       }
       // A row at a time: along the row d and m are (row base) + c (Du, Mu)
-      // for the block column c, so |d|^2 and |m|^2 are quadratics in c whose
-      // coefficients are formed once per row (the backward needs only the
-      // two squared norms, not the vectors); the moments (1, lx, ly, lx^2,
-      // lx ly, ly^2) of the weights follow from per-row sums over
-      // (1, c, c^2). The columns are unrolled, so c is a constant.
+      // for the block column c, and the backward needs only their squared
+      // norms: with u = Du/|Du|, |d|^2 = (|Du| c + db.u)^2 + |db - (db.u) u|^2
+      // (likewise for m), two FMAs per pixel, a sum of squares (no
+      // cancellation between large terms, never negative). The moments
+      // (1, lx, ly, lx^2, lx ly, ly^2) of the weights follow from per-row
+      // sums over (1, c, c^2). The columns are unrolled, so c is a constant.
       const float fbx = (float)bx;
       for (int row = 0; row < 8; ++row) {
         const float ly = (float)(by + row);
@@ -767,12 +785,16 @@ __device__ __forceinline__ void bwd_tile(const TileInfo &ti, const Ws &w, const 
             mb[k] = fmaf(fbx, st[S_MU + k], mb[k]);
           }
         }
-        const float Ad = fmaf(db[2], db[2], fmaf(db[1], db[1], db[0] * db[0]));
-        const float Am = fmaf(mb[2], mb[2], fmaf(mb[1], mb[1], mb[0] * mb[0]));
-        const float Bd =
-            2.f * fmaf(db[2], st[S_DU + 2], fmaf(db[1], st[S_DU + 1], db[0] * st[S_DU]));
-        const float Bm =
-            2.f * fmaf(mb[2], st[S_MU + 2], fmaf(mb[1], st[S_MU + 1], mb[0] * st[S_MU]));
+        const float td = fmaf(db[2], ud[2], fmaf(db[1], ud[1], db[0] * ud[0]));
+        const float tm = fmaf(mb[2], um[2], fmaf(mb[1], um[1], mb[0] * um[0]));
+        float pd[3], pm[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          pd[k] = fmaf(-td, ud[k], db[k]);
+          pm[k] = fmaf(-tm, um[k], mb[k]);
+        }
+        const float Pd = fmaf(pd[2], pd[2], fmaf(pd[1], pd[1], pd[0] * pd[0]));
+        const float Pm = fmaf(pm[2], pm[2], fmaf(pm[1], pm[1], pm[0] * pm[0]));
         float rs[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int col = 0; col < 8; col += 2) {
@@ -780,10 +802,11 @@ __device__ __forceinline__ void bwd_tile(const TileInfo &ti, const Ws &w, const 
           const int p0 = (by + row) * TW + bx + col;
           const int p1 = p0 + 1;
           const float f0c = (float)col, f1c = (float)(col + 1);
-          const float dd0 = col == 0 ? Ad : fmaf(f0c, fmaf(f0c, Cd, Bd), Ad);
-          const float mm0 = col == 0 ? Am : fmaf(f0c, fmaf(f0c, Cm, Bm), Am);
-          const float dd1 = fmaf(f1c, fmaf(f1c, Cd, Bd), Ad);
-          const float mm1 = fmaf(f1c, fmaf(f1c, Cm, Bm), Am);
+          const float sd0 = col == 0 ? td : fmaf(nD, f0c, td);
+          const float sm0 = col == 0 ? tm : fmaf(nM, f0c, tm);
+          const float sd1 = fmaf(nD, f1c, td), sm1 = fmaf(nM, f1c, tm);
+          const float dd0 = fmaf(sd0, sd0, Pd), mm0 = fmaf(sm0, sm0, Pm);
+          const float dd1 = fmaf(sd1, sd1, Pd), mm1 = fmaf(sm1, sm1, Pm);
           const bool f0 = hitb && is_fragment(dd0, mm0, st[S_RC]);
           const bool f1 = hitb && is_fragment(dd1, mm1, st[S_RC]);
           if (f0) bwd_fragment<KMAX>(st, sp_all + p0 * L::kStride, col, dd0, mm0,
