@@ -2,7 +2,9 @@
 
 Two ``rocprofv3 --pmc`` runs of the same command (one with FETCH_SIZE, one
 with WRITE_SIZE; both report KiB per dispatch) are reduced to bytes per
-launch for each kernel. Each counter is scaled by the factor that makes a
+launch for each kernel (each entry keeps the workload and command it was
+measured with; ``--merge`` adds the kernels of another schedule to an
+existing record). Each counter is scaled by the factor that makes a
 plain elementwise copy of known size (run inside the same command) read and
 write exactly its size. The record carries a digest of the kernel sources
 it was measured on, so a reader can tell when the kernels have changed
@@ -111,10 +113,18 @@ def main():
     ap.add_argument("--workload", default="")
     ap.add_argument("--command", default="")
     ap.add_argument("--out", required=True)
+    ap.add_argument("--merge", action="store_true",
+                    help="keep the kernels of an existing record that this run did not launch")
     a = ap.parse_args()
     rec = summarize(a.fetch, a.write, a.copy_bytes)
-    rec["workload"] = a.workload
-    rec["command"] = a.command
+    for k in rec["kernels"].values():
+        k["workload"] = a.workload
+        k["command"] = a.command
+    if a.merge and os.path.exists(a.out):
+        with open(a.out) as fh:
+            old = json.load(fh)
+        for key, k in old.get("kernels", {}).items():
+            rec["kernels"].setdefault(key, k)
     with open(a.out, "w") as fh:
         json.dump(rec, fh, indent=1)
     for k, v in rec["kernels"].items():
