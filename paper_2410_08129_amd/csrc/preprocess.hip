@@ -92,6 +92,30 @@ __device__ inline void activate(const GaussPtrs &gp, int64_t g, Activated &a) {
   a.o = 1.0 / (1.0 + exp(-(double)gp.logits[g]));
 }
 
+// What the backward's view loop needs of an activated Gaussian: the mean
+// and A = R diag(s) (the rest is recomputed after the loop, which keeps
+// fewer registers live while the partials are summed).
+struct ViewAct {
+  double mu[3], A[3][3];
+};
+
+__device__ inline void view_act(const Activated &a, ViewAct &va) {
+  for (int k = 0; k < 3; ++k) {
+    va.mu[k] = a.mu[k];
+    for (int j = 0; j < 3; ++j) va.A[k][j] = a.R[k][j] * a.s[j];
+  }
+}
+
+// View rows of M T from A = R diag(s): Rv = W3 A, mv = W3 mu + t.
+__device__ inline void view_rows_va(const ViewParams &V, const ViewAct &va, double Rv[3][3],
+                                    double mv[3]) {
+  for (int k = 0; k < 3; ++k) {
+    const double w0 = V.w2c[4 * k + 0], w1 = V.w2c[4 * k + 1], w2 = V.w2c[4 * k + 2];
+    mv[k] = w0 * va.mu[0] + w1 * va.mu[1] + w2 * va.mu[2] + (double)V.w2c[4 * k + 3];
+    for (int j = 0; j < 3; ++j) Rv[k][j] = w0 * va.A[0][j] + w1 * va.A[1][j] + w2 * va.A[2][j];
+  }
+}
+
 // View rows of M T: Rv[k][j] = (W3 R diag(s))_{kj}, mv = W3 mu + t.
 __device__ inline void view_rows(const ViewParams &V, const Activated &a, double Rv[3][3],
                                  double mv[3]) {
@@ -740,8 +764,12 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(GaussPtrs gp, GradPtrs g
       total += (uint32_t)tile_count(w.rects[(int64_t)v * cfg.n + g],
                                     tslot_mask(w.tslots[(int64_t)v * cfg.n + g]));
 
-  Activated a;
-  if (total) activate(gp, g, a);
+  ViewAct va;
+  if (total) {
+    Activated a0;
+    activate(gp, g, a0);
+    view_act(a0, va);
+  }
   double gA[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
   double gmu[3] = {0, 0, 0};
   double go = 0.0;
@@ -816,7 +844,7 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(GaussPtrs gp, GradPtrs g
         go += acc[P_O];
         // Pluecker coefficients -> view rows of M T.
         double Rv[3][3], mv[3];
-        view_rows(V, a, Rv, mv);
+        view_rows_va(V, va, Rv, mv);
         double gR[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
         double gm[3] = {0, 0, 0};
         double t[3];
@@ -855,7 +883,8 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(GaussPtrs gp, GradPtrs g
             __float_as_uint(w.records[((int64_t)v * cfg.n + g) * kRecFloats + R_FLAGS]);
         for (int c = 0; c < 3; ++c)
           if (flags & (1u << c)) gc[c] = 0.0;
-        double dv[3] = {a.mu[0] - V.cam_pos[0], a.mu[1] - V.cam_pos[1], a.mu[2] - V.cam_pos[2]};
+        double dv[3] = {va.mu[0] - V.cam_pos[0], va.mu[1] - V.cam_pos[1],
+                        va.mu[2] - V.cam_pos[2]};
         const double dn = sqrt(dot3(dv, dv));
         const double dir[3] = {dv[0] / dn, dv[1] / dn, dv[2] / dn};
         double gdir[3] = {0, 0, 0};
@@ -880,6 +909,8 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(GaussPtrs gp, GradPtrs g
     return;
   }
   // A = R diag(s): to rotation, scales and quaternion.
+  Activated a;
+  activate(gp, g, a);
   double gRot[3][3], gs[3] = {0, 0, 0};
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) {

@@ -207,15 +207,15 @@ __device__ __forceinline__ float eval_mm(const float *c, const PixQ &u) {
   return fmaf(s1, s1, fmaf(s2, s2, c[0]));
 }
 
-// min(x, a) as one median-of-three with -inf (fminf would first
-// canonicalize both operands).
-__device__ __forceinline__ float min_med3(float x, float a) {
-  return __builtin_amdgcn_fmed3f(x, a, -INFINITY);
+// min(x, a) as a compare and a select (fminf canonicalizes its operands
+// first, which costs an instruction per call in the raster loops).
+__device__ __forceinline__ float min_sel(float x, float a) {
+  return x <= a ? x : a;
 }
 
 // alpha = min(alpha_max, o exp(-rho^2 / 2)) with rho^2 = mm / dd.
 __device__ __forceinline__ float frag_alpha(float o, float mm, float inv, float amax) {
-  return min_med3(o * exp2_fast((mm * inv) * kNegHalfLog2e), amax);
+  return min_sel(o * exp2_fast((mm * inv) * kNegHalfLog2e), amax);
 }
 
 __device__ __forceinline__ bool is_fragment(float dd, float mm, float rc) {
@@ -565,7 +565,8 @@ __device__ __forceinline__ void bwd_fragment(const float *st, const float *Pp, i
   const float r2 = mm * inv;
   const float e = exp2_fast(r2 * kNegHalfLog2e);
   const float araw = st[S_O] * e;
-  const float alpha = min_med3(araw, amax);
+  const bool unclamped = araw <= amax;
+  const float alpha = unclamped ? araw : amax;
   const float G0 = Pp[0], G1 = Pp[1], G2 = Pp[2], w1 = Pp[3];
   // tail: dC/dalpha = w1 (c - c_tail) - T P (c_bg - c_tail) / (1 - alpha),
   // dC/dc = w1 alpha; core: the pixel's precomputed T_i (c_i - B_i) and T_i
@@ -582,7 +583,7 @@ __device__ __forceinline__ void bwd_fragment(const float *st, const float *Pp, i
   acc[14] = fmaf(wc, G1, acc[14]);
   acc[15] = fmaf(wc, G2, acc[15]);
   // Where alpha is clamped, o and rho^2 receive no gradient.
-  const float g = (araw <= amax) ? dLda : 0.f;
+  const float g = unclamped ? dLda : 0.f;
   {
     acc[12] = fmaf(g, e, acc[12]);
     const float s1 = -alpha * g * inv;      // weight of m: 2 dL/drho^2 / |d|^2
@@ -602,6 +603,28 @@ __device__ __forceinline__ void bwd_fragment(const float *st, const float *Pp, i
   }
 }
 
+// Waves per backward workgroup. A tile's 64-instance chunks are dealt to
+// its waves round-robin, so waves whose share ends early idle until the
+// tile is done: with four waves ~25% of the wave time at 1080p; fewer waves
+// idle less but stage the tile's per-pixel factors for fewer waves.
+#ifndef HTGS_BWD_WAVES_SMALL
+#define HTGS_BWD_WAVES_SMALL 2
+#endif
+#ifndef HTGS_BWD_WAVES_MID
+#define HTGS_BWD_WAVES_MID 4
+#endif
+template <int TW, int TH>
+constexpr int bwd_waves() {
+  return TW * TH <= 64 ? HTGS_BWD_WAVES_SMALL : (TW * TH <= 128 ? HTGS_BWD_WAVES_MID : 4);
+}
+
+// Target waves per SIMD of the backward (register budget; HIP's second
+// launch-bounds argument is a minimum number of waves per execution unit).
+template <int KMAX, int TW>
+constexpr int bwd_simd_waves() {
+  return (TW == 8 && KMAX <= 8) ? 5 : ((TW == 8 && KMAX <= 16) ? 4 : 1);
+}
+
 template <int KMAX, int TW, int TH, bool EXACT>
 __device__ __forceinline__ void bwd_tile(const TileInfo &ti, const Ws &w, const ViewSet &vs,
                                          const KCfg &cfg, const float *__restrict__ state,
@@ -611,9 +634,11 @@ __device__ __forceinline__ void bwd_tile(const TileInfo &ti, const Ws &w, const 
   constexpr int BX = TW / 8;
   using L = PixLayout<KMAX>;
   __shared__ float4 s_pix[NT * L::kStride / 4];
+  constexpr int BW = bwd_waves<TW, TH>();
+  constexpr int BT = 64 * BW;
   // per wave, for the 8x8 block being walked: [block pixel][lane] = core
   // index + 1 of the lane's instance at that pixel, 0 if not in the core
-  __shared__ uint8_t s_slot[4][64][64];
+  __shared__ uint8_t s_slot[BW][64][64];
 
   const ViewParams &V = vs.v[ti.v];
   const int tid = threadIdx.x;
@@ -624,7 +649,7 @@ __device__ __forceinline__ void bwd_tile(const TileInfo &ti, const Ws &w, const 
   float *sp_all = reinterpret_cast<float *>(s_pix);
 
   // Per-pixel adjoint factors.
-  for (int p = tid; p < NT; p += 256) {
+  for (int p = tid; p < NT; p += BT) {
     const int px = px0 + p % TW, py = py0 + p / TW;
     float *Pp = sp_all + p * L::kStride;
     float G[3] = {0.f, 0.f, 0.f}, w1 = 0.f, q1 = 0.f, q2 = 0.f;
@@ -703,7 +728,7 @@ __device__ __forceinline__ void bwd_tile(const TileInfo &ti, const Ws &w, const 
   const uint32_t count = rg.y - rg.x;
   const uint32_t nch = (count + 63u) >> 6;
   const float amax = cfg.alpha_max;
-  for (uint32_t c = wave; c < nch; c += 4) {
+  for (uint32_t c = wave; c < nch; c += BW) {
     const uint32_t j = rg.x + c * 64u + lane;
     const bool active = j < rg.y;
     float st[S_FLOATS];
@@ -885,7 +910,7 @@ __global__ void __launch_bounds__(TW *TH) k_raster_fwd(Ws w, ViewSet vs, KCfg cf
 }
 
 template <int KMAX, int TW, int TH, bool EXACT>
-__global__ void __launch_bounds__(256, (TW == 8 && KMAX <= 8) ? 5 : ((TW == 8 && KMAX <= 16) ? 4 : 1))
+__global__ void __launch_bounds__((64 * bwd_waves<TW, TH>()), (bwd_simd_waves<KMAX, TW>()))
     k_raster_bwd(Ws w, ViewSet vs, KCfg cfg, const float *__restrict__ state,
                  const uint32_t *__restrict__ vals) {
 #define HTGS_BWD_BODY(T) bwd_tile<KMAX, TW, TH, EXACT>(T, w, vs, cfg, state, vals)
@@ -935,8 +960,9 @@ static hipError_t bwd_launch(const Ws &w, const ViewSet &vs, const KCfg &cfg, co
                              const uint32_t *vals, hipStream_t s) {
   int blocks = 8 * ((vs.total_tiles + 7) / 8);
   auto *kern = k_raster_bwd<KMAX, TW, TH, EXACT>;
-  if (cfg.persistent) blocks = resident_blocks((const void *)kern, 256, vs.total_tiles);
-  hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), 0, s, w, vs, cfg, state, vals);
+  constexpr int BT = 64 * bwd_waves<TW, TH>();
+  if (cfg.persistent) blocks = resident_blocks((const void *)kern, BT, vs.total_tiles);
+  hipLaunchKernelGGL(kern, dim3(blocks), dim3(BT), 0, s, w, vs, cfg, state, vals);
   return hipGetLastError();
 }
 
