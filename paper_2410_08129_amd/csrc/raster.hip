@@ -728,9 +728,19 @@ __device__ __forceinline__ void bwd_tile(const TileInfo &ti, const Ws &w, const 
   const uint32_t count = rg.y - rg.x;
   const uint32_t nch = (count + 63u) >> 6;
   const float amax = cfg.alpha_max;
-  for (uint32_t c = wave; c < nch; c += BW) {
+  // Chunk schedule. In general a wave takes every BW-th chunk over all of
+  // the tile's 8x8 blocks. With two blocks and four waves (16x8, 8x16
+  // tiles) a pair of waves shares each chunk instead, one block each, and
+  // the pairs alternate chunks; the block-1 wave hands its sums to the
+  // block-0 wave, which writes the partial. A tile whose chunk count is not
+  // a multiple of the wave count then leaves fewer waves idle.
+  constexpr bool PAIRS = (NB == 2 && BW == 4);
+  const int myblk = PAIRS ? (wave >> 1) : -1;
+  const uint32_t c_end = PAIRS ? 2u * ((nch + 1u) >> 1) : nch;  // uniform per block when PAIRS
+  const uint32_t c_step = PAIRS ? 2u : (uint32_t)BW;
+  for (uint32_t c = PAIRS ? (uint32_t)(wave & 1) : (uint32_t)wave; c < c_end; c += c_step) {
     const uint32_t j = rg.x + c * 64u + lane;
-    const bool active = j < rg.y;
+    const bool active = c < nch && j < rg.y;
     float st[S_FLOATS];
 #pragma unroll
     for (int k = 0; k < S_FLOATS; ++k) st[k] = 0.f;
@@ -745,7 +755,7 @@ __device__ __forceinline__ void bwd_tile(const TileInfo &ti, const Ws &w, const 
       float rec[kRecFloats];
       load_record(recs, gid, rec);
       stage_record(rec, px0, py0, st);
-      slot = tslot_slot(w.tslots[(int64_t)ti.v * cfg.n + gid], ti.tx, ti.ty);
+      if (myblk <= 0) slot = tslot_slot(w.tslots[(int64_t)ti.v * cfg.n + gid], ti.tx, ti.ty);
     }
     // acc: d-moments (6), m-moments (6), dL/do, dL/drgb (3)
     float acc[16];
@@ -769,6 +779,7 @@ __device__ __forceinline__ void bwd_tile(const TileInfo &ti, const Ws &w, const 
       }
     }
     for (int blk = 0; blk < NB; ++blk) {
+      if (PAIRS && blk != myblk) continue;
       const int bx = (blk % BX) * 8, by = (blk / BX) * 8;
       const bool hitb = active && rect_meets_block(st + S_BB0, bx, by);
       if (__ballot(hitb) == 0ull) continue;
@@ -862,7 +873,21 @@ __device__ __forceinline__ void bwd_tile(const TileInfo &ti, const Ws &w, const 
       }
       __builtin_amdgcn_wave_barrier();
     }
-    if (active && (uint64_t)slot < (uint64_t)w.capacity) {
+    if constexpr (PAIRS) {
+      // The block-1 wave's core table is free now: it carries the sums.
+      float *xch = reinterpret_cast<float *>(&s_slot[2 + (wave & 1)][0][0]);
+      if (myblk == 1) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) xch[k * 64 + lane] = acc[k];
+      }
+      __syncthreads();
+      if (myblk == 0) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) acc[k] += xch[k * 64 + lane];
+      }
+      __syncthreads();  // before the block-1 waves rebuild their tables
+    }
+    if (myblk <= 0 && active && (uint64_t)slot < (uint64_t)w.capacity) {
       // Gradients of the record coefficients in camera coordinates
       // u = (x - cx)/fx, v = (y - cy)/fy: d = D0 + u Du + v Dv with u = ut + lx/fx.
       const float ut = ((float)px0 + 0.5f - V.cx) / V.fx, vt = ((float)py0 + 0.5f - V.cy) / V.fy;
