@@ -410,6 +410,10 @@ __global__ void __launch_bounds__(kPreThreads) k_preprocess(GaussPtrs gp, KCfg c
                                                              Ws w) {
   __shared__ uint32_t s_ticket;
   constexpr int NVL = MV ? kMaxViews : 1;
+  // instances formed before the look-back (single view: the batched form's
+  // per-view tables already fill most of the LDS)
+  constexpr int NSTAGE = MV ? 0 : 3072;
+  __shared__ uint32_t s_ekey[NSTAGE > 0 ? NSTAGE : 1], s_egid[NSTAGE > 0 ? NSTAGE : 1];
   __shared__ uint32_t s_start[NVL * kPreThreads + 1];
   __shared__ uint32_t s_vrect[NVL][kPreThreads];
   __shared__ unsigned long long s_vmask[NVL][kPreThreads];
@@ -474,13 +478,73 @@ __global__ void __launch_bounds__(kPreThreads) k_preprocess(GaussPtrs gp, KCfg c
   if (tid == 0) s_start[nent] = block_total;
   __syncthreads();
 
+  // The workgroup's count is published first. When the workgroup's
+  // instances fit, they are formed into LDS before the look-back, so the
+  // wait for the predecessors' prefixes overlaps that work; otherwise they
+  // are formed after it, straight to memory.
+  if (tid == 0) {
+    if (blk == 0) st_rel_u64(&w.pp_look[0], kFlagP64 | block_total);
+    else st_rel_u64(&w.pp_look[blk], kFlagA64 | block_total);
+  }
+  const bool staged = block_total <= (uint32_t)NSTAGE;
+
+  // Instance e of the workgroup: its tile key and Gaussian index.
+  auto make_instance = [&](uint32_t e, uint32_t &key, uint32_t &gid) {
+    // the last (group, view, lane) entry starting at or before e owns it
+    int lo = 0, hi = nent;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (s_start[mid] <= e) lo = mid; else hi = mid;
+    }
+    uint32_t rank = e - s_start[lo];
+    const int grp = lo / (64 * nviews);
+    const int v = MV ? (lo >> 6) - grp * nviews : 0;
+    const int owner = grp * 64 + (lo & 63);
+    gid = (uint32_t)(blk * kPreThreads + owner);
+    const uint32_t pr = s_vrect[v][owner];
+    const uint32_t rw = pr >> 20;
+    // With a tile mask, the rank-th surviving tile is the rank-th set bit.
+    const unsigned long long mk = s_vmask[v][owner];
+    if (mk) {
+      unsigned long long m = mk;
+      uint32_t pos = 0, k = rank;
+#pragma unroll
+      for (int wd = 32; wd >= 1; wd >>= 1) {
+        const uint32_t c = (uint32_t)__popcll(m & ((1ull << wd) - 1ull));
+        if (k >= c) {
+          k -= c;
+          m >>= wd;
+          pos += (uint32_t)wd;
+        }
+      }
+      rank = pos;
+    }
+    // rank / rw and rank % rw; rank < 2^20 and rw <= 1024 are exact in
+    // float32, and the quotient estimate is off by at most one
+    int qy = (int)((float)rank * __builtin_amdgcn_rcpf((float)rw));
+    int rx = (int)rank - qy * (int)rw;
+    if (rx < 0) { --qy; rx += (int)rw; }
+    if (rx >= (int)rw) { ++qy; rx -= (int)rw; }
+    const uint32_t ty = ((pr >> 10) & 1023u) + (uint32_t)qy;
+    const uint32_t tx = (pr & 1023u) + (uint32_t)rx;
+    key = (uint32_t)vs.v[v].tile_base + ty * (uint32_t)vs.v[v].tiles_x + tx;
+    for (int p = 0; p < w.passes; ++p) atomicAdd(&s_hist[p][(key >> (8 * p)) & 255u], 1u);
+  };
+  if constexpr (NSTAGE > 0) {
+    if (staged) {
+      for (uint32_t e = tid; e < block_total; e += kPreThreads) {
+        uint32_t key, gid;
+        make_instance(e, key, gid);
+        s_ekey[e] = key;
+        s_egid[e] = gid;
+      }
+    }
+  }
+
   // Decoupled look-back across workgroups (in ticket order).
   if (tid == 0) {
     unsigned long long excl = 0;
-    if (blk == 0) {
-      st_rel_u64(&w.pp_look[0], kFlagP64 | block_total);
-    } else {
-      st_rel_u64(&w.pp_look[blk], kFlagA64 | block_total);
+    if (blk > 0) {
       int64_t j = blk - 1;
       int spins = 0;
       while (true) {
@@ -535,54 +599,22 @@ __global__ void __launch_bounds__(kPreThreads) k_preprocess(GaussPtrs gp, KCfg c
     }
   }
 
-  // Emit instances, one per loop iteration, balanced over the workgroup.
+  // Instances to memory, one per loop iteration, balanced over the workgroup.
   uint16_t *k16 = reinterpret_cast<uint16_t *>(w.keys[0]);
   uint32_t *k32 = reinterpret_cast<uint32_t *>(w.keys[0]);
   for (uint32_t e = tid; e < block_total; e += kPreThreads) {
-    // the last (group, view, lane) entry starting at or before e owns it
-    int lo = 0, hi = nent;
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (s_start[mid] <= e) lo = mid; else hi = mid;
+    uint32_t key, gid;
+    if (NSTAGE > 0 && staged) {
+      key = s_ekey[e];
+      gid = s_egid[e];
+    } else {
+      make_instance(e, key, gid);
     }
-    uint32_t rank = e - s_start[lo];
-    const int grp = lo / (64 * nviews);
-    const int v = MV ? (lo >> 6) - grp * nviews : 0;
-    const int owner = grp * 64 + (lo & 63);
-    const int64_t gi = blk * kPreThreads + owner;
-    const uint32_t pr = s_vrect[v][owner];
-    const uint32_t rw = pr >> 20;
-    // With a tile mask, the rank-th surviving tile is the rank-th set bit.
-    const unsigned long long mk = s_vmask[v][owner];
-    if (mk) {
-      unsigned long long m = mk;
-      uint32_t pos = 0, k = rank;
-#pragma unroll
-      for (int wd = 32; wd >= 1; wd >>= 1) {
-        const uint32_t c = (uint32_t)__popcll(m & ((1ull << wd) - 1ull));
-        if (k >= c) {
-          k -= c;
-          m >>= wd;
-          pos += (uint32_t)wd;
-        }
-      }
-      rank = pos;
-    }
-    // rank / rw and rank % rw; rank < 2^20 and rw <= 1024 are exact in
-    // float32, and the quotient estimate is off by at most one
-    int qy = (int)((float)rank * __builtin_amdgcn_rcpf((float)rw));
-    int rx = (int)rank - qy * (int)rw;
-    if (rx < 0) { --qy; rx += (int)rw; }
-    if (rx >= (int)rw) { ++qy; rx -= (int)rw; }
-    const uint32_t ty = ((pr >> 10) & 1023u) + (uint32_t)qy;
-    const uint32_t tx = (pr & 1023u) + (uint32_t)rx;
-    const uint32_t key = (uint32_t)vs.v[v].tile_base + ty * (uint32_t)vs.v[v].tiles_x + tx;
     const unsigned long long pos = base + e;
     if (pos < (unsigned long long)w.capacity) {
       if (w.key16) k16[pos] = (uint16_t)key; else k32[pos] = key;
-      w.vals[0][pos] = (uint32_t)gi;
+      w.vals[0][pos] = gid;
     }
-    for (int p = 0; p < w.passes; ++p) atomicAdd(&s_hist[p][(key >> (8 * p)) & 255u], 1u);
   }
   __syncthreads();
   for (int p = 0; p < w.passes; ++p) {
