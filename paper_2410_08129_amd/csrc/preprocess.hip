@@ -802,9 +802,11 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(GaussPtrs gp, GradPtrs g
     activate(gp, g, a0);
     view_act(a0, va);
   }
-  double gA[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-  double gmu[3] = {0, 0, 0};
-  double go = 0.0;
+  // per-view terms are formed in float64 and summed over the views in
+  // float32 (at most 16 terms), which keeps fewer registers live
+  float gA[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  float gmu[3] = {0, 0, 0};
+  float go = 0.f;
   float gsh[3 * NB];
 #pragma unroll
   for (int k = 0; k < 3 * NB; ++k) gsh[k] = 0.f;
@@ -904,11 +906,11 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(GaussPtrs gp, GradPtrs g
           for (int j = 0; j < 3; ++j) {
             double s_ = 0.0;
             for (int k = 0; k < 3; ++k) s_ += (double)V.w2c[4 * k + i] * gR[k][j];
-            gA[i][j] += s_;
+            gA[i][j] += (float)s_;
           }
           double sm = 0.0;
           for (int k = 0; k < 3; ++k) sm += (double)V.w2c[4 * k + i] * gm[k];
-          gmu[i] += sm;
+          gmu[i] += (float)sm;
         }
         // Colour: SH coefficients and the viewing direction.
         const uint32_t flags =
@@ -924,7 +926,7 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(GaussPtrs gp, GradPtrs g
         sh_dots<NB>(shrow, gc, wsv);
         sh_backward<DEG>(wsv, dir, gc, gsh, gdir);
         const double radial = dot3(gdir, dir);
-        for (int j = 0; j < 3; ++j) gmu[j] += (gdir[j] - dir[j] * radial) / dn;
+        for (int j = 0; j < 3; ++j) gmu[j] += (float)((gdir[j] - dir[j] * radial) / dn);
       }
       __builtin_amdgcn_wave_barrier();
     }
