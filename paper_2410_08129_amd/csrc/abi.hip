@@ -30,7 +30,7 @@ int64_t align_up(int64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
   int64_t status, total, pp_look, hist, sort_look, ranges, order_hist, zero_end;
-  int64_t records, rects, tslots, order, keys0, keys1, vals0, vals1, partials, bytes;
+  int64_t records, rects, tslots, cflags, order, keys0, keys1, vals0, vals1, partials, bytes;
   int64_t capacity, max_chunks;
   int32_t key_bits, passes, key16;
 };
@@ -60,6 +60,7 @@ Layout make_layout(int64_t n, int n_views, int64_t total_tiles, int64_t capacity
   L.zero_end = o;
   L.records = o; o = align_up(o + (int64_t)n_views * n * kRecFloats * 4);
   L.rects = o; o = align_up(o + (int64_t)n_views * n * 16);
+  L.cflags = o; o = align_up(o + (int64_t)n_views * n);
   L.tslots = o; o = align_up(o + (int64_t)n_views * n * 16);
   L.order = o; o = align_up(o + 4 * total_tiles);
   L.keys0 = o; o = align_up(o + kb * capacity);
@@ -98,6 +99,7 @@ Ws make_ws(void *base, const Layout &L) {
   w.records = reinterpret_cast<float *>(b + L.records);
   w.rects = reinterpret_cast<int4 *>(b + L.rects);
   w.tslots = reinterpret_cast<uint4 *>(b + L.tslots);
+  w.cflags = reinterpret_cast<uint8_t *>(b + L.cflags);
   w.keys[0] = b + L.keys0;
   w.keys[1] = b + L.keys1;
   w.vals[0] = reinterpret_cast<uint32_t *>(b + L.vals0);

@@ -27,7 +27,7 @@ enum RecField {
   R_O = 22,     // opacity
   R_RC = 23,    // rho_c (squared cutoff radius)
   R_RGB = 24,   // colour (3)
-  R_FLAGS = 27, // bit c set: colour channel c was clamped at 0
+  R_FLAGS = 27, // bit c set: colour channel c was clamped at 0 (also in Ws::cflags)
   R_IX = 28, R_IY = 29,  // reference pixel, int32 bit patterns
   R_BB0 = 30,   // covered pixel rect: x0 | y0 << 16
   R_BB1 = 31    //                     x1 | y1 << 16 (inclusive)
@@ -109,6 +109,7 @@ struct Ws {
   float *records;              // [views][n][32]
   int4 *rects;                 // [views][n] tile rect (tx0, ty0, tx1, ty1), empty if tx0 > tx1
   uint4 *tslots;               // [views][n] tile-slot descriptor (see below)
+  uint8_t *cflags;             // [views][n] bit c: colour channel c was clamped at 0
   void *keys[2];
   uint32_t *vals[2];
   float *partials;             // [capacity][24]

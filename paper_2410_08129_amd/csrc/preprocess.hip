@@ -380,6 +380,7 @@ __device__ inline uint32_t preprocess_view(const GaussPtrs &gp, const KCfg &cfg,
     col[c] = acc;
   }
   dst[R_RGB / 4] = make_float4(col[0], col[1], col[2], __uint_as_float(flags));
+  w.cflags[(int64_t)v * cfg.n + g] = (uint8_t)flags;
 
   unsigned long long mask = 0ull;
   if (cull) {
@@ -913,8 +914,7 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(GaussPtrs gp, GradPtrs g
           gmu[i] += (float)sm;
         }
         // Colour: SH coefficients and the viewing direction.
-        const uint32_t flags =
-            __float_as_uint(w.records[((int64_t)v * cfg.n + g) * kRecFloats + R_FLAGS]);
+        const uint32_t flags = w.cflags[(int64_t)v * cfg.n + g];
         for (int c = 0; c < 3; ++c)
           if (flags & (1u << c)) gc[c] = 0.0;
         double dv[3] = {va.mu[0] - V.cam_pos[0], va.mu[1] - V.cam_pos[1],
