@@ -823,12 +823,10 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(GaussPtrs gp, GradPtrs g
 #pragma unroll
       for (int k = 0; k < 22; ++k) s_acc[wave][k][lane] = 0.f;
       __builtin_amdgcn_wave_barrier();
-      for (uint64_t base = lo; base < hi; base += 64) {
-        const uint64_t sl = base + lane;
-        const bool valid = sl < hi;
-        float v22[22];
-        uint32_t seg = 0xffffffffu;
-        if (valid) {
+      // Partials of slot sl (zeros and no segment past the range).
+      auto load_partial = [&](uint64_t sl, float *v22, uint32_t &seg) {
+        seg = 0xffffffffu;
+        if (sl < hi) {
           const float4 *P = reinterpret_cast<const float4 *>(w.partials + (int64_t)sl * kPartialFloats);
 #pragma unroll
           for (int k = 0; k < 5; ++k) {
@@ -842,6 +840,19 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(GaussPtrs gp, GradPtrs g
 #pragma unroll
           for (int k = 0; k < 22; ++k) v22[k] = 0.f;
         }
+      };
+      // The next 64 slots are loaded while this chunk is scanned.
+      float nv[22];
+      uint32_t nseg;
+      load_partial(lo + lane, nv, nseg);
+      for (uint64_t base = lo; base < hi; base += 64) {
+        const uint64_t sl = base + lane;
+        const bool valid = sl < hi;
+        float v22[22];
+        uint32_t seg = nseg;
+#pragma unroll
+        for (int k = 0; k < 22; ++k) v22[k] = nv[k];
+        if (base + 64 < hi) load_partial(base + 64 + lane, nv, nseg);
         // Inclusive segmented scan over the wave with DPP lane moves (no
         // LDS): shifts by 1, 2, 4, 8 inside each row of 16 lanes, then the
         // last lane of row 0 / row 2 into rows 1 / 3, then lane 31 into rows
