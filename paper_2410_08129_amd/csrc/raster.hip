@@ -787,9 +787,11 @@ __device__ __forceinline__ void bwd_tile(const TileInfo &ti, const Ws &w, const 
       {
         const int p = (by + (lane >> 3)) * TW + bx + (lane & 7);
         const float *Pp = sp_all + p * L::kStride;
-        uint32_t *row = reinterpret_cast<uint32_t *>(&s_slot[wave][lane][0]);
+        // cleared with consecutive lanes on consecutive words (no bank
+        // conflicts), then each lane fills its own pixel's row
+        uint32_t *tab = reinterpret_cast<uint32_t *>(&s_slot[wave][0][0]);
 #pragma unroll
-        for (int k = 0; k < 16; ++k) row[k] = 0u;
+        for (int k = 0; k < 16; ++k) tab[k * 64 + lane] = 0u;
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int i = 0; i < KMAX; ++i) {
