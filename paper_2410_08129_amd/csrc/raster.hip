@@ -236,6 +236,13 @@ struct TileInfo {
   int t, v, tx, ty;
 };
 
+// Float offset of a tile's forward state (tile-major layout: nval values
+// of nt pixels per tile, tiles row-major inside their view).
+__device__ __forceinline__ int64_t tile_state_off(const ViewParams &V, const TileInfo &ti,
+                                                  int nval, int nt) {
+  return V.state_off + ((int64_t)ti.ty * V.tiles_x + ti.tx) * nval * nt;
+}
+
 __device__ __forceinline__ bool tile_info(const ViewSet &vs, const KCfg &cfg, const Ws &w,
                                           TileInfo &ti) {
   if (cfg.cost_order) {
@@ -521,21 +528,23 @@ __device__ __forceinline__ void fwd_tile(const TileInfo &ti, const Ws &w, const 
   V.out_rgb[npix + pix] = fmaf(T, X1, C1);
   V.out_rgb[2 * npix + pix] = fmaf(T, X2, C2);
   if (state) {
-    float *sp = state + V.state_off + pix;
+    // tile-major state: this tile's values, value by value, each over the
+    // tile's 8x8 blocks (this wave's block is block number `wave`)
+    float *sp = state + tile_state_off(V, ti, 3 * K + 6, NT) + wave * 64 + lane;
 #pragma unroll
     for (int i = 0; i < KMAX; ++i) {
       if (i < K) {
-        sp[(int64_t)i * npix] = __int_as_float(gids[i]);
-        sp[(int64_t)(K + i) * npix] = ca[i];
-        sp[(int64_t)(2 * K + i) * npix] = __int_as_float(cp[i]);
+        sp[(int64_t)i * NT] = __int_as_float(gids[i]);
+        sp[(int64_t)(K + i) * NT] = ca[i];
+        sp[(int64_t)(2 * K + i) * NT] = __int_as_float(cp[i]);
       }
     }
-    sp[(int64_t)(3 * K) * npix] = T;
-    sp[(int64_t)(3 * K + 1) * npix] = A;
-    sp[(int64_t)(3 * K + 2) * npix] = S0;
-    sp[(int64_t)(3 * K + 3) * npix] = S1;
-    sp[(int64_t)(3 * K + 4) * npix] = S2;
-    sp[(int64_t)(3 * K + 5) * npix] = P;
+    sp[(int64_t)(3 * K) * NT] = T;
+    sp[(int64_t)(3 * K + 1) * NT] = A;
+    sp[(int64_t)(3 * K + 2) * NT] = S0;
+    sp[(int64_t)(3 * K + 3) * NT] = S1;
+    sp[(int64_t)(3 * K + 4) * NT] = S2;
+    sp[(int64_t)(3 * K + 5) * NT] = P;
   }
 }
 
@@ -648,9 +657,14 @@ __device__ __forceinline__ void bwd_tile(const TileInfo &ti, const Ws &w, const 
   const int64_t npix = (int64_t)V.width * V.height;
   float *sp_all = reinterpret_cast<float *>(s_pix);
 
-  // Per-pixel adjoint factors.
-  for (int p = tid; p < NT; p += BT) {
-    const int px = px0 + p % TW, py = py0 + p / TW;
+  // Per-pixel adjoint factors. Threads walk the pixels in the state's
+  // order (8x8 blocks, row-major inside), so consecutive threads read
+  // consecutive state words.
+  const float *tstate = state + tile_state_off(V, ti, 3 * K + 6, NT);
+  for (int ps = tid; ps < NT; ps += BT) {
+    const int lxp = ((ps >> 6) % BX) * 8 + (ps & 7), lyp = ((ps >> 6) / BX) * 8 + ((ps >> 3) & 7);
+    const int p = lyp * TW + lxp;
+    const int px = px0 + lxp, py = py0 + lyp;
     float *Pp = sp_all + p * L::kStride;
     float G[3] = {0.f, 0.f, 0.f}, w1 = 0.f, q1 = 0.f, q2 = 0.f;
     int pos[KMAX];
@@ -660,25 +674,25 @@ __device__ __forceinline__ void bwd_tile(const TileInfo &ti, const Ws &w, const 
     if (px < V.width && py < V.height) {
       const int64_t pix = (int64_t)py * V.width + px;
       for (int c = 0; c < 3; ++c) G[c] = V.grad_rgb[c * npix + pix];
-      const float *sp = state + V.state_off + pix;
+      const float *sp = tstate + ps;
       float ca[KMAX], cc[KMAX][3];
 #pragma unroll
       for (int i = 0; i < KMAX; ++i) {
         ca[i] = 0.f; cc[i][0] = cc[i][1] = cc[i][2] = 0.f;
         if (i < K) {
-          const int id = __float_as_int(sp[(int64_t)i * npix]);
-          ca[i] = sp[(int64_t)(K + i) * npix];
-          pos[i] = __float_as_int(sp[(int64_t)(2 * K + i) * npix]);
+          const int id = __float_as_int(sp[(int64_t)i * NT]);
+          ca[i] = sp[(int64_t)(K + i) * NT];
+          pos[i] = __float_as_int(sp[(int64_t)(2 * K + i) * NT]);
           if (id >= 0) {
             const float *r = recs + (int64_t)id * kRecFloats + R_RGB;
             cc[i][0] = r[0]; cc[i][1] = r[1]; cc[i][2] = r[2];
           }
         }
       }
-      const float A = sp[(int64_t)(3 * K + 1) * npix];
-      const float S[3] = {sp[(int64_t)(3 * K + 2) * npix], sp[(int64_t)(3 * K + 3) * npix],
-                          sp[(int64_t)(3 * K + 4) * npix]};
-      const float Pt = sp[(int64_t)(3 * K + 5) * npix];
+      const float A = sp[(int64_t)(3 * K + 1) * NT];
+      const float S[3] = {sp[(int64_t)(3 * K + 2) * NT], sp[(int64_t)(3 * K + 3) * NT],
+                          sp[(int64_t)(3 * K + 4) * NT]};
+      const float Pt = sp[(int64_t)(3 * K + 5) * NT];
       float T = 1.f;
 #pragma unroll
       for (int i = 0; i < KMAX; ++i) {

@@ -321,14 +321,26 @@ def export_bins(params, sh_degree, cams, st, ws, stream=None):
 
 
 def state_planes(frame: Frame, view: int = 0):
-    """Views the per-pixel forward state of one view as named planes."""
+    """Copies the per-pixel forward state of one view into named planes
+    ([values, H, W]); the state itself is tile-major (see htgs.h)."""
     K = int(frame.st.K)
+    tw, th = int(frame.st.tile_w), int(frame.st.tile_h)
+    nval = 3 * K + 6
+
+    def tiles(c):
+        return (c.width + tw - 1) // tw, (c.height + th - 1) // th
+
     off = 0
     for c in frame.cams[:view]:
-        off += (3 * K + 6) * c.width * c.height
+        tx, ty = tiles(c)
+        off += nval * tx * ty * tw * th
     cam = frame.cams[view]
-    npix = cam.width * cam.height
-    blk = frame.state[off: off + (3 * K + 6) * npix].view(3 * K + 6, cam.height, cam.width)
+    tx, ty = tiles(cam)
+    bx, by = tw // 8, th // 8
+    blk = frame.state[off: off + nval * tx * ty * tw * th]
+    # [tile row, tile col, value, block row, block col, row, col]
+    blk = blk.view(ty, tx, nval, by, bx, 8, 8).permute(2, 0, 3, 5, 1, 4, 6)
+    blk = blk.reshape(nval, ty * th, tx * tw)[:, :cam.height, :cam.width].contiguous()
     return dict(core_ids=blk[:K].view(torch.int32), core_alpha=blk[K:2 * K],
                 core_pos=blk[2 * K:3 * K].view(torch.int32), T=blk[3 * K], A=blk[3 * K + 1],
                 S=blk[3 * K + 2: 3 * K + 5], P=blk[3 * K + 5])
