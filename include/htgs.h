@@ -149,11 +149,12 @@ int htgs_workspace_bytes(int64_t n, const htgs_camera *cams, int32_t n_views,
                          int64_t *bytes_out);
 
 /* Bytes of the per-pixel forward state of ALL views (caller-owned, kept from
- * forward to backward): per pixel 12K+24 bytes, 3K+6 float32 values: K core
+ * forward to backward): per pixel 24K+24 bytes, 6K+6 float32 values: K core
  * Gaussian ids (int32, -1 = empty, front to back), K core alphas, K core
- * positions in the pixel's tile list (int32, used by the backward),
- * T_{n+1}, tail sum of alpha, tail sum of alpha*rgb (3 values), tail
- * product of (1-alpha). Layout, per view in order: tile by tile (row-major
+ * positions in the pixel's tile list (int32, used by the backward), K core
+ * colours (r, g, b each), T_{n+1}, tail sum of alpha, tail sum of
+ * alpha*rgb (3 values), tail product of (1-alpha). Layout, per view in
+ * order: tile by tile (row-major
  * over the view's tiles, each tile padded to full size at the image edge);
  * inside a tile, value by value; inside a value, the tile's 8x8 pixel
  * blocks row-major, inside a block its pixels row-major. (A tile's values

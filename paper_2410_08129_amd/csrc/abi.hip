@@ -210,7 +210,7 @@ ViewSet make_views(const htgs_camera *cams, int32_t n_views, const htgs_config *
     P.out_rgb = out_rgb ? out_rgb[v] : nullptr;
     P.grad_rgb = grad_rgb ? grad_rgb[v] : nullptr;
     tiles += (int64_t)P.tiles_x * P.tiles_y;
-    state_off += (int64_t)(3 * cfg->K + 6) * P.tiles_x * P.tiles_y * cfg->tile_w * cfg->tile_h;
+    state_off += (int64_t)state_values(cfg->K) * P.tiles_x * P.tiles_y * cfg->tile_w * cfg->tile_h;
   }
   vs.total_tiles = (int32_t)tiles;
   return vs;
@@ -414,7 +414,7 @@ int htgs_state_bytes(const htgs_camera *cams, int32_t n_views, const htgs_config
   for (int v = 0; v < n_views; ++v) {
     const int64_t tx = (cams[v].width + cfg->tile_w - 1) / cfg->tile_w;
     const int64_t ty = (cams[v].height + cfg->tile_h - 1) / cfg->tile_h;
-    b += (int64_t)(12 * cfg->K + 24) * tx * ty * cfg->tile_w * cfg->tile_h;
+    b += (int64_t)4 * state_values(cfg->K) * tx * ty * cfg->tile_w * cfg->tile_h;
   }
   *bytes_out = b;
   return HTGS_OK;

@@ -124,6 +124,10 @@ constexpr uint32_t kFlagA32 = 1u << 30, kFlagP32 = 2u << 30, kMask32 = (1u << 30
 constexpr unsigned long long kFlagA64 = 1ull << 62, kFlagP64 = 2ull << 62,
                              kMask64 = (1ull << 62) - 1ull;
 constexpr int kSpinLimit = 1 << 22;
+// Forward state values per pixel: K ids, K alphas, K list positions, K rgb
+// triples, T, sum alpha, sum alpha rgb (3), prod (1 - alpha).
+__host__ __device__ constexpr int state_values(int K) { return 6 * K + 6; }
+
 constexpr int kLookWindow = 4;   // look-back words read per round trip
 
 enum StatusBits : uint32_t { ST_OVERFLOW = 1u, ST_SPIN = 2u };

@@ -475,11 +475,12 @@ __device__ __forceinline__ void fwd_tile(const TileInfo &ti, const Ws &w, const 
   float Ac = 0.f, Sc0 = 0.f, Sc1 = 0.f, Sc2 = 0.f;
   uint32_t ncore = 0;
   int gids[KMAX];
-  float ca[KMAX];
+  float ca[KMAX], crgb[KMAX][3];
 #pragma unroll
   for (int i = 0; i < KMAX; ++i) {
     gids[i] = -1;
     ca[i] = 0.f;
+    crgb[i][0] = crgb[i][1] = crgb[i][2] = 0.f;
     if (i < K && cp[i] >= 0) {
       const uint32_t gid = vals[rg.x + (uint32_t)cp[i]];
       gids[i] = (int)gid;
@@ -492,6 +493,7 @@ __device__ __forceinline__ void fwd_tile(const TileInfo &ti, const Ws &w, const 
       const float a = frag_alpha(st[F_O], mm, rcp_fast(dd), amax);
       ca[i] = a;
       const float4 c = make_float4(st[F_R], st[F_G], st[F_B], 0.f);
+      crgb[i][0] = c.x; crgb[i][1] = c.y; crgb[i][2] = c.z;
       const float wgt = a * T;
       C0 = fmaf(wgt, c.x, C0);
       C1 = fmaf(wgt, c.y, C1);
@@ -530,21 +532,24 @@ __device__ __forceinline__ void fwd_tile(const TileInfo &ti, const Ws &w, const 
   if (state) {
     // tile-major state: this tile's values, value by value, each over the
     // tile's 8x8 blocks (this wave's block is block number `wave`)
-    float *sp = state + tile_state_off(V, ti, 3 * K + 6, NT) + wave * 64 + lane;
+    float *sp = state + tile_state_off(V, ti, state_values(K), NT) + wave * 64 + lane;
 #pragma unroll
     for (int i = 0; i < KMAX; ++i) {
       if (i < K) {
         sp[(int64_t)i * NT] = __int_as_float(gids[i]);
         sp[(int64_t)(K + i) * NT] = ca[i];
         sp[(int64_t)(2 * K + i) * NT] = __int_as_float(cp[i]);
+        sp[(int64_t)(3 * K + 3 * i) * NT] = crgb[i][0];
+        sp[(int64_t)(3 * K + 3 * i + 1) * NT] = crgb[i][1];
+        sp[(int64_t)(3 * K + 3 * i + 2) * NT] = crgb[i][2];
       }
     }
-    sp[(int64_t)(3 * K) * NT] = T;
-    sp[(int64_t)(3 * K + 1) * NT] = A;
-    sp[(int64_t)(3 * K + 2) * NT] = S0;
-    sp[(int64_t)(3 * K + 3) * NT] = S1;
-    sp[(int64_t)(3 * K + 4) * NT] = S2;
-    sp[(int64_t)(3 * K + 5) * NT] = P;
+    sp[(int64_t)(6 * K) * NT] = T;
+    sp[(int64_t)(6 * K + 1) * NT] = A;
+    sp[(int64_t)(6 * K + 2) * NT] = S0;
+    sp[(int64_t)(6 * K + 3) * NT] = S1;
+    sp[(int64_t)(6 * K + 4) * NT] = S2;
+    sp[(int64_t)(6 * K + 5) * NT] = P;
   }
 }
 
@@ -660,7 +665,7 @@ __device__ __forceinline__ void bwd_tile(const TileInfo &ti, const Ws &w, const 
   // Per-pixel adjoint factors. Threads walk the pixels in the state's
   // order (8x8 blocks, row-major inside), so consecutive threads read
   // consecutive state words.
-  const float *tstate = state + tile_state_off(V, ti, 3 * K + 6, NT);
+  const float *tstate = state + tile_state_off(V, ti, state_values(K), NT);
   for (int ps = tid; ps < NT; ps += BT) {
     const int lxp = ((ps >> 6) % BX) * 8 + (ps & 7), lyp = ((ps >> 6) / BX) * 8 + ((ps >> 3) & 7);
     const int p = lyp * TW + lxp;
@@ -680,19 +685,19 @@ __device__ __forceinline__ void bwd_tile(const TileInfo &ti, const Ws &w, const 
       for (int i = 0; i < KMAX; ++i) {
         ca[i] = 0.f; cc[i][0] = cc[i][1] = cc[i][2] = 0.f;
         if (i < K) {
-          const int id = __float_as_int(sp[(int64_t)i * NT]);
+          // all loads independent of each other (one round trip); empty
+          // entries (position -1) get alpha and colour 0 from the forward
           ca[i] = sp[(int64_t)(K + i) * NT];
           pos[i] = __float_as_int(sp[(int64_t)(2 * K + i) * NT]);
-          if (id >= 0) {
-            const float *r = recs + (int64_t)id * kRecFloats + R_RGB;
-            cc[i][0] = r[0]; cc[i][1] = r[1]; cc[i][2] = r[2];
-          }
+          cc[i][0] = sp[(int64_t)(3 * K + 3 * i) * NT];
+          cc[i][1] = sp[(int64_t)(3 * K + 3 * i + 1) * NT];
+          cc[i][2] = sp[(int64_t)(3 * K + 3 * i + 2) * NT];
         }
       }
-      const float A = sp[(int64_t)(3 * K + 1) * NT];
-      const float S[3] = {sp[(int64_t)(3 * K + 2) * NT], sp[(int64_t)(3 * K + 3) * NT],
-                          sp[(int64_t)(3 * K + 4) * NT]};
-      const float Pt = sp[(int64_t)(3 * K + 5) * NT];
+      const float A = sp[(int64_t)(6 * K + 1) * NT];
+      const float S[3] = {sp[(int64_t)(6 * K + 2) * NT], sp[(int64_t)(6 * K + 3) * NT],
+                          sp[(int64_t)(6 * K + 4) * NT]};
+      const float Pt = sp[(int64_t)(6 * K + 5) * NT];
       float T = 1.f;
 #pragma unroll
       for (int i = 0; i < KMAX; ++i) {

@@ -325,7 +325,7 @@ def state_planes(frame: Frame, view: int = 0):
     ([values, H, W]); the state itself is tile-major (see htgs.h)."""
     K = int(frame.st.K)
     tw, th = int(frame.st.tile_w), int(frame.st.tile_h)
-    nval = 3 * K + 6
+    nval = 6 * K + 6
 
     def tiles(c):
         return (c.width + tw - 1) // tw, (c.height + th - 1) // th
@@ -342,8 +342,9 @@ def state_planes(frame: Frame, view: int = 0):
     blk = blk.view(ty, tx, nval, by, bx, 8, 8).permute(2, 0, 3, 5, 1, 4, 6)
     blk = blk.reshape(nval, ty * th, tx * tw)[:, :cam.height, :cam.width].contiguous()
     return dict(core_ids=blk[:K].view(torch.int32), core_alpha=blk[K:2 * K],
-                core_pos=blk[2 * K:3 * K].view(torch.int32), T=blk[3 * K], A=blk[3 * K + 1],
-                S=blk[3 * K + 2: 3 * K + 5], P=blk[3 * K + 5])
+                core_pos=blk[2 * K:3 * K].view(torch.int32),
+                core_rgb=blk[3 * K:6 * K].reshape(K, 3, cam.height, cam.width),
+                T=blk[6 * K], A=blk[6 * K + 1], S=blk[6 * K + 2: 6 * K + 5], P=blk[6 * K + 5])
 
 
 # ---------------------------------------------------------------------------

@@ -48,12 +48,12 @@ def test_workspace_and_state_sizes():
     # 16-bit keys: 2 key buffers x 2 B + 2 value buffers x 4 B + 96 B partials
     assert abs((c - b) - 10000 * (4 + 8 + 96)) < 4096
     st8 = scenes.RenderSettings(K=8)
-    assert htgs.state_bytes(cams, st8) == (12 * 8 + 24) * 128 * 128
+    assert htgs.state_bytes(cams, st8) == (24 * 8 + 24) * 128 * 128
     # the state is tile-major, each tile padded to full size at the image edge
     two = [cams[0], cams[0].crop(0, 0, 50, 30)]
     tw, th = st8.tile_w, st8.tile_h
     padded = ((50 + tw - 1) // tw * tw) * ((30 + th - 1) // th * th)
-    assert htgs.state_bytes(two, st8) == (12 * 8 + 24) * (128 * 128 + padded)
+    assert htgs.state_bytes(two, st8) == (24 * 8 + 24) * (128 * 128 + padded)
 
 
 @pytest.mark.parametrize("field,value", [
