@@ -333,17 +333,16 @@ __device__ __forceinline__ void fwd_tile(const TileInfo &ti, const Ws &w, const 
   const float *recs = w.records + (int64_t)ti.v * cfg.n * kRecFloats;
   const uint64_t lanemask_lt = (1ull << lane) - 1ull;
 
-  // Core: depth and list position of up to K fragments, sorted by depth
-  // (ties keep list order). Every fragment is added to the running sums
-  // (alpha, alpha rgb, prod 1 - alpha); once the list is done the core
-  // members' alphas are recomputed from their records (same arithmetic, so
-  // the same values) and taken out of the sums, which leaves exactly the
-  // tail sums.
-  float cz[KMAX];
+  // Core: depth, alpha and list position of up to K fragments, sorted by
+  // depth (ties keep list order). Every fragment is added to the running
+  // sums (alpha, alpha rgb, prod 1 - alpha); once the list is done the core
+  // members are taken back out of them (with the very alphas that went in),
+  // which leaves exactly the tail sums.
+  float cz[KMAX], ca[KMAX];
   int cp[KMAX];
 #pragma unroll
   for (int i = 0; i < KMAX; ++i) {
-    cz[i] = INFINITY; cp[i] = -1;
+    cz[i] = INFINITY; ca[i] = 0.f; cp[i] = -1;
   }
   float zlast = INFINITY;
   float A = 0.f, S0 = 0.f, S1 = 0.f, S2 = 0.f, P = 1.f;
@@ -436,9 +435,11 @@ __device__ __forceinline__ void fwd_tile(const TileInfo &ti, const Ws &w, const 
 #pragma unroll
           for (int i = KMAX - 1; i >= 1; --i) {
             cp[i] = c[i - 1] ? cp[i - 1] : (c[i] ? pos : cp[i]);
+            ca[i] = c[i - 1] ? ca[i - 1] : (c[i] ? alpha : ca[i]);
             cz[i] = __builtin_amdgcn_fmed3f(cz[i - 1], cz[i], z);
           }
           cp[0] = c[0] ? pos : cp[0];
+          ca[0] = c[0] ? alpha : ca[0];
           cz[0] = c[0] ? z : cz[0];
           if (K == KMAX) {
             zlast = cz[KMAX - 1];
@@ -475,35 +476,34 @@ __device__ __forceinline__ void fwd_tile(const TileInfo &ti, const Ws &w, const 
   float Ac = 0.f, Sc0 = 0.f, Sc1 = 0.f, Sc2 = 0.f;
   uint32_t ncore = 0;
   int gids[KMAX];
-  float ca[KMAX], crgb[KMAX][3];
+  float crgb[KMAX][3];
+  // ids, then colours: every entry's loads are independent of the others'
+#pragma unroll
+  for (int i = 0; i < KMAX; ++i)
+    gids[i] = (i < K && cp[i] >= 0) ? (int)vals[rg.x + (uint32_t)cp[i]] : -1;
 #pragma unroll
   for (int i = 0; i < KMAX; ++i) {
-    gids[i] = -1;
-    ca[i] = 0.f;
-    crgb[i][0] = crgb[i][1] = crgb[i][2] = 0.f;
-    if (i < K && cp[i] >= 0) {
-      const uint32_t gid = vals[rg.x + (uint32_t)cp[i]];
-      gids[i] = (int)gid;
-      float rec[kRecFloats];
-      load_record(recs, gid, rec);
-      // the same staging and arithmetic as in the list walk: the same alpha
-      float st[F_FLOATS];
-      stage_fwd(rec, cx2, cy2, st);
-      const float dd = eval_q(st + F_QD, u), mm = eval_mm(st + F_QM, u);
-      const float a = frag_alpha(st[F_O], mm, rcp_fast(dd), amax);
-      ca[i] = a;
-      const float4 c = make_float4(st[F_R], st[F_G], st[F_B], 0.f);
-      crgb[i][0] = c.x; crgb[i][1] = c.y; crgb[i][2] = c.z;
+    float4 c = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (gids[i] >= 0)
+      c = reinterpret_cast<const float4 *>(recs + (int64_t)gids[i] * kRecFloats)[R_RGB / 4];
+    crgb[i][0] = c.x; crgb[i][1] = c.y; crgb[i][2] = c.z;
+  }
+#pragma unroll
+  for (int i = 0; i < KMAX; ++i) {
+    if (gids[i] >= 0) {
+      const float a = ca[i];
       const float wgt = a * T;
-      C0 = fmaf(wgt, c.x, C0);
-      C1 = fmaf(wgt, c.y, C1);
-      C2 = fmaf(wgt, c.z, C2);
+      C0 = fmaf(wgt, crgb[i][0], C0);
+      C1 = fmaf(wgt, crgb[i][1], C1);
+      C2 = fmaf(wgt, crgb[i][2], C2);
       T *= 1.f - a;
       Ac += a;
-      Sc0 = fmaf(a, c.x, Sc0);
-      Sc1 = fmaf(a, c.y, Sc1);
-      Sc2 = fmaf(a, c.z, Sc2);
+      Sc0 = fmaf(a, crgb[i][0], Sc0);
+      Sc1 = fmaf(a, crgb[i][1], Sc1);
+      Sc2 = fmaf(a, crgb[i][2], Sc2);
       ++ncore;
+    } else {
+      ca[i] = 0.f;
     }
   }
   // Tail sums: everything minus the core; exactly empty when no fragment
@@ -946,8 +946,25 @@ __device__ __forceinline__ void bwd_tile(const TileInfo &ti, const Ws &w, const 
   }
 }
 
+// Minimum waves per SIMD asked of the compiler for the forward (HIP's
+// second launch bound): 4 keeps up to 128 VGPRs per lane. The one-wave 8x8
+// forward with a core of up to 8 entries fits in that; wider tiles, with
+// their per-wave splat lists, spill a few words outside the splat loop, and
+// still run faster than at 3 waves. The macros let a build try other bounds.
+#ifndef HTGS_FWD_WAVES_NARROW
+#define HTGS_FWD_WAVES_NARROW 4
+#endif
+#ifndef HTGS_FWD_WAVES_WIDE
+#define HTGS_FWD_WAVES_WIDE 4
+#endif
+template <int KMAX, int TW, int BM>
+constexpr int fwd_simd_waves() {
+  // (a doubled LDS batch holds the forward at 3 workgroups per SIMD anyway)
+  return (KMAX > 8 || BM > 1) ? 1 : (TW == 8 ? HTGS_FWD_WAVES_NARROW : HTGS_FWD_WAVES_WIDE);
+}
+
 template <int KMAX, int TW, int TH, int BM, bool EXACT>
-__global__ void __launch_bounds__(TW *TH) k_raster_fwd(Ws w, ViewSet vs, KCfg cfg,
+__global__ void __launch_bounds__((TW * TH), (fwd_simd_waves<KMAX, TW, BM>())) k_raster_fwd(Ws w, ViewSet vs, KCfg cfg,
                                                        float *__restrict__ state,
                                                        const uint32_t *__restrict__ vals) {
 #define HTGS_FWD_BODY(T) fwd_tile<KMAX, TW, TH, BM, EXACT>(T, w, vs, cfg, state, vals)
