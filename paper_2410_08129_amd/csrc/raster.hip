@@ -333,11 +333,15 @@ __device__ __forceinline__ void fwd_tile(const TileInfo &ti, const Ws &w, const 
   const float *recs = w.records + (int64_t)ti.v * cfg.n * kRecFloats;
   const uint64_t lanemask_lt = (1ull << lane) - 1ull;
 
-  // Core: depth, alpha and list position of up to K fragments, sorted by
-  // depth (ties keep list order). Every fragment is added to the running
-  // sums (alpha, alpha rgb, prod 1 - alpha); once the list is done the core
-  // members are taken back out of them (with the very alphas that went in),
-  // which leaves exactly the tail sums.
+  // Core: depth, list position and (CARRY) alpha of up to K fragments,
+  // sorted by depth (ties keep list order). Every fragment is added to the
+  // running sums (alpha, alpha rgb, prod 1 - alpha); once the list is done
+  // the core members are taken back out of them with the same alphas, which
+  // leaves exactly the tail sums. Cores of up to 8 entries carry the alphas
+  // through the insertion; larger ones recompute them from the records at
+  // the end (same staging and arithmetic, so the same values), which keeps
+  // 16 registers free for occupancy.
+  constexpr bool CARRY = KMAX <= 8;
   float cz[KMAX], ca[KMAX];
   int cp[KMAX];
 #pragma unroll
@@ -435,11 +439,11 @@ __device__ __forceinline__ void fwd_tile(const TileInfo &ti, const Ws &w, const 
 #pragma unroll
           for (int i = KMAX - 1; i >= 1; --i) {
             cp[i] = c[i - 1] ? cp[i - 1] : (c[i] ? pos : cp[i]);
-            ca[i] = c[i - 1] ? ca[i - 1] : (c[i] ? alpha : ca[i]);
+            if constexpr (CARRY) ca[i] = c[i - 1] ? ca[i - 1] : (c[i] ? alpha : ca[i]);
             cz[i] = __builtin_amdgcn_fmed3f(cz[i - 1], cz[i], z);
           }
           cp[0] = c[0] ? pos : cp[0];
-          ca[0] = c[0] ? alpha : ca[0];
+          if constexpr (CARRY) ca[0] = c[0] ? alpha : ca[0];
           cz[0] = c[0] ? z : cz[0];
           if (K == KMAX) {
             zlast = cz[KMAX - 1];
@@ -475,35 +479,70 @@ __device__ __forceinline__ void fwd_tile(const TileInfo &ti, const Ws &w, const 
   float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
   float Ac = 0.f, Sc0 = 0.f, Sc1 = 0.f, Sc2 = 0.f;
   uint32_t ncore = 0;
-  int gids[KMAX];
-  float crgb[KMAX][3];
-  // ids, then colours: every entry's loads are independent of the others'
-#pragma unroll
-  for (int i = 0; i < KMAX; ++i)
-    gids[i] = (i < K && cp[i] >= 0) ? (int)vals[rg.x + (uint32_t)cp[i]] : -1;
-#pragma unroll
-  for (int i = 0; i < KMAX; ++i) {
-    float4 c = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (gids[i] >= 0)
-      c = reinterpret_cast<const float4 *>(recs + (int64_t)gids[i] * kRecFloats)[R_RGB / 4];
-    crgb[i][0] = c.x; crgb[i][1] = c.y; crgb[i][2] = c.z;
-  }
-#pragma unroll
-  for (int i = 0; i < KMAX; ++i) {
-    if (gids[i] >= 0) {
-      const float a = ca[i];
+  // tile-major state: this tile's values, value by value, each over the
+  // tile's 8x8 blocks (this wave's block is block number `wave`)
+  float *sp = state ? state + tile_state_off(V, ti, state_values(K), NT) + wave * 64 + lane
+                    : nullptr;
+  // One core member: composite, take it out of the sums, store it.
+  auto core_entry = [&](int i, int gid, float a, float r, float g, float b) {
+    if (gid >= 0) {
       const float wgt = a * T;
-      C0 = fmaf(wgt, crgb[i][0], C0);
-      C1 = fmaf(wgt, crgb[i][1], C1);
-      C2 = fmaf(wgt, crgb[i][2], C2);
+      C0 = fmaf(wgt, r, C0);
+      C1 = fmaf(wgt, g, C1);
+      C2 = fmaf(wgt, b, C2);
       T *= 1.f - a;
       Ac += a;
-      Sc0 = fmaf(a, crgb[i][0], Sc0);
-      Sc1 = fmaf(a, crgb[i][1], Sc1);
-      Sc2 = fmaf(a, crgb[i][2], Sc2);
+      Sc0 = fmaf(a, r, Sc0);
+      Sc1 = fmaf(a, g, Sc1);
+      Sc2 = fmaf(a, b, Sc2);
       ++ncore;
-    } else {
-      ca[i] = 0.f;
+    }
+    if (sp) {
+      sp[(int64_t)i * NT] = __int_as_float(gid);
+      sp[(int64_t)(K + i) * NT] = a;
+      sp[(int64_t)(2 * K + i) * NT] = __int_as_float(cp[i]);
+      sp[(int64_t)(3 * K + 3 * i) * NT] = r;
+      sp[(int64_t)(3 * K + 3 * i + 1) * NT] = g;
+      sp[(int64_t)(3 * K + 3 * i + 2) * NT] = b;
+    }
+  };
+  if constexpr (CARRY) {
+    // ids, then colours: every entry's loads are independent of the others'
+    int gids[KMAX];
+    float crgb[KMAX][3];
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i)
+      gids[i] = (i < K && cp[i] >= 0) ? (int)vals[rg.x + (uint32_t)cp[i]] : -1;
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i) {
+      float4 c = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (gids[i] >= 0)
+        c = reinterpret_cast<const float4 *>(recs + (int64_t)gids[i] * kRecFloats)[R_RGB / 4];
+      crgb[i][0] = c.x; crgb[i][1] = c.y; crgb[i][2] = c.z;
+    }
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i)
+      if (i < K)
+        core_entry(i, gids[i], gids[i] >= 0 ? ca[i] : 0.f, crgb[i][0], crgb[i][1], crgb[i][2]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i) {
+      if (i < K) {
+        int gid = -1;
+        float a = 0.f, r = 0.f, g = 0.f, b = 0.f;
+        if (cp[i] >= 0) {
+          gid = (int)vals[rg.x + (uint32_t)cp[i]];
+          float rec[kRecFloats];
+          load_record(recs, gid, rec);
+          // the same staging and arithmetic as in the list walk: the same alpha
+          float st[F_FLOATS];
+          stage_fwd(rec, cx2, cy2, st);
+          const float dd = eval_q(st + F_QD, u), mm = eval_mm(st + F_QM, u);
+          a = frag_alpha(st[F_O], mm, rcp_fast(dd), amax);
+          r = st[F_R]; g = st[F_G]; b = st[F_B];
+        }
+        core_entry(i, gid, a, r, g, b);
+      }
     }
   }
   // Tail sums: everything minus the core; exactly empty when no fragment
@@ -529,21 +568,7 @@ __device__ __forceinline__ void fwd_tile(const TileInfo &ti, const Ws &w, const 
   V.out_rgb[pix] = fmaf(T, X0, C0);
   V.out_rgb[npix + pix] = fmaf(T, X1, C1);
   V.out_rgb[2 * npix + pix] = fmaf(T, X2, C2);
-  if (state) {
-    // tile-major state: this tile's values, value by value, each over the
-    // tile's 8x8 blocks (this wave's block is block number `wave`)
-    float *sp = state + tile_state_off(V, ti, state_values(K), NT) + wave * 64 + lane;
-#pragma unroll
-    for (int i = 0; i < KMAX; ++i) {
-      if (i < K) {
-        sp[(int64_t)i * NT] = __int_as_float(gids[i]);
-        sp[(int64_t)(K + i) * NT] = ca[i];
-        sp[(int64_t)(2 * K + i) * NT] = __int_as_float(cp[i]);
-        sp[(int64_t)(3 * K + 3 * i) * NT] = crgb[i][0];
-        sp[(int64_t)(3 * K + 3 * i + 1) * NT] = crgb[i][1];
-        sp[(int64_t)(3 * K + 3 * i + 2) * NT] = crgb[i][2];
-      }
-    }
+  if (sp) {
     sp[(int64_t)(6 * K) * NT] = T;
     sp[(int64_t)(6 * K + 1) * NT] = A;
     sp[(int64_t)(6 * K + 2) * NT] = S0;
