@@ -202,6 +202,31 @@ def test_gradients_match_oracle_on_subcrop(seed, tile):
     sub, cam, st, target = _subcrop(seed)
     st.tile_w, st.tile_h = _shape(tile)
     log(f"gradients: 256 Gaussians, 32x32, seed {seed}, tile {tile}")
+    _check_grads(sub, cam, st, target)
+
+
+def test_gradients_dense_two_block_tiles():
+    # Two 16x8 tiles with 1,200-1,700 instances each (a tile list of 20-27
+    # 64-instance chunks shared by the pairs of backward waves). 300
+    # Gaussians, each repeated 8 times; copy r is moved by
+    # r (0.003, -0.002, 0.004), which keeps the copies of one Gaussian 0.004
+    # apart in depth (random jitter made near-equal depths, whose core order
+    # float32 cannot decide like float64).
+    sub, cam, st, target = _subcrop(23, n_sel=300, size=16)
+    sub = sub.subset(np.tile(np.arange(300), 8))
+    r = np.repeat(np.arange(8), 300)[:, None].astype(np.float32)
+    sub.means = (sub.means + r * np.array([0.003, -0.002, 0.004], np.float32)).astype(np.float32)
+    st.tile_w, st.tile_h = 16, 8
+    params = to_dev(sub)
+    frame = htgs.forward(params, sub.sh_degree, [cam], st)
+    keys, vals, rects, flags = htgs.export_bins(params, sub.sh_degree, [cam], st, frame.ws)
+    per_tile = np.bincount(np.asarray(keys, dtype=np.int64))
+    log(f"gradients: 2400 Gaussians, 16x16, tiles 16x8, instances per tile {per_tile.tolist()}")
+    assert per_tile.min() > 1200
+    _check_grads(sub, cam, st, target)
+
+
+def _check_grads(sub, cam, st, target):
     ref_img = oracle.render.render_scene(sub, cam, st, cull=False).numpy()
     G = np.sign(ref_img - target) / (3 * cam.width * cam.height)
     ref_img, ref = _oracle_grads(sub, cam, st, G)
