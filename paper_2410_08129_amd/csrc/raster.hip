@@ -395,8 +395,6 @@ __device__ __forceinline__ void fwd_tile(const TileInfo &ti, const Ws &w, const 
       __builtin_amdgcn_wave_barrier();
     }
     if (!inside) continue;
-    // One staged splat per step; the ray-test part of the next one is read
-    // from LDS while this one is evaluated (two register buffers).
     auto stage_index = [&](int q) -> int {
       if constexpr (NW > 1) return s_list[wave][q];
       else return q;
@@ -455,17 +453,15 @@ __device__ __forceinline__ void fwd_tile(const TileInfo &ti, const Ws &w, const 
         }
       }
     };
-    float ea[4 * F_TEST4], eb[4 * F_TEST4];
-    if (nlist > 0) fetch(stage_index(0), ea);
-    for (int q = 0; q < nlist; q += 2) {
+    // One staged splat per step, its ray-test values read from LDS just
+    // before use: without a second register buffer for the next splat the
+    // 8x8 forward stays under 96 VGPRs (5 waves per SIMD), and the extra
+    // wave hides the LDS latency better than the buffer did.
+    for (int q = 0; q < nlist; ++q) {
       const int ja = stage_index(q);
-      const bool has_b = q + 1 < nlist;
-      const int jb = has_b ? stage_index(q + 1) : 0;
-      if (has_b) fetch(jb, eb);
+      float ea[4 * F_TEST4];
+      fetch(ja, ea);
       step(ja, ea);
-      if (!has_b) break;
-      if (q + 2 < nlist) fetch(stage_index(q + 2), ea);
-      step(jb, eb);
     }
   }
   __syncthreads();
@@ -972,10 +968,9 @@ __device__ __forceinline__ void bwd_tile(const TileInfo &ti, const Ws &w, const 
 }
 
 // Minimum waves per SIMD asked of the compiler for the forward (HIP's
-// second launch bound): 4 keeps up to 128 VGPRs per lane. The one-wave 8x8
-// forward with a core of up to 8 entries fits in that; wider tiles, with
-// their per-wave splat lists, spill a few words outside the splat loop, and
-// still run faster than at 3 waves. The macros let a build try other bounds.
+// second launch bound): 4 keeps up to 128 VGPRs per lane, which the
+// forward with a core of up to 8 entries fits in without spilling (8x8
+// tiles stay under 96, 5 waves). The macros let a build try other bounds.
 #ifndef HTGS_FWD_WAVES_NARROW
 #define HTGS_FWD_WAVES_NARROW 4
 #endif
