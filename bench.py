@@ -195,11 +195,12 @@ def run_single(args):
     # this workload, if it was taken on the current kernel sources
     kmax = next(k for k in (1, 2, 4, 8, 16, 32) if k >= max(st.K, 1))
     exact = "true" if st.K == kmax else "false"
+    persist = "true" if st.persistent else "false"
     if dom == "raster_bwd":
-        key = f"k_raster_bwd<{kmax}, {st.tile_w}, {st.tile_h}, {exact}>"
+        key = f"k_raster_bwd<{kmax}, {st.tile_w}, {st.tile_h}, {exact}, {persist}>"
     else:
         bm = 2 if st.lds_batch == 2 * st.tile_w * st.tile_h else 1
-        key = f"k_raster_fwd<{kmax}, {st.tile_w}, {st.tile_h}, {bm}, {exact}>"
+        key = f"k_raster_fwd<{kmax}, {st.tile_w}, {st.tile_h}, {bm}, {exact}, {persist}>"
     tr = pmc.traffic_for(os.path.join(ROOT, "profiles", f"hbm_traffic_{args.workload}.json"), key)
     roofline = dict(kernel=dom, bound="alu", achieved=round(ach, 3),
                     peak=round(FP32_PEAK_TFLOPS, 1), unit="TFLOP/s",

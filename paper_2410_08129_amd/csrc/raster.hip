@@ -272,10 +272,13 @@ __device__ __forceinline__ void tile_of_slot(const ViewSet &vs, const KCfg &cfg,
 
 // Runs BODY(ti) for the workgroup's tile, or, in persistent mode, for tiles
 // taken from the atomic queue w.status[QSLOT] until it is exhausted (every
-// workgroup leaves when the queue passes the tile count).
-#define HTGS_FOR_TILES(QSLOT, BODY)                                              \
+// workgroup leaves when the queue passes the tile count). PERSIST is a
+// compile-time choice: the queue loop and its LDS word would otherwise cost
+// the one-tile kernels registers and, for 8x8 backward tiles, a workgroup
+// per CU (16 KiB of LDS plus that word).
+#define HTGS_FOR_TILES(PERSIST, QSLOT, BODY)                                     \
   do {                                                                           \
-    if (!cfg.persistent) {                                                       \
+    if constexpr (!(PERSIST)) {                                                  \
       TileInfo ti_;                                                              \
       if (tile_info(vs, cfg, w, ti_)) BODY(ti_);                                 \
     } else {                                                                     \
@@ -983,21 +986,21 @@ constexpr int fwd_simd_waves() {
   return (KMAX > 8 || BM > 1) ? 1 : (TW == 8 ? HTGS_FWD_WAVES_NARROW : HTGS_FWD_WAVES_WIDE);
 }
 
-template <int KMAX, int TW, int TH, int BM, bool EXACT>
-__global__ void __launch_bounds__((TW * TH), (fwd_simd_waves<KMAX, TW, BM>())) k_raster_fwd(Ws w, ViewSet vs, KCfg cfg,
-                                                       float *__restrict__ state,
-                                                       const uint32_t *__restrict__ vals) {
+template <int KMAX, int TW, int TH, int BM, bool EXACT, bool PERSIST>
+__global__ void __launch_bounds__((TW * TH), (fwd_simd_waves<KMAX, TW, BM>()))
+    k_raster_fwd(Ws w, ViewSet vs, KCfg cfg, float *__restrict__ state,
+                 const uint32_t *__restrict__ vals) {
 #define HTGS_FWD_BODY(T) fwd_tile<KMAX, TW, TH, BM, EXACT>(T, w, vs, cfg, state, vals)
-  HTGS_FOR_TILES(kQueueFwd, HTGS_FWD_BODY);
+  HTGS_FOR_TILES(PERSIST, kQueueFwd, HTGS_FWD_BODY);
 #undef HTGS_FWD_BODY
 }
 
-template <int KMAX, int TW, int TH, bool EXACT>
+template <int KMAX, int TW, int TH, bool EXACT, bool PERSIST>
 __global__ void __launch_bounds__((64 * bwd_waves<TW, TH>()), (bwd_simd_waves<KMAX, TW>()))
     k_raster_bwd(Ws w, ViewSet vs, KCfg cfg, const float *__restrict__ state,
                  const uint32_t *__restrict__ vals) {
 #define HTGS_BWD_BODY(T) bwd_tile<KMAX, TW, TH, EXACT>(T, w, vs, cfg, state, vals)
-  HTGS_FOR_TILES(kQueueBwd, HTGS_BWD_BODY);
+  HTGS_FOR_TILES(PERSIST, kQueueBwd, HTGS_BWD_BODY);
 #undef HTGS_BWD_BODY
 }
 
@@ -1020,32 +1023,43 @@ static int resident_blocks(const void *kernel, int threads, int tiles) {
   const int n = per_cu * cus;
   return n < tiles ? n : (tiles > 0 ? tiles : 1);
 }
+template <int KMAX, int TW, int TH, int BM, bool EXACT>
+static hipError_t fwd_launch_bm(const Ws &w, const ViewSet &vs, const KCfg &cfg, float *state,
+                                const uint32_t *vals, hipStream_t s) {
+  if (cfg.persistent) {
+    auto *kern = k_raster_fwd<KMAX, TW, TH, BM, EXACT, true>;
+    const int blocks = resident_blocks((const void *)kern, TW * TH, vs.total_tiles);
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(TW * TH), 0, s, w, vs, cfg, state, vals);
+  } else {
+    auto *kern = k_raster_fwd<KMAX, TW, TH, BM, EXACT, false>;
+    const int blocks = 8 * ((vs.total_tiles + 7) / 8);
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(TW * TH), 0, s, w, vs, cfg, state, vals);
+  }
+  return hipGetLastError();
+}
+
 template <int KMAX, int TW, int TH, bool EXACT>
 static hipError_t fwd_launch(const Ws &w, const ViewSet &vs, const KCfg &cfg, float *state,
                              const uint32_t *vals, hipStream_t s) {
-  int blocks = 8 * ((vs.total_tiles + 7) / 8);
   if constexpr (TW == 8) {
-    if (cfg.batch_mult == 2) {
-      auto *kern = k_raster_fwd<KMAX, TW, TH, 2, EXACT>;
-      if (cfg.persistent) blocks = resident_blocks((const void *)kern, TW * TH, vs.total_tiles);
-      hipLaunchKernelGGL(kern, dim3(blocks), dim3(TW * TH), 0, s, w, vs, cfg, state, vals);
-      return hipGetLastError();
-    }
+    if (cfg.batch_mult == 2) return fwd_launch_bm<KMAX, TW, TH, 2, EXACT>(w, vs, cfg, state, vals, s);
   }
-  auto *kern = k_raster_fwd<KMAX, TW, TH, 1, EXACT>;
-  if (cfg.persistent) blocks = resident_blocks((const void *)kern, TW * TH, vs.total_tiles);
-  hipLaunchKernelGGL(kern, dim3(blocks), dim3(TW * TH), 0, s, w, vs, cfg, state, vals);
-  return hipGetLastError();
+  return fwd_launch_bm<KMAX, TW, TH, 1, EXACT>(w, vs, cfg, state, vals, s);
 }
 
 template <int KMAX, int TW, int TH, bool EXACT>
 static hipError_t bwd_launch(const Ws &w, const ViewSet &vs, const KCfg &cfg, const float *state,
                              const uint32_t *vals, hipStream_t s) {
-  int blocks = 8 * ((vs.total_tiles + 7) / 8);
-  auto *kern = k_raster_bwd<KMAX, TW, TH, EXACT>;
   constexpr int BT = 64 * bwd_waves<TW, TH>();
-  if (cfg.persistent) blocks = resident_blocks((const void *)kern, BT, vs.total_tiles);
-  hipLaunchKernelGGL(kern, dim3(blocks), dim3(BT), 0, s, w, vs, cfg, state, vals);
+  if (cfg.persistent) {
+    auto *kern = k_raster_bwd<KMAX, TW, TH, EXACT, true>;
+    const int blocks = resident_blocks((const void *)kern, BT, vs.total_tiles);
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(BT), 0, s, w, vs, cfg, state, vals);
+  } else {
+    auto *kern = k_raster_bwd<KMAX, TW, TH, EXACT, false>;
+    const int blocks = 8 * ((vs.total_tiles + 7) / 8);
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(BT), 0, s, w, vs, cfg, state, vals);
+  }
   return hipGetLastError();
 }
 
