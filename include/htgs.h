@@ -92,7 +92,11 @@ typedef struct htgs_camera {
  *  alpha_max  alpha clamp, alpha = min(alpha_max, o exp(-rho^2/2)), in (0,1)
  *  bg         background colour c_bg of Eq. pixel_color_computation
  *  tile_w/h   8x8, 16x8, 16x16 or 32x8 pixels (one 64-lane wave per 8x8
- *             block); K <= 16 for the 256-pixel shapes
+ *             block); K <= 16 for the 256-pixel shapes. There is no
+ *             "0 = choose for me" value: the schedule (tile shape, LDS
+ *             batch, order, culling, queue) is picked by timing candidates
+ *             on the workload, which the Python package's autotuner does
+ *             above this boundary, and passed in here
  *  lds_batch  records staged per batch in the forward: 0 or the tile's pixel
  *             count (one per thread), or, with 8x8 tiles, twice that
  *  flags      HTGS_FLAG_COST_ORDER: rasterize tiles in descending order of
@@ -179,10 +183,17 @@ int htgs_render_forward(const htgs_gaussians *g, const htgs_camera *cam,
                         const htgs_config *cfg, void *ws, int64_t ws_bytes, void *state,
                         float *out_rgb, void *stream);
 
-/* Backward of the last htgs_render_forward() on this workspace and state:
- * grad_rgb is dL/dC [3,H,W]; gradients w.r.t. every parameter are ADDED to
- * `grads`. Deterministic (no floating-point atomics). Same g, cam, cfg as the
- * forward. */
+/* Backward of the last htgs_render_forward() on this workspace and state
+ * (Sec. 3.3, last paragraph: the core's fragments are re-evaluated from the
+ * stored per-pixel core and differentiated back to front; every tail
+ * fragment's derivative uses per-pixel factors precomputed from the stored
+ * tail sums). grad_rgb is dL/dC [3,H,W]; gradients w.r.t. every parameter
+ * are ADDED to `grads` (or written, with HTGS_FLAG_GRAD_OVERWRITE).
+ * Deterministic (no floating-point atomics). The backward evaluates each
+ * pixel's fragments with the forward's own float32 forms, so it
+ * differentiates exactly the fragments the forward blended. Same g, cam, cfg
+ * as the forward. After a forward whose status reports a flag, the
+ * gradients are zero (added: unchanged). */
 int htgs_render_backward(const htgs_gaussians *g, const htgs_camera *cam,
                          const htgs_config *cfg, void *ws, int64_t ws_bytes,
                          const void *state, const float *grad_rgb, const htgs_grads *grads,
@@ -230,6 +241,21 @@ int htgs_debug_export_bins(const htgs_gaussians *g, const htgs_camera *cams, int
                            const htgs_config *cfg, const void *ws, int64_t ws_bytes,
                            uint32_t *keys_out, uint32_t *values_out, int64_t max_out,
                            int32_t *rects_out, int64_t *instances_out, void *stream);
+
+/* Debugging and testing.
+ * htgs_debug_set_spin_limit: look-back rounds (each one memory round trip
+ *   and a short sleep) after which a workgroup waiting for its
+ *   predecessors' prefix gives up, default 4,194,304; a negative value makes
+ *   every wait give up at once. A give-up sets HTGS_STATUS_SPIN_TIMEOUT:
+ *   every later stage of the call then treats the lists as empty (the image
+ *   is the background, gradients are zero) and no kernel reads or writes
+ *   out of bounds. Host-side setting for later calls; not thread-safe.
+ * htgs_debug_fragment_counts: fragments (pixel-Gaussian pairs with
+ *   rho^2 <= rho_c) counted by the last forward raster on ws and by the
+ *   backward rasters since that forward. SYNCHRONISES the stream. */
+int htgs_debug_set_spin_limit(int32_t limit);
+int htgs_debug_fragment_counts(const void *ws, int64_t ws_bytes, int64_t *forward_out,
+                               int64_t *backward_out, void *stream);
 
 /* Static description of an error code. */
 const char *htgs_strerror(int code);

@@ -14,7 +14,7 @@ hipError_t launch_preprocess(const GaussPtrs &gp, const KCfg &cfg, const ViewSet
 hipError_t launch_preprocess_bwd(const GaussPtrs &gp, const GradPtrs &gr, const KCfg &cfg,
                                  const ViewSet &vs, const Ws &w, hipStream_t s);
 hipError_t launch_sort_passes(const Ws &w, hipStream_t s);
-hipError_t launch_ranges(const Ws &w, hipStream_t s);
+hipError_t launch_ranges(const Ws &w, int total_tiles, hipStream_t s);
 hipError_t launch_tile_order(const Ws &w, int total_tiles, hipStream_t s);
 hipError_t launch_raster_fwd(const Ws &w, const ViewSet &vs, const KCfg &cfg, float *state,
                              const uint32_t *vals, hipStream_t s);
@@ -24,6 +24,9 @@ hipError_t launch_raster_bwd(const Ws &w, const ViewSet &vs, const KCfg &cfg, co
 namespace {
 
 constexpr int64_t kAlign = 256;
+// Look-back rounds before a cross-workgroup wait gives up (a debug entry
+// point lowers it; negative: give up at once).
+int32_t g_spin_limit = kSpinLimit;
 constexpr int64_t kMaxCapacity = (1ll << 30) - 1;
 
 int64_t align_up(int64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -51,7 +54,7 @@ Layout make_layout(int64_t n, int n_views, int64_t total_tiles, int64_t capacity
   const int64_t kb = L.key16 ? 2 : 4;
   int64_t o = 0;
   L.status = o; o = align_up(o + 64);
-  L.total = o; o = align_up(o + 16);
+  L.total = o; o = align_up(o + 32);   // instances, forward and backward fragments
   L.pp_look = o; o = align_up(o + 8 * ((n + kPreThreads - 1) / kPreThreads));
   L.hist = o; o = align_up(o + 4 * 256 * 4);
   L.sort_look = o; o = align_up(o + (int64_t)L.passes * L.max_chunks * 256 * 4);
@@ -90,6 +93,7 @@ Ws make_ws(void *base, const Layout &L) {
   w.status = reinterpret_cast<uint32_t *>(b + L.status);
   w.total = reinterpret_cast<unsigned long long *>(b + L.total);
   w.frags = w.total + 1;
+  w.frags_bwd = w.total + 2;
   w.pp_look = reinterpret_cast<unsigned long long *>(b + L.pp_look);
   w.hist = reinterpret_cast<uint32_t *>(b + L.hist);
   w.sort_look = reinterpret_cast<uint32_t *>(b + L.sort_look);
@@ -111,6 +115,7 @@ Ws make_ws(void *base, const Layout &L) {
   w.passes = L.passes;
   w.key16 = L.key16;
   w.final_buf = L.passes & 1;
+  w.spin_limit = g_spin_limit;
   return w;
 }
 
@@ -308,7 +313,7 @@ int run_front(const htgs_gaussians *g, const ViewSet &vs, const htgs_config *cfg
   }
   if (sort && L.capacity > 0) {
     StageTimer t(HTGS_STAGE_RANGES, s);
-    HIP_TRY(launch_ranges(w, s));
+    HIP_TRY(launch_ranges(w, vs.total_tiles, s));
     if (cfg->flags & HTGS_FLAG_COST_ORDER) HIP_TRY(launch_tile_order(w, vs.total_tiles, s));
   }
   return HTGS_OK;
@@ -483,9 +488,28 @@ int htgs_read_status(const void *ws, int64_t ws_bytes, uint32_t *flags_out,
   HIP_TRY(hipMemcpyAsync(counts, static_cast<const char *>(ws) + L.total, 16,
                          hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  *flags_out = flags;
+  *flags_out = flags & kStatusPublic;
   if (instances_out) *instances_out = (int64_t)counts[0];
   if (fragments_out) *fragments_out = (int64_t)counts[1];
+  return HTGS_OK;
+}
+
+int htgs_debug_set_spin_limit(int32_t limit) {
+  g_spin_limit = limit;
+  return HTGS_OK;
+}
+
+int htgs_debug_fragment_counts(const void *ws, int64_t ws_bytes, int64_t *forward_out,
+                               int64_t *backward_out, void *stream) {
+  if (!ws || !forward_out || !backward_out || ws_bytes < 512) return HTGS_E_INVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  unsigned long long counts[3] = {0, 0, 0};
+  const Layout L = make_layout(0, 1, 1, 0);
+  HIP_TRY(hipMemcpyAsync(counts, static_cast<const char *>(ws) + L.total, 24,
+                         hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *forward_out = (int64_t)counts[1];
+  *backward_out = (int64_t)counts[2];
   return HTGS_OK;
 }
 

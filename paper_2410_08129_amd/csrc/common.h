@@ -100,6 +100,7 @@ struct Ws {
   uint32_t *status;            // [0] flags, [1] preprocess ticket, [2..5] sort tickets
   unsigned long long *total;   // instance count (64-bit)
   unsigned long long *frags;   // fragments counted by the forward raster
+  unsigned long long *frags_bwd;  // fragments counted by the backward raster
   unsigned long long *pp_look; // preprocess look-back words, one per block
   uint32_t *hist;              // [4][256] digit histograms
   uint32_t *sort_look;         // [passes][max_chunks][256]
@@ -117,20 +118,37 @@ struct Ws {
   int64_t max_chunks;
   int32_t key_bits, passes, key16;
   int32_t final_buf;           // which of keys/vals holds the sorted lists
+  int32_t spin_limit;          // look-back rounds before a wait gives up (< 0: at once)
 };
 
 // Look-back words: 2 flag bits on top of the value.
 constexpr uint32_t kFlagA32 = 1u << 30, kFlagP32 = 2u << 30, kMask32 = (1u << 30) - 1u;
 constexpr unsigned long long kFlagA64 = 1ull << 62, kFlagP64 = 2ull << 62,
                              kMask64 = (1ull << 62) - 1ull;
-constexpr int kSpinLimit = 1 << 22;
+constexpr int kSpinLimit = 1 << 22;   // default look-back rounds before giving up
 // Forward state values per pixel: K ids, K alphas, K list positions, K rgb
 // triples, T, sum alpha, sum alpha rgb (3), prod (1 - alpha).
 __host__ __device__ constexpr int state_values(int K) { return 6 * K + 6; }
 
 constexpr int kLookWindow = 4;   // look-back words read per round trip
 
-enum StatusBits : uint32_t { ST_OVERFLOW = 1u, ST_SPIN = 2u };
+// Status word. ST_SPIN: some cross-workgroup wait gave up, so some prefix
+// is wrong; the stage bit says where (preprocess, or sort pass p), so that
+// a later launch can tell a give-up of an earlier launch (whose outputs it
+// must not trust) from one of its own concurrent workgroups.
+enum StatusBits : uint32_t {
+  ST_OVERFLOW = 1u, ST_SPIN = 2u, ST_SPIN_PRE = 1u << 8, ST_SPIN_SORT0 = 1u << 9
+};
+constexpr uint32_t kStatusPublic = ST_OVERFLOW | ST_SPIN;
+// give-up bits of the stages before sort pass p
+__host__ __device__ constexpr uint32_t spin_bits_before_sort(int p) {
+  return ST_SPIN_PRE | (((1u << p) - 1u) << 9);
+}
+// outputs of the front end are unusable: overflow or any give-up
+__device__ __forceinline__ bool front_failed(const Ws &w) {
+  return (__hip_atomic_load(&w.status[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
+          (ST_OVERFLOW | ST_SPIN)) != 0u;
+}
 // status words of the persistent raster queues (16-byte aligned, cleared
 // before each raster launch)
 constexpr int kQueueFwd = 8, kQueueBwd = 12;

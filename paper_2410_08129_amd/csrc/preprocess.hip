@@ -549,6 +549,14 @@ __global__ void __launch_bounds__(kPreThreads) k_preprocess(GaussPtrs gp, KCfg c
       int64_t j = blk - 1;
       int spins = 0;
       while (true) {
+        // A wait that gives up (w.spin_limit rounds without progress; a
+        // negative limit gives up at once) flags the status word and goes
+        // on with a prefix that is too small: slots stay below the true
+        // ones, and every later stage sees the flag.
+        if (spins > w.spin_limit) {
+          atomicOr(&w.status[0], (uint32_t)(ST_SPIN | ST_SPIN_PRE));
+          break;
+        }
         // kLookWindow predecessors per round trip; stop at the first
         // inclusive (P) or unpublished word.
         unsigned long long sv[kLookWindow];
@@ -568,10 +576,7 @@ __global__ void __launch_bounds__(kPreThreads) k_preprocess(GaussPtrs gp, KCfg c
         if (done) break;
         j -= used;
         if (used == 0) {
-          if (++spins > kSpinLimit) {
-            atomicOr(&w.status[0], (uint32_t)ST_SPIN);
-            break;
-          }
+          ++spins;
           __builtin_amdgcn_s_sleep(1);
         }
       }
@@ -788,9 +793,9 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(GaussPtrs gp, GradPtrs g
   const bool live = g < cfg.n;
   const int nviews = MV ? vs.n : 1;
   const unsigned long long I = *w.total;
-  // An overflowed forward (reported by the status word) leaves no usable
-  // partials: zero gradient.
-  const bool ok = I <= (unsigned long long)w.capacity;
+  // An overflowed forward, or one whose look-back gave up (both reported
+  // by the status word), leaves no usable partials: zero gradient.
+  const bool ok = I <= (unsigned long long)w.capacity && !front_failed(w);
   uint32_t total = 0;
   if (live && ok)
     for (int v = 0; v < nviews; ++v)
@@ -817,8 +822,8 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(GaussPtrs gp, GradPtrs g
     const uint64_t group_end = (g0 + 64 < cfg.n) ? (uint64_t)w.tslots[g0 + 64].x : (uint64_t)I;
     for (int v = 0; v < nviews; ++v) {
       const uint64_t lo = w.tslots[(int64_t)v * cfg.n + g0].x;
-      const uint64_t hi = (v + 1 < nviews) ? (uint64_t)w.tslots[(int64_t)(v + 1) * cfg.n + g0].x
-                                           : group_end;
+      const uint64_t hi = min((v + 1 < nviews) ? (uint64_t)w.tslots[(int64_t)(v + 1) * cfg.n + g0].x
+                                               : group_end, (uint64_t)I);
       if (lo >= hi) continue;  // no instance of this group in view v
 #pragma unroll
       for (int k = 0; k < 22; ++k) s_acc[wave][k][lane] = 0.f;

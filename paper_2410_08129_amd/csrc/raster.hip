@@ -200,6 +200,14 @@ __device__ __forceinline__ float eval_q(const float *c, const PixQ &u) {
   return fmaf(u.yy, c[5], fmaf(u.xy, c[4], fmaf(u.xx, c[3], fmaf(u.y, c[2], fmaf(u.x, c[1], c[0])))));
 }
 
+// |d|^2 from its staged quadratic, the Y terms first (a pixel row shares
+// them) and then the X terms: c0 + Y c2 + Y^2 c5 + X^2 c3 + X (c1 + Y c4).
+// The backward evaluates it in the same order, row part once per row, so
+// both passes get the same bits.
+__device__ __forceinline__ float eval_dd(const float *c, const PixQ &u) {
+  return fmaf(u.x, fmaf(u.y, c[4], c[1]), fmaf(u.xx, c[3], fmaf(u.yy, c[5], fmaf(u.y, c[2], c[0]))));
+}
+
 // |m|^2 = s1^2 + s2^2 + |r|^2 (see FwdStage).
 __device__ __forceinline__ float eval_mm(const float *c, const PixQ &u) {
   const float s1 = fmaf(c[1], u.x, fmaf(c[2], u.y, c[3]));
@@ -325,7 +333,9 @@ __device__ __forceinline__ void fwd_tile(const TileInfo &ti, const Ws &w, const 
   const int px0 = ti.tx * TW, py0 = ti.ty * TH;
   const int px = px0 + lx, py = py0 + ly;
   const bool inside = (px < V.width) && (py < V.height);
-  const uint2 rg = w.ranges[ti.t];
+  // a failed front end (overflow, a look-back that gave up) leaves every
+  // tile empty: background, and no list or record is read
+  const uint2 rg = front_failed(w) ? make_uint2(0u, 0u) : w.ranges[ti.t];
   PixQ u;
   u.x = (float)lx - 0.5f * (float)(TW - 1);
   u.y = (float)ly - 0.5f * (float)(TH - 1);
@@ -410,7 +420,7 @@ __device__ __forceinline__ void fwd_tile(const TileInfo &ti, const Ws &w, const 
       }
     };
     auto step = [&](int j, const float *e) {
-      const float dd = eval_q(e + F_QD, u);
+      const float dd = eval_dd(e + F_QD, u);
       const float mm = eval_mm(e + F_QM, u);
       if (!is_fragment(dd, mm, e[F_RC])) return;
       ++nfrag;
@@ -536,7 +546,7 @@ __device__ __forceinline__ void fwd_tile(const TileInfo &ti, const Ws &w, const 
           // the same staging and arithmetic as in the list walk: the same alpha
           float st[F_FLOATS];
           stage_fwd(rec, cx2, cy2, st);
-          const float dd = eval_q(st + F_QD, u), mm = eval_mm(st + F_QM, u);
+          const float dd = eval_dd(st + F_QD, u), mm = eval_mm(st + F_QM, u);
           a = frag_alpha(st[F_O], mm, rcp_fast(dd), amax);
           r = st[F_R]; g = st[F_G]; b = st[F_B];
         }
@@ -595,20 +605,21 @@ struct PixLayout {
 // a tail fragment. rs holds this row's sums of the d and m weights times
 // (1, c, c^2).
 template <int KMAX>
-__device__ __forceinline__ void bwd_fragment(const float *st, const float *Pp, int c,
+__device__ __forceinline__ void bwd_fragment(float op, const float *rgb, const float *Pp, int c,
                                              float dd, float mm, int cslot, float amax,
                                              float *rs, float *acc) {
   using L = PixLayout<KMAX>;
+  // alpha exactly as the forward's frag_alpha forms it
   const float inv = rcp_fast(dd);
   const float r2 = mm * inv;
   const float e = exp2_fast(r2 * kNegHalfLog2e);
-  const float araw = st[S_O] * e;
+  const float araw = op * e;
   const bool unclamped = araw <= amax;
   const float alpha = unclamped ? araw : amax;
   const float G0 = Pp[0], G1 = Pp[1], G2 = Pp[2], w1 = Pp[3];
   // tail: dC/dalpha = w1 (c - c_tail) - T P (c_bg - c_tail) / (1 - alpha),
   // dC/dc = w1 alpha; core: the pixel's precomputed T_i (c_i - B_i) and T_i
-  const float gdc = fmaf(G2, st[S_RGB + 2], fmaf(G1, st[S_RGB + 1], G0 * st[S_RGB]));
+  const float gdc = fmaf(G2, rgb[2], fmaf(G1, rgb[1], G0 * rgb[0]));
   const float tail = fmaf(w1, gdc, -Pp[4]) - Pp[5] * rcp_fast(1.f - alpha);
   // Branch-free: every lane reads a core entry (entry 0 for tail
   // fragments) and selects.
@@ -666,7 +677,7 @@ constexpr int bwd_simd_waves() {
 template <int KMAX, int TW, int TH, bool EXACT>
 __device__ __forceinline__ void bwd_tile(const TileInfo &ti, const Ws &w, const ViewSet &vs,
                                          const KCfg &cfg, const float *__restrict__ state,
-                                         const uint32_t *__restrict__ vals) {
+                                         const uint32_t *__restrict__ vals, uint32_t &nfr) {
   constexpr int NT = TW * TH;
   constexpr int NB = NT / 64;
   constexpr int BX = TW / 8;
@@ -781,50 +792,48 @@ __device__ __forceinline__ void bwd_tile(const TileInfo &ti, const Ws &w, const 
   const int myblk = PAIRS ? (wave >> 1) : -1;
   const uint32_t c_end = PAIRS ? 2u * ((nch + 1u) >> 1) : nch;  // uniform per block when PAIRS
   const uint32_t c_step = PAIRS ? 2u : (uint32_t)BW;
+  const int cx2 = 2 * px0 + TW - 1, cy2 = 2 * py0 + TH - 1;
+  const float hx = 0.5f * (float)(TW - 1), hy = 0.5f * (float)(TH - 1);
   for (uint32_t c = PAIRS ? (uint32_t)(wave & 1) : (uint32_t)wave; c < c_end; c += c_step) {
     const uint32_t j = rg.x + c * 64u + lane;
     const bool active = c < nch && j < rg.y;
-    float st[S_FLOATS];
+    // The forward's staged forms of |d|^2 and |m|^2 for this (tile, splat)
+    // (stage_fwd, same arithmetic), so that every pixel's |d|^2, |m|^2,
+    // fragment test and alpha are bit-identical to the forward's: the
+    // backward differentiates exactly the fragments the image blended.
+    float qd[6], qm[6], rc = -1.f, op = 0.f, rgb[3] = {0.f, 0.f, 0.f};
+    int bb[4] = {1 << 20, 1 << 20, -1, -1};
 #pragma unroll
-    for (int k = 0; k < S_FLOATS; ++k) st[k] = 0.f;
-    st[S_RC] = -1.f;
-    st[S_BB0] = __int_as_float(1 << 20);
-    st[S_BB1] = __int_as_float(1 << 20);
-    st[S_BB2] = __int_as_float(-1);
-    st[S_BB3] = __int_as_float(-1);
-    uint32_t slot = 0;
+    for (int k = 0; k < 6; ++k) { qd[k] = 0.f; qm[k] = 0.f; }
+    uint32_t slot = 0, gid = 0;
     if (active) {
-      const uint32_t gid = vals[j];
+      gid = vals[j];
       float rec[kRecFloats];
       load_record(recs, gid, rec);
-      stage_record(rec, px0, py0, st);
+      float sf[F_FLOATS];
+      stage_fwd(rec, cx2, cy2, sf);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) { qd[k] = sf[F_QD + k]; qm[k] = sf[F_QM + k]; }
+      rc = sf[F_RC];
+      op = sf[F_O];
+      rgb[0] = sf[F_R]; rgb[1] = sf[F_G]; rgb[2] = sf[F_B];
+      const uint32_t b0 = __float_as_uint(rec[R_BB0]), b1 = __float_as_uint(rec[R_BB1]);
+      bb[0] = (int)(b0 & 0xffffu) - px0;
+      bb[1] = (int)(b0 >> 16) - py0;
+      bb[2] = (int)(b1 & 0xffffu) - px0;
+      bb[3] = (int)(b1 >> 16) - py0;
       if (myblk <= 0) slot = tslot_slot(w.tslots[(int64_t)ti.v * cfg.n + gid], ti.tx, ti.ty);
     }
+    const float bbf[4] = {__int_as_float(bb[0]), __int_as_float(bb[1]), __int_as_float(bb[2]),
+                          __int_as_float(bb[3])};
     // acc: d-moments (6), m-moments (6), dL/do, dL/drgb (3)
     float acc[16];
 #pragma unroll
     for (int k = 0; k < 16; ++k) acc[k] = 0.f;
-    // Unit vectors along Du and Mu and their lengths (zero stays zero).
-    float ud[3], um[3], nD, nM;
-    {
-      const float nd2 = fmaf(st[S_DU + 2], st[S_DU + 2],
-                             fmaf(st[S_DU + 1], st[S_DU + 1], st[S_DU] * st[S_DU]));
-      const float nm2 = fmaf(st[S_MU + 2], st[S_MU + 2],
-                             fmaf(st[S_MU + 1], st[S_MU + 1], st[S_MU] * st[S_MU]));
-      const float rd = nd2 > 0.f ? __builtin_amdgcn_rsqf(nd2) : 0.f;
-      const float rm = nm2 > 0.f ? __builtin_amdgcn_rsqf(nm2) : 0.f;
-      nD = nd2 * rd;
-      nM = nm2 * rm;
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        ud[k] = st[S_DU + k] * rd;
-        um[k] = st[S_MU + k] * rm;
-      }
-    }
     for (int blk = 0; blk < NB; ++blk) {
       if (PAIRS && blk != myblk) continue;
       const int bx = (blk % BX) * 8, by = (blk / BX) * 8;
-      const bool hitb = active && rect_meets_block(st + S_BB0, bx, by);
+      const bool hitb = active && rect_meets_block(bbf, bx, by);
       if (__ballot(hitb) == 0ull) continue;
       // Core table of this block for this chunk: lane = block pixel.
       {
@@ -846,54 +855,37 @@ __device__ __forceinline__ void bwd_tile(const TileInfo &ti, const Ws &w, const 
         }
         __builtin_amdgcn_wave_barrier();
       }
-      // A row at a time: along the row d and m are (row base) + c (Du, Mu)
-      // for the block column c, and the backward needs only their squared
-      // norms: with u = Du/|Du|, |d|^2 = (|Du| c + db.u)^2 + |db - (db.u) u|^2
-      // (likewise for m), two FMAs per pixel, a sum of squares (no
-      // cancellation between large terms, never negative). The moments
-      // (1, lx, ly, lx^2, lx ly, ly^2) of the weights follow from per-row
-      // sums over (1, c, c^2). The columns are unrolled, so c is a constant.
+      // Pixels of the block inside the image (the forward skips the rest).
+      const int cols_in = V.width - (px0 + bx), rows_in = V.height - (py0 + by);
+      // A row at a time: the row's parts of the two staged forms (Y, the
+      // pixel's offset from the tile centre, fixed), then two FMAs per pixel
+      // for each; the columns are unrolled, so for one-block tiles X is a
+      // constant. The moments (1, lx, ly, lx^2, lx ly, ly^2) of the weights
+      // follow from per-row sums over (1, c, c^2).
       const float fbx = (float)bx;
       for (int row = 0; row < 8; ++row) {
         const float ly = (float)(by + row);
-        float db[3], mb[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          db[k] = fmaf(ly, st[S_DV + k], st[S_D0 + k]);
-          mb[k] = fmaf(ly, st[S_MV + k], st[S_M0 + k]);
-          if constexpr (BX > 1) {
-            db[k] = fmaf(fbx, st[S_DU + k], db[k]);
-            mb[k] = fmaf(fbx, st[S_MU + k], mb[k]);
-          }
-        }
-        const float td = fmaf(db[2], ud[2], fmaf(db[1], ud[1], db[0] * ud[0]));
-        const float tm = fmaf(mb[2], um[2], fmaf(mb[1], um[1], mb[0] * um[0]));
-        float pd[3], pm[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          pd[k] = fmaf(-td, ud[k], db[k]);
-          pm[k] = fmaf(-tm, um[k], mb[k]);
-        }
-        const float Pd = fmaf(pd[2], pd[2], fmaf(pd[1], pd[1], pd[0] * pd[0]));
-        const float Pm = fmaf(pm[2], pm[2], fmaf(pm[1], pm[1], pm[0] * pm[0]));
+        const float Y = ly - hy, YY = Y * Y;
+        const float rd0 = fmaf(YY, qd[5], fmaf(Y, qd[2], qd[0]));
+        const float rd1 = fmaf(Y, qd[4], qd[1]);
+        const float s2 = fmaf(qm[4], Y, qm[5]);
+        const float rm0 = fmaf(s2, s2, qm[0]);
+        const float rm1 = fmaf(qm[2], Y, qm[3]);
+        const bool row_in = hitb && row < rows_in;
         float rs[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int col = 0; col < 8; col += 2) {
-          const int q = row * 8 + col;
-          const int p0 = (by + row) * TW + bx + col;
-          const int p1 = p0 + 1;
-          const float f0c = (float)col, f1c = (float)(col + 1);
-          const float sd0 = col == 0 ? td : fmaf(nD, f0c, td);
-          const float sm0 = col == 0 ? tm : fmaf(nM, f0c, tm);
-          const float sd1 = fmaf(nD, f1c, td), sm1 = fmaf(nM, f1c, tm);
-          const float dd0 = fmaf(sd0, sd0, Pd), mm0 = fmaf(sm0, sm0, Pm);
-          const float dd1 = fmaf(sd1, sd1, Pd), mm1 = fmaf(sm1, sm1, Pm);
-          const bool f0 = hitb && is_fragment(dd0, mm0, st[S_RC]);
-          const bool f1 = hitb && is_fragment(dd1, mm1, st[S_RC]);
-          if (f0) bwd_fragment<KMAX>(st, sp_all + p0 * L::kStride, col, dd0, mm0,
-                                     (int)s_slot[wave][q][lane] - 1, amax, rs, acc);
-          if (f1) bwd_fragment<KMAX>(st, sp_all + p1 * L::kStride, col + 1, dd1, mm1,
-                                     (int)s_slot[wave][q + 1][lane] - 1, amax, rs, acc);
+        for (int col = 0; col < 8; ++col) {
+          const float X = (fbx + (float)col) - hx, XX = X * X;
+          const float dd = fmaf(X, rd1, fmaf(XX, qd[3], rd0));
+          const float s1 = fmaf(qm[1], X, rm1);
+          const float mm = fmaf(s1, s1, rm0);
+          const bool f = row_in && col < cols_in && is_fragment(dd, mm, rc);
+          if (f) {
+            ++nfr;
+            const int q = row * 8 + col;
+            bwd_fragment<KMAX>(op, rgb, sp_all + ((by + row) * TW + bx + col) * L::kStride, col,
+                               dd, mm, (int)s_slot[wave][q][lane] - 1, amax, rs, acc);
+          }
         }
         if constexpr (BX > 1) {
           // sums over (1, c, c^2) -> over (1, lx, lx^2), lx = bx + c
@@ -934,7 +926,14 @@ __device__ __forceinline__ void bwd_tile(const TileInfo &ti, const Ws &w, const 
     }
     if (myblk <= 0 && active && (uint64_t)slot < (uint64_t)w.capacity) {
       // Gradients of the record coefficients in camera coordinates
-      // u = (x - cx)/fx, v = (y - cy)/fy: d = D0 + u Du + v Dv with u = ut + lx/fx.
+      // u = (x - cx)/fx, v = (y - cy)/fy: d = D0 + u Du + v Dv with
+      // u = ut + lx/fx. The tile-corner affine coefficients come from the
+      // record again (it is still in the cache), which keeps them out of
+      // the registers during the pixel loop.
+      float rec[kRecFloats];
+      load_record(recs, gid, rec);
+      float st[S_FLOATS];
+      stage_record(rec, px0, py0, st);
       const float ut = ((float)px0 + 0.5f - V.cx) / V.fx, vt = ((float)py0 + 0.5f - V.cy) / V.fy;
       const float ifx = 1.f / V.fx, ify = 1.f / V.fy;
       float out[kPartialFloats];
@@ -959,7 +958,7 @@ __device__ __forceinline__ void bwd_tile(const TileInfo &ti, const Ws &w, const 
       out[P_C] = acc[13];
       out[P_C + 1] = acc[14];
       out[P_C + 2] = acc[15];
-      out[P_SEG] = __uint_as_float(((uint32_t)ti.v << 27) | vals[j]);
+      out[P_SEG] = __uint_as_float(((uint32_t)ti.v << 27) | gid);
       out[23] = 0.f;
       float4 *dst = reinterpret_cast<float4 *>(w.partials + (int64_t)slot * kPartialFloats);
 #pragma unroll
@@ -999,9 +998,20 @@ template <int KMAX, int TW, int TH, bool EXACT, bool PERSIST>
 __global__ void __launch_bounds__((64 * bwd_waves<TW, TH>()), (bwd_simd_waves<KMAX, TW>()))
     k_raster_bwd(Ws w, ViewSet vs, KCfg cfg, const float *__restrict__ state,
                  const uint32_t *__restrict__ vals) {
-#define HTGS_BWD_BODY(T) bwd_tile<KMAX, TW, TH, EXACT>(T, w, vs, cfg, state, vals)
+  // the forward of a failed front end rendered empty tiles: nothing to do
+  if (front_failed(w)) return;
+  uint32_t nfr = 0;   // fragments this thread differentiated
+#define HTGS_BWD_BODY(T) bwd_tile<KMAX, TW, TH, EXACT>(T, w, vs, cfg, state, vals, nfr)
   HTGS_FOR_TILES(PERSIST, kQueueBwd, HTGS_BWD_BODY);
 #undef HTGS_BWD_BODY
+  // one atomic per workgroup
+  __shared__ uint32_t s_nfr;
+  __syncthreads();
+  if (threadIdx.x == 0) s_nfr = 0u;
+  __syncthreads();
+  if (nfr) atomicAdd(&s_nfr, nfr);
+  __syncthreads();
+  if (threadIdx.x == 0 && s_nfr) atomicAdd(w.frags_bwd, (unsigned long long)s_nfr);
 }
 
 // ---------------------------------------------------------------------------

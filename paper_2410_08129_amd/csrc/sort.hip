@@ -35,8 +35,12 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_pass(Ws w, int pass, int 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const unsigned long long tot = *w.total;
   // On overflow only part of the keys exist while the histograms count all
-  // of them; nothing is sorted and the status word reports the overflow.
+  // of them; after a give-up of the preprocess or an earlier pass the keys
+  // (and their slots) are not the counted ones. Nothing is sorted then, and
+  // the status word reports why. (A give-up inside this pass only moves
+  // positions down within [0, I): every later launch sees its flag.)
   if (tot > (unsigned long long)w.capacity) return;
+  if (ld_acq_u32(&w.status[0]) & spin_bits_before_sort(pass)) return;
   const uint64_t I = tot;
   const uint64_t nchunks = (I + kSortChunk - 1) / kSortChunk;
   if (tid == 0) s_ticket = atomicAdd(&w.status[2 + pass], 1u);
@@ -143,6 +147,10 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_pass(Ws w, int pass, int 
     int64_t j = (int64_t)chunk - 1;
     int spins = 0;
     while (true) {
+      if (spins > w.spin_limit) {  // give up (a negative limit: at once)
+        atomicOr(&w.status[0], (uint32_t)ST_SPIN | ((uint32_t)ST_SPIN_SORT0 << pass));
+        break;
+      }
       uint32_t sv[kLookWindow];
 #pragma unroll
       for (int k = 0; k < kLookWindow; ++k)
@@ -161,10 +169,7 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_pass(Ws w, int pass, int 
       if (done) break;
       j -= used;
       if (used == 0) {
-        if (++spins > kSpinLimit) {
-          atomicOr(&w.status[0], (uint32_t)ST_SPIN);
-          break;
-        }
+        ++spins;
         __builtin_amdgcn_s_sleep(1);
       }
     }
@@ -187,9 +192,11 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_pass(Ws w, int pass, int 
 // Per-tile [start, end): each thread takes 8 consecutive sorted keys (one
 // or two 16-byte loads) plus the key before them, and marks the key changes.
 template <typename KeyT>
-__global__ void __launch_bounds__(256) k_ranges(Ws w, const KeyT *__restrict__ keys) {
+__global__ void __launch_bounds__(256) k_ranges(Ws w, const KeyT *__restrict__ keys,
+                                                 uint32_t total_tiles) {
   const unsigned long long tot = *w.total;
-  if (tot > (unsigned long long)w.capacity) return;  // overflow: every tile stays empty
+  // overflow or a give-up: the keys are not a sorted list, every tile stays empty
+  if (tot > (unsigned long long)w.capacity || front_failed(w)) return;
   const uint64_t I = tot;
   const uint64_t ngroups = (I + 7) / 8;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -218,8 +225,10 @@ __global__ void __launch_bounds__(256) k_ranges(Ws w, const KeyT *__restrict__ k
       const uint64_t i = i0 + j;
       if (i >= I) break;
       const uint32_t nk = (j < 7 && i + 1 < I) ? k[j + 1] : (j == 7 ? next : 0xffffffffu);
-      if (i == 0 || k[j] != prev) w.ranges[k[j]].x = (uint32_t)i;
-      if (i + 1 == I || k[j] != nk) w.ranges[k[j]].y = (uint32_t)(i + 1);
+      if (k[j] < total_tiles) {
+        if (i == 0 || k[j] != prev) w.ranges[k[j]].x = (uint32_t)i;
+        if (i + 1 == I || k[j] != nk) w.ranges[k[j]].y = (uint32_t)(i + 1);
+      }
       prev = k[j];
     }
   }
@@ -299,12 +308,12 @@ static hipError_t sort_impl(const Ws &w, hipStream_t s) {
 }
 
 template <typename KeyT>
-static hipError_t ranges_impl(const Ws &w, hipStream_t s) {
+static hipError_t ranges_impl(const Ws &w, int total_tiles, hipStream_t s) {
   const KeyT *sorted = reinterpret_cast<const KeyT *>(w.keys[w.passes & 1]);
   int rb = (int)((w.capacity + 8 * 256 - 1) / (8 * 256));
   if (rb < 1) rb = 1;
   if (rb > 8192) rb = 8192;
-  hipLaunchKernelGGL(k_ranges<KeyT>, dim3(rb), dim3(256), 0, s, w, sorted);
+  hipLaunchKernelGGL(k_ranges<KeyT>, dim3(rb), dim3(256), 0, s, w, sorted, (uint32_t)total_tiles);
   return hipGetLastError();
 }
 
@@ -313,9 +322,10 @@ hipError_t launch_sort_passes(const Ws &w, hipStream_t s) {
   return w.key16 ? sort_impl<uint16_t>(w, s) : sort_impl<uint32_t>(w, s);
 }
 
-hipError_t launch_ranges(const Ws &w, hipStream_t s) {
+hipError_t launch_ranges(const Ws &w, int total_tiles, hipStream_t s) {
   if (w.capacity == 0) return hipSuccess;
-  return w.key16 ? ranges_impl<uint16_t>(w, s) : ranges_impl<uint32_t>(w, s);
+  return w.key16 ? ranges_impl<uint16_t>(w, total_tiles, s)
+                 : ranges_impl<uint32_t>(w, total_tiles, s);
 }
 
 }  // namespace htgs

@@ -29,6 +29,7 @@ EXPORTED = (
     "htgs_render_forward", "htgs_render_backward", "htgs_render_forward_batched",
     "htgs_render_backward_batched", "htgs_read_status", "htgs_debug_export_bins",
     "htgs_strerror", "htgs_version", "htgs_profile_enable", "htgs_profile_read",
+    "htgs_debug_set_spin_limit", "htgs_debug_fragment_counts",
 )
 STAGES = ("fill", "preprocess", "sort", "ranges", "raster_fwd", "raster_bwd", "reduce",
           "preprocess_bwd")
@@ -95,6 +96,8 @@ def lib():
     L.htgs_profile_read.argtypes = [P(ctypes.c_double), P(i64), i32]
     L.htgs_debug_export_bins.argtypes = [P(Gaussians), P(Camera), i32, P(Config), vp, i64, vp, vp,
                                          i64, vp, P(i64), vp]
+    L.htgs_debug_set_spin_limit.argtypes = [i32]
+    L.htgs_debug_fragment_counts.argtypes = [vp, i64, P(i64), P(i64), vp]
     L.htgs_strerror.argtypes = [ctypes.c_int]
     L.htgs_strerror.restype = ctypes.c_char_p
     L.htgs_version.argtypes = []
@@ -215,6 +218,24 @@ def read_status(ws: torch.Tensor, stream=None, fragments=False):
     if fragments:
         return flags.value, n.value, nf.value
     return flags.value, n.value
+
+
+def fragment_counts(ws: torch.Tensor, stream=None):
+    """(forward, backward) fragment counts of the last forward on ``ws`` and
+    the backwards since."""
+    f, b = ctypes.c_int64(), ctypes.c_int64()
+    check(lib().htgs_debug_fragment_counts(ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                           ctypes.byref(f), ctypes.byref(b),
+                                           stream_handle(stream)), "fragment_counts")
+    return f.value, b.value
+
+
+def set_spin_limit(limit: int):
+    """Look-back rounds before a wait gives up (negative: at once); testing."""
+    check(lib().htgs_debug_set_spin_limit(int(limit)), "set_spin_limit")
+
+
+DEFAULT_SPIN_LIMIT = 1 << 22
 
 
 def profile_enable(on: bool):

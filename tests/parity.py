@@ -134,3 +134,49 @@ def check_image(gpu_img, gpu_core, ref_img, info, st, tol=TOL_IMG, max_unresolve
                  resolved=resolved, unresolved=unresolved)
     assert len(unresolved) <= max_unresolved, stats
     return stats
+
+
+def ambiguous_pixels(info, H, W, st):
+    """[H, W] bool: pixels holding a near-tie of the kind the image protocol
+    arbitrates (a fragment within DELTA_RHO of rho^2 = rho_c, an alpha
+    within DELTA_A of tau_K or of the clamp, or two eligible fragments
+    among the front K + 1 whose depths lie within DELTA_Z). At such a pixel
+    float32 may take either branch, and the gradient differs between the
+    branches, so gradient windows leave these pixels out of the loss."""
+    fr = info['frags']
+    out = np.zeros(H * W, bool)
+    if fr['pix'].size == 0:
+        return out.reshape(H, W)
+    rho2, rc, raw, z = fr['rho2'], fr['rho_c'], fr['raw'], fr['depth']
+    alpha = np.minimum(st.alpha_max, raw)
+    frag = fr['frag'].astype(bool)
+    near = np.abs(rho2 - rc) <= DELTA_RHO * rc
+    near |= frag & (np.abs(alpha - st.tau_core) <= DELTA_A * st.tau_core)
+    near |= frag & (np.abs(raw - st.alpha_max) <= DELTA_A * st.alpha_max)
+    np.logical_or.at(out, fr['pix'][near], True)
+    K = int(st.K)
+    elig = frag & (alpha >= st.tau_core)
+    pix_e, z_e = fr['pix'][elig], z[elig]
+    order = np.lexsort((z_e, pix_e))
+    pix_e, z_e = pix_e[order], z_e[order]
+    if pix_e.size > 1 and K > 0:
+        start = np.searchsorted(pix_e, pix_e, side='left')
+        rank = np.arange(pix_e.size) - start
+        same = pix_e[1:] == pix_e[:-1]
+        close = np.abs(z_e[1:] - z_e[:-1]) <= DELTA_Z * np.abs(z_e[:-1])
+        hit = same & close & (rank[:-1] < K)
+        np.logical_or.at(out, pix_e[1:][hit], True)
+    return out.reshape(H, W)
+
+
+def grad_errors(got, ref):
+    """Per-tensor (|g - g_ref| / |g_ref|, max |g - g_ref| / max |g_ref|)."""
+    out = []
+    for a, b in zip(got, ref):
+        a = np.asarray(a, np.float64)
+        b = np.asarray(b, np.float64)
+        den = np.linalg.norm(b)
+        rel = np.linalg.norm(a - b) / max(den, 1e-30)
+        elem = np.abs(a - b).max() / max(np.abs(b).max(), 1e-30) if b.size else 0.0
+        out.append((float(den), float(rel), float(elem)))
+    return out

@@ -1,0 +1,189 @@
+"""Parity at full scene density under the benchmark's schedule (needs an
+MI355X).
+
+* 32-bit keys: the tile lists of a 3840x2160 frame at 8x8 tiles (129,600
+  tiles, three sort passes) bit-exact against the oracle's lists.
+* Gradients through the torch.autograd.Function: the whole 720p frame of
+  the 1M-Gaussian scene with every Gaussian, 8x8 tiles, cost order, tile
+  culling and gradient overwrite (the benchmark's schedule), the loss
+  weights non-zero on two 64x64 windows; the gradient of every Gaussian
+  whose box meets a window against the oracle's float64 autograd (1e-3
+  relative, norm and element-wise), and exactly zero for all others.
+* Large splats: Gaussians covering more than 64 tiles (backward partial
+  segments longer than one 64-slot scan) among 256 small ones.
+* Forward and backward count the same fragments (they evaluate the same
+  staged forms) on the 1080p frame."""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2410_08129_amd import htgs, scenes
+from tests import crops, parity, window_grads
+
+pytestmark = pytest.mark.gpu
+
+NAMES = ("means", "log_scales", "quats", "opacity_logits", "sh")
+BENCH = dict(K=8, tile_w=8, tile_h=8, cost_order=True, tile_cull=True, grad_overwrite=True)
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+def to_dev(sc, grad=False):
+    return [torch.tensor(a, device="cuda", requires_grad=grad) for a in sc.arrays()]
+
+
+def test_tile_lists_bit_exact_32bit_keys():
+    sc = scenes.clustered_scene(200_000, 64, seed=2, sh_degree=1)
+    cam = scenes.look_at((0, 0, -25), (0, 0, 0), (0, -1, 0), 70.0, 3840, 2160)
+    st = scenes.RenderSettings(K=8, tile_w=8, tile_h=8)
+    log("bins 200k Gaussians, 3840x2160, 8x8 tiles")
+    params = to_dev(sc)
+    frame = htgs.forward(params, sc.sh_degree, [cam], st, with_state=False)
+    keys, vals, rects, flags = htgs.export_bins(params, sc.sh_degree, [cam], st, frame.ws)
+    assert flags == 0
+    ref = oracle.bins.tile_lists(sc.means, sc.log_scales, sc.quats, sc.opacity_logits, cam, st)
+    assert ref['tiles_x'] * ref['tiles_y'] > 65536
+    n_amb = parity.compare_bins(keys, vals, rects, ref)
+    log(f"  instances {len(keys)}, tiles {ref['tiles_x'] * ref['tiles_y']}, round-off ties {n_amb}")
+
+
+def _gpu_autograd(sc, cam, st, G_full):
+    params = to_dev(sc, grad=True)
+    img = htgs.render(*params, sc.sh_degree, cam, st)
+    loss = (img * torch.tensor(G_full, dtype=torch.float32, device="cuda")).sum()
+    grads = torch.autograd.grad(loss, params)
+    torch.cuda.synchronize()
+    return img.detach(), [g.cpu().numpy().astype(np.float64) for g in grads]
+
+
+def _check_windows(sc, cam, st, windows, grads):
+    ref, touched = window_grads.accumulate(sc.n, [a.shape[1:] for a in sc.arrays()], windows)
+    for name, g, r in zip(NAMES, grads, ref):
+        # Gaussians that reach no window pixel get exactly zero
+        assert not np.any(g[~touched]), name
+    sel = np.nonzero(touched)[0]
+    for name, (den, rel, elem) in zip(NAMES, parity.grad_errors([g[sel] for g in grads],
+                                                                 [r[sel] for r in ref])):
+        log(f"  {name}: |g| {den:.3e}, rel {rel:.2e}, elem {elem:.2e}")
+        assert rel <= 1e-3 and elem <= 1e-3, name
+
+
+def test_dense_window_gradients_through_autograd():
+    sc, cam, st0, p, h, vis = crops._scene_720p()
+    st = scenes.RenderSettings(**BENCH)
+    target = scenes.smooth_target(cam.height, cam.width).astype(np.float64)
+    wins = [(608, 328), (171, 402)]
+    # loss weights of the L1 loss at the oracle's window images
+    G = np.zeros((3, cam.height, cam.width))
+    windows = []
+    for (x0, y0) in wins:
+        ref_img = oracle.render.render_scene(sc.subset(crops.meeting(p, h, vis, x0, y0, 64, 64)),
+                                             cam.crop(x0, y0, 64, 64), st)
+        G[:, y0:y0 + 64, x0:x0 + 64] = np.sign(ref_img.numpy()
+                                               - target[:, y0:y0 + 64, x0:x0 + 64]) / G.size
+    for (x0, y0) in wins:
+        w = window_grads.oracle_window(sc, cam, st, x0, y0, 64, 64, G, p, h, vis)
+        log(f"window ({x0},{y0}): {w['idx'].size} Gaussians, {w['frags_per_px']:.1f} frags/px, "
+            f"near-tie pixels left out {int(w['amb'].sum())}")
+        windows.append(w)
+    img, grads = _gpu_autograd(sc, cam, st, G)
+    # the window images of the same frame (plain forward, for the core ids)
+    frame = htgs.forward(to_dev(sc), sc.sh_degree, [cam], st)
+    torch.cuda.synchronize()
+    assert torch.equal(frame.images[0], img)
+    core = htgs.state_planes(frame, 0)['core_ids'].cpu().numpy()
+    full = img.cpu().numpy()
+    for (x0, y0), w in zip(wins, windows):
+        stats = parity.check_image(full[:, y0:y0 + 64, x0:x0 + 64], core[:, y0:y0 + 64, x0:x0 + 64],
+                                   w['ref'], w['info'], st)
+        log(f"  image ({x0},{y0}): {stats}")
+    _check_windows(sc, cam, st, windows, grads)
+
+
+def test_large_splats_backward():
+    """Three splats covering 150-190 tiles each (partial segments of three
+    64-slot scans) in front of 256 small ones, 128x96 pixels, 8x8 tiles."""
+    sub, win, st0, _ = crops.subcrop_720p(29)
+    cam = win.crop(-48, -32, 128, 96)
+    c = sub.means.astype(np.float64).mean(0)
+    rng = np.random.default_rng(29)
+    toward = cam.center - c
+    toward /= np.linalg.norm(toward)
+    big_means = c + toward * np.array([[0.6], [1.0], [1.4]]) + rng.normal(0, 0.15, (3, 3))
+    big = scenes.Scene(big_means.astype(np.float32),
+                       np.log(np.array([[0.9, 0.6, 0.5], [0.5, 0.8, 0.7], [0.7, 0.5, 0.9]]))
+                       .astype(np.float32),
+                       rng.normal(0, 1, (3, 4)).astype(np.float32),
+                       np.array([-0.5, 0.0, -1.0], np.float32),
+                       rng.normal(0, 0.3, (3, 16, 3)).astype(np.float32), 3)
+    sc = scenes.Scene(*[np.concatenate([a, b]) for a, b in zip(sub.arrays(), big.arrays())], 3)
+    st = scenes.RenderSettings(**BENCH)
+    params = to_dev(sc)
+    frame = htgs.forward(params, sc.sh_degree, [cam], st)
+    keys, vals, _, flags = htgs.export_bins(params, sc.sh_degree, [cam], st, frame.ws)
+    assert flags == 0
+    per_g = np.bincount(vals.astype(np.int64), minlength=sc.n)
+    log(f"large splats: instances of the big three {per_g[-3:].tolist()}")
+    assert (per_g[-3:] > 64).all()
+    pre = oracle.splat.prepare(sc.means, sc.log_scales, sc.quats, sc.opacity_logits, cam,
+                               st.tau_alpha)
+    p, h, vis = pre['p'].numpy(), pre['h'].numpy(), pre['visible'].numpy()
+    target = np.random.default_rng(3).uniform(0, 1, (3, cam.height, cam.width))
+    ref_img = oracle.render.render_scene(sc, cam, st).numpy()
+    G = np.sign(ref_img - target) / ref_img.size
+    windows = [window_grads.oracle_window(sc, cam, st, 0, 0, 128, 96, G, p, h, vis)]
+    log(f"  {windows[0]['frags_per_px']:.1f} frags/px, near-tie pixels left out "
+        f"{int(windows[0]['amb'].sum())}")
+    img, grads = _gpu_autograd(sc, cam, st, G)
+    _check_windows(sc, cam, st, windows, grads)
+
+
+@pytest.mark.parametrize("tile", [(8, 8), (16, 8), (16, 16)])
+def test_forward_and_backward_count_the_same_fragments(tile):
+    """The backward evaluates |d|^2, |m|^2 and the cutoff with the forward's
+    staged forms in the same order, so both passes see the identical set of
+    fragments: the two counters agree exactly on the whole 1080p frame."""
+    sc, cams, _ = scenes.workload_1080p()
+    st = scenes.RenderSettings(**dict(BENCH, tile_w=tile[0], tile_h=tile[1]))
+    params = to_dev(sc)
+    frame = htgs.forward(params, sc.sh_degree, cams, st)
+    G = torch.full_like(frame.images[0], 1e-6)
+    htgs.backward(params, frame, [G])
+    fwd, bwd = htgs.fragment_counts(frame.ws)
+    log(f"1080p tile {tile}: forward {fwd} fragments, backward {bwd}")
+    assert fwd > 1e8 and fwd == bwd
+
+
+def test_forced_lookback_give_up_is_flagged_and_safe():
+    """With a spin limit below zero every look-back gives up at once: the
+    status word reports it, the later stages treat the lists as empty (the
+    image is the background, the gradients zero) and every kernel exits
+    normally; a normal call afterwards is unaffected."""
+    sc, cams, st = scenes.workload_small()
+    st = scenes.RenderSettings(K=4, tile_w=8, tile_h=8, bg=(0.2, 0.4, 0.6), cost_order=True)
+    params = to_dev(sc)
+    ref = htgs.forward(params, sc.sh_degree, cams, st)
+    torch.cuda.synchronize()
+    ref_img = ref.images[0].clone()
+    try:
+        htgs.set_spin_limit(-1)
+        frame = htgs.forward(params, sc.sh_degree, cams, st, ws=ref.ws)
+        grads = htgs.backward(params, frame, [torch.ones_like(frame.images[0])])
+        torch.cuda.synchronize()
+        flags, _ = htgs.read_status(frame.ws)
+    finally:
+        htgs.set_spin_limit(htgs.DEFAULT_SPIN_LIMIT)
+    log(f"  forced give-up: status flags {flags}")
+    assert flags & htgs.HTGS_STATUS_SPIN_TIMEOUT
+    bg = torch.tensor(st.bg, device="cuda")[:, None, None].expand_as(frame.images[0])
+    assert torch.equal(frame.images[0], bg)
+    assert all(not torch.any(g) for g in grads)
+    again = htgs.forward(params, sc.sh_degree, cams, st, ws=ref.ws)
+    torch.cuda.synchronize()
+    assert htgs.read_status(again.ws)[0] == 0
+    assert torch.equal(again.images[0], ref_img)

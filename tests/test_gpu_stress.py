@@ -6,14 +6,17 @@ Checked: finite image and gradients over the full frame, no status flags;
 64x64 crops of the full-frame image against the float64 oracle (1e-4
 max-abs, near-ties through the admissibility protocol); gradients of a
 256-Gaussian subset (centred on a visible zero-axis splat) on a 32x32
-window against the oracle's float64 autograd (1e-3 relative)."""
+window against the oracle's float64 autograd (1e-3 relative); and the
+gradient of a 64x64 window of the full frame, every Gaussian rendered,
+through the autograd wrapper, against the oracle over all Gaussians whose
+box meets the window."""
 import numpy as np
 import pytest
 import torch
 
 import oracle
 from paper_2410_08129_amd import htgs, scenes
-from tests import parity
+from tests import crops, parity, window_grads
 
 pytestmark = pytest.mark.gpu
 
@@ -30,6 +33,14 @@ def stress():
     log("stress: generating 6M Gaussians")
     sc, cams, st = scenes.workload_stress()
     return sc, cams[0], st
+
+
+@pytest.fixture(scope="module")
+def stress_boxes(stress):
+    sc, cam, st = stress
+    pre = oracle.splat.prepare(sc.means, sc.log_scales, sc.quats, sc.opacity_logits, cam,
+                               st.tau_alpha)
+    return pre['p'].numpy(), pre['h'].numpy(), pre['visible'].numpy()
 
 
 @pytest.fixture(scope="module")
@@ -68,8 +79,8 @@ def test_stress_full_frame_finite(stress, stress_frame):
 def test_stress_image_crops(stress, stress_frame):
     sc, cam, st = stress
     img, core = stress_frame['img'], stress_frame['core']
-    crops = [(1888, 1048)] + [(x, y) for x, y, _ in scenes.random_crops(cam, 2, 64, seed=9)]
-    for (x0, y0) in crops:
+    wins = [(1888, 1048)] + [(x, y) for x, y, _ in scenes.random_crops(cam, 2, 64, seed=9)]
+    for (x0, y0) in wins:
         c = cam.crop(x0, y0, 64, 64)
         ref, info = oracle.render.render_scene(sc, c, st, info=True)
         stats = parity.check_image(img[:, y0:y0 + 64, x0:x0 + 64],
@@ -79,11 +90,8 @@ def test_stress_image_crops(stress, stress_frame):
         assert stats['max_err_clean'] < 1e-4
 
 
-def _degenerate_subcrop(sc, cam, st, seed, n_sel=256, size=32):
-    pre = oracle.splat.prepare(sc.means, sc.log_scales, sc.quats, sc.opacity_logits, cam,
-                               st.tau_alpha)
-    p, h = pre['p'].numpy(), pre['h'].numpy()
-    vis = pre['visible'].numpy()
+def _degenerate_subcrop(sc, cam, st, boxes, seed, n_sel=256, size=32):
+    p, h, vis = boxes
     deg = np.isinf(sc.log_scales).any(1)
     rng = np.random.default_rng(seed)
     inner = np.nonzero(vis & deg & (p[:, 0] > 64) & (p[:, 0] < cam.width - 64)
@@ -102,9 +110,9 @@ def _degenerate_subcrop(sc, cam, st, seed, n_sel=256, size=32):
 
 
 @pytest.mark.parametrize("seed", [21, 22])
-def test_stress_gradients_on_subcrop(stress, seed):
+def test_stress_gradients_on_subcrop(stress, stress_boxes, seed):
     sc, cam, st = stress
-    sub, c = _degenerate_subcrop(sc, cam, st, seed)
+    sub, c = _degenerate_subcrop(sc, cam, st, stress_boxes, seed)
     log(f"stress gradients: seed {seed}, "
         f"{int(np.isinf(sub.log_scales).any(1).sum())} zero-axis of 256")
     G = np.random.default_rng(seed).normal(0, 1, (3, c.height, c.width)) / (3 * c.height * c.width)
@@ -134,5 +142,41 @@ def test_stress_gradients_on_subcrop(stress, seed):
         den = np.linalg.norm(b)
         rel = num / max(den, 1e-30)
         elem = np.abs(a - b).max() / max(np.abs(b).max(), 1e-30)
+        log(f"  {name}: |g| {den:.3e}, rel {rel:.2e}, elem {elem:.2e}")
+        assert rel <= 1e-3 and elem <= 1e-3, name
+
+
+def test_stress_window_gradients_through_autograd(stress, stress_boxes):
+    """A 64x64 window at the frame centre (~470 fragments per pixel), the
+    whole 6M-Gaussian frame rendered through htgs.render with 8x8 tiles,
+    cost order, tile culling and gradient overwrite."""
+    sc, cam, st0 = stress
+    p, h, vis = stress_boxes
+    st = scenes.RenderSettings(K=16, tile_w=8, tile_h=8, cost_order=True, tile_cull=True,
+                               grad_overwrite=True)
+    x0, y0 = 1888, 1048
+    idx = crops.meeting(p, h, vis, x0, y0, 64, 64)
+    ref_img = oracle.render.render_scene(sc.subset(idx), cam.crop(x0, y0, 64, 64), st).numpy()
+    target = scenes.smooth_target(cam.height, cam.width)[:, y0:y0 + 64, x0:x0 + 64]
+    G = np.zeros((3, cam.height, cam.width))
+    G[:, y0:y0 + 64, x0:x0 + 64] = np.sign(ref_img - target) / G.size
+    w = window_grads.oracle_window(sc, cam, st, x0, y0, 64, 64, G, p, h, vis)
+    log(f"stress window: {w['idx'].size} Gaussians, {w['frags_per_px']:.1f} frags/px, "
+        f"near-tie pixels left out {int(w['amb'].sum())}")
+    params = [torch.tensor(a, device="cuda", requires_grad=True) for a in sc.arrays()]
+    img = htgs.render(*params, sc.sh_degree, cam, st)
+    loss = (img * torch.tensor(G, dtype=torch.float32, device="cuda")).sum()
+    grads = [g.cpu().numpy() for g in torch.autograd.grad(loss, params)]
+    torch.cuda.synchronize()
+    del params, img, loss
+    torch.cuda.empty_cache()
+    ref, touched = window_grads.accumulate(sc.n, [a.shape[1:] for a in sc.arrays()], [w])
+    for name, g in zip(NAMES, grads):
+        assert np.isfinite(g).all(), name
+        assert not np.any(g[~touched]), name
+    sel = np.nonzero(touched)[0]
+    for name, (den, rel, elem) in zip(NAMES, parity.grad_errors([g[sel].astype(np.float64)
+                                                                  for g in grads],
+                                                                 [r[sel] for r in ref])):
         log(f"  {name}: |g| {den:.3e}, rel {rel:.2e}, elem {elem:.2e}")
         assert rel <= 1e-3 and elem <= 1e-3, name
