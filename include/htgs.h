@@ -114,7 +114,12 @@ typedef struct htgs_camera {
  *             HTGS_FLAG_PERSISTENT: the raster launches hold as many
  *             workgroups as fit on the device at once, each pulling tiles
  *             from an atomic queue (in descending-cost order with
- *             HTGS_FLAG_COST_ORDER) until it runs out */
+ *             HTGS_FLAG_COST_ORDER) until it runs out;
+ *             HTGS_FLAG_NO_TAIL: inference without the tail (Sec. 4.3,
+ *             "Hybrid Transparency Ablations"): C = sum over the core of
+ *             alpha_i T_i c_i + T_{n+1} c_bg, every non-core fragment left
+ *             out; the state then holds an empty tail. Forward only: the
+ *             backward rejects it with HTGS_E_INVAL */
 typedef struct htgs_config {
   int32_t K;
   float tau_alpha;
@@ -131,6 +136,7 @@ typedef struct htgs_config {
 #define HTGS_FLAG_GRAD_OVERWRITE 2u
 #define HTGS_FLAG_TILE_CULL 4u
 #define HTGS_FLAG_PERSISTENT 8u
+#define HTGS_FLAG_NO_TAIL 16u
 
 /* Gradient outputs, same shapes as htgs_gaussians. The backward ADDS into
  * them (+=), or overwrites them with HTGS_FLAG_GRAD_OVERWRITE; any pointer

@@ -12,6 +12,10 @@ fragment forms the tail, blended without order:
 Readings where the paper is silent: n is the number of actual core members
 (n <= K) and T_{n+1} the transmittance after them; an empty tail contributes
 T_{n+1} c_bg; equal depths are ordered by ascending Gaussian index.
+
+Inference without the tail (Sec. 4.3, "Hybrid Transparency Ablations",
+Table ablations): the tail term is left out, so the background lies
+directly behind the core, C = sum_{i<=n} alpha_i T_i c_i + T_{n+1} c_bg.
 """
 from __future__ import annotations
 
@@ -41,10 +45,11 @@ def composite_pixel(core_alpha, core_colour, tail_alpha, tail_colour, bg):
     return C + T * X
 
 
-def hybrid(alpha, colour, depth, frag, K, tau_core, bg):
+def hybrid(alpha, colour, depth, frag, K, tau_core, bg, tail=True):
     """Vectorised over pixels: alpha/depth/frag [P,G] (alpha = 0 off the
     fragments), colour [G,3]. Returns C [P,3] and per-pixel core indices
-    (ordered, [P,min(K,G)], -1 past the n-th) for parity checks."""
+    (ordered, [P,min(K,G)], -1 past the n-th) for parity checks. With
+    ``tail=False`` the tail term is dropped (inference without the tail)."""
     Pn, G = alpha.shape
     bg = torch.as_tensor(bg, dtype=F64)
     eligible = frag & (alpha >= tau_core)
@@ -69,6 +74,9 @@ def hybrid(alpha, colour, depth, frag, K, tau_core, bg):
         T_n1 = torch.ones(Pn, dtype=F64)
         core_mask = torch.zeros((Pn, G), dtype=torch.bool)
         core_ids = torch.zeros((Pn, 0), dtype=torch.long)
+    if not tail:
+        C = core_sum + T_n1[:, None] * bg[None, :]
+        return C, core_ids
     tail = frag & ~core_mask
     a_tail = torch.where(tail, alpha, torch.zeros_like(alpha))
     A = a_tail.sum(1)

@@ -110,7 +110,7 @@ def render(means, log_scales, quats, opacity_logits, sh_coeffs, sh_degree, cam, 
             continue
         rho2, z, frag, raw, alpha = evaluate(prep, xs, ys, settings)
         C, core = blend.hybrid(alpha, prep.colour, z, frag, settings.K, settings.tau_core,
-                               settings.bg)
+                               settings.bg, tail=not getattr(settings, 'no_tail', False))
         outs.append(C)
         if info:
             gid = prep.idx[core.clamp(min=0)]

@@ -44,7 +44,9 @@ int bits_for(int64_t tiles) {
   return b;
 }
 
-Layout make_layout(int64_t n, int n_views, int64_t total_tiles, int64_t capacity) {
+// partials = false: a forward-only layout (no backward partials).
+Layout make_layout(int64_t n, int n_views, int64_t total_tiles, int64_t capacity,
+                   bool partials = true) {
   Layout L{};
   L.capacity = capacity;
   L.key_bits = bits_for(total_tiles);
@@ -70,19 +72,21 @@ Layout make_layout(int64_t n, int n_views, int64_t total_tiles, int64_t capacity
   L.keys1 = o; o = align_up(o + kb * capacity);
   L.vals0 = o; o = align_up(o + 4 * capacity);
   L.vals1 = o; o = align_up(o + 4 * capacity);
-  L.partials = o; o = align_up(o + (int64_t)kPartialFloats * 4 * capacity);
+  L.partials = o; o = align_up(o + (partials ? (int64_t)kPartialFloats * 4 * capacity : 0));
   L.bytes = o;
   return L;
 }
 
 // Largest capacity whose layout fits in ws_bytes, or -1.
-int64_t capacity_for(int64_t n, int n_views, int64_t total_tiles, int64_t ws_bytes) {
-  if (make_layout(n, n_views, total_tiles, 0).bytes > ws_bytes) return -1;
+int64_t capacity_for(int64_t n, int n_views, int64_t total_tiles, int64_t ws_bytes,
+                     bool partials = true) {
+  if (make_layout(n, n_views, total_tiles, 0, partials).bytes > ws_bytes) return -1;
   int64_t lo = 0, hi = kMaxCapacity;
-  if (make_layout(n, n_views, total_tiles, hi).bytes <= ws_bytes) return hi;
+  if (make_layout(n, n_views, total_tiles, hi, partials).bytes <= ws_bytes) return hi;
   while (hi - lo > 1) {
     const int64_t mid = lo + (hi - lo) / 2;
-    if (make_layout(n, n_views, total_tiles, mid).bytes <= ws_bytes) lo = mid; else hi = mid;
+    if (make_layout(n, n_views, total_tiles, mid, partials).bytes <= ws_bytes) lo = mid;
+    else hi = mid;
   }
   return lo;
 }
@@ -138,7 +142,7 @@ int check_cfg(const htgs_config *cfg) {
     return HTGS_E_INVAL;
   if (cfg->flags &
       ~(uint32_t)(HTGS_FLAG_COST_ORDER | HTGS_FLAG_GRAD_OVERWRITE | HTGS_FLAG_TILE_CULL |
-                  HTGS_FLAG_PERSISTENT))
+                  HTGS_FLAG_PERSISTENT | HTGS_FLAG_NO_TAIL))
     return HTGS_E_INVAL;
   return HTGS_OK;
 }
@@ -237,6 +241,7 @@ KCfg make_kcfg(const htgs_gaussians *g, const htgs_config *cfg) {
   k.grad_overwrite = (cfg->flags & HTGS_FLAG_GRAD_OVERWRITE) ? 1 : 0;
   k.tile_cull = (cfg->flags & HTGS_FLAG_TILE_CULL) ? 1 : 0;
   k.persistent = (cfg->flags & HTGS_FLAG_PERSISTENT) ? 1 : 0;
+  k.no_tail = (cfg->flags & HTGS_FLAG_NO_TAIL) ? 1 : 0;
   return k;
 }
 
@@ -282,8 +287,10 @@ struct StageTimer {
   Profiler::Rec rec{};
   hipStream_t s;
   bool active = false;
-  StageTimer(int stage, hipStream_t st, int launches = 1) : s(st) {
-    if (!g_prof.on) return;
+  // timed = false: never records (the no-allocation entry point creates no
+  // events)
+  StageTimer(int stage, hipStream_t st, int launches = 1, bool timed = true) : s(st) {
+    if (!g_prof.on || !timed) return;
     rec.stage = stage;
     rec.launches = launches;
     rec.a = g_prof.take();
@@ -297,45 +304,47 @@ struct StageTimer {
 };
 
 int run_front(const htgs_gaussians *g, const ViewSet &vs, const htgs_config *cfg, const Layout &L,
-              void *ws, hipStream_t s, bool sort) {
+              void *ws, hipStream_t s, bool sort, bool timed = true) {
   const Ws w = make_ws(ws, L);
   {
-    StageTimer t(HTGS_STAGE_FILL, s);
+    StageTimer t(HTGS_STAGE_FILL, s, 1, timed);
     HIP_TRY(launch_fill_zero(ws, L.zero_end, s));
   }
   {
-    StageTimer t(HTGS_STAGE_PREPROCESS, s);
+    StageTimer t(HTGS_STAGE_PREPROCESS, s, 1, timed);
     HIP_TRY(launch_preprocess(make_gp(g), make_kcfg(g, cfg), vs, w, s));
   }
   if (sort && L.capacity > 0) {
-    StageTimer t(HTGS_STAGE_SORT, s, L.passes);
+    StageTimer t(HTGS_STAGE_SORT, s, L.passes, timed);
     HIP_TRY(launch_sort_passes(w, s));
   }
   if (sort && L.capacity > 0) {
-    StageTimer t(HTGS_STAGE_RANGES, s);
+    StageTimer t(HTGS_STAGE_RANGES, s, 1, timed);
     HIP_TRY(launch_ranges(w, vs.total_tiles, s));
     if (cfg->flags & HTGS_FLAG_COST_ORDER) HIP_TRY(launch_tile_order(w, vs.total_tiles, s));
   }
   return HTGS_OK;
 }
 
+// partials = false: forward-only workspace layout, no stage timing (the
+// no-allocation entry point).
 int forward_impl(const htgs_gaussians *g, const htgs_camera *cams, int32_t n_views,
                  const htgs_config *cfg, void *ws, int64_t ws_bytes, void *state,
-                 float *const *out_rgb, void *stream) {
+                 float *const *out_rgb, void *stream, bool partials = true) {
   int e = check_common(g, cams, n_views, cfg);
   if (e) return e;
   if (!ws || !out_rgb) return HTGS_E_INVAL;
   for (int v = 0; v < n_views; ++v)
     if (!out_rgb[v]) return HTGS_E_INVAL;
   const int64_t tiles = total_tiles_of(cams, n_views, cfg);
-  const int64_t cap = capacity_for(g->n, n_views, tiles, ws_bytes);
+  const int64_t cap = capacity_for(g->n, n_views, tiles, ws_bytes, partials);
   if (cap < 0) return HTGS_E_WORKSPACE;
-  const Layout L = make_layout(g->n, n_views, tiles, cap);
+  const Layout L = make_layout(g->n, n_views, tiles, cap, partials);
   const ViewSet vs = make_views(cams, n_views, cfg, out_rgb, nullptr);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if ((e = run_front(g, vs, cfg, L, ws, s, true))) return e;
+  if ((e = run_front(g, vs, cfg, L, ws, s, true, partials))) return e;
   const Ws w = make_ws(ws, L);
-  StageTimer t(HTGS_STAGE_RASTER_FWD, s);
+  StageTimer t(HTGS_STAGE_RASTER_FWD, s, 1, partials);
   if (cfg->flags & HTGS_FLAG_PERSISTENT)
     HIP_TRY(launch_fill_zero(static_cast<char *>(ws) + L.status + 4 * kQueueFwd, 16, s));
   HIP_TRY(launch_raster_fwd(w, vs, make_kcfg(g, cfg), static_cast<float *>(state),
@@ -349,6 +358,8 @@ int backward_impl(const htgs_gaussians *g, const htgs_camera *cams, int32_t n_vi
   int e = check_common(g, cams, n_views, cfg);
   if (e) return e;
   if (!ws || !state || !grad_rgb || !grads) return HTGS_E_INVAL;
+  // inference-only modes have no backward
+  if (cfg->flags & HTGS_FLAG_NO_TAIL) return HTGS_E_INVAL;
   if (!aligned16(grads->means) || !aligned16(grads->log_scales) || !aligned16(grads->quats) ||
       !aligned16(grads->opacity_logits) || !aligned16(grads->sh))
     return HTGS_E_INVAL;

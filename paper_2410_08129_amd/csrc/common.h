@@ -85,6 +85,7 @@ struct KCfg {
   int32_t grad_overwrite;  // preprocess backward stores gradients instead of adding
   int32_t tile_cull;       // drop rect tiles that no fragment can reach (rects of <= 64 tiles)
   int32_t persistent;      // raster workgroups pull tiles from an atomic queue
+  int32_t no_tail;         // forward leaves the tail out (inference)
 };
 
 struct GaussPtrs {

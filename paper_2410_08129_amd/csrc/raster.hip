@@ -343,6 +343,7 @@ __device__ __forceinline__ void fwd_tile(const TileInfo &ti, const Ws &w, const 
   const int cx2 = 2 * px0 + TW - 1, cy2 = 2 * py0 + TH - 1;
   const int K = EXACT ? KMAX : cfg.K;
   const float tau_core = cfg.tau_core, amax = cfg.alpha_max;
+  const bool no_tail = cfg.no_tail != 0;
   const float *recs = w.records + (int64_t)ti.v * cfg.n * kRecFloats;
   const uint64_t lanemask_lt = (1ull << lane) - 1ull;
 
@@ -427,11 +428,13 @@ __device__ __forceinline__ void fwd_tile(const TileInfo &ti, const Ws &w, const 
       const float inv = rcp_fast(dd);
       const float alpha = frag_alpha(e[F_O], mm, inv, amax);
       const float4 f5 = s_stage[j * SV + F_QZ / 4 + 1];   // qz4, qz5, g, b
-      A += alpha;
-      S0 = fmaf(alpha, e[F_R], S0);
-      S1 = fmaf(alpha, f5.z, S1);
-      S2 = fmaf(alpha, f5.w, S2);
-      P *= 1.f - alpha;
+      if (!no_tail) {   // uniform: a kernel argument
+        A += alpha;
+        S0 = fmaf(alpha, e[F_R], S0);
+        S1 = fmaf(alpha, f5.z, S1);
+        S2 = fmaf(alpha, f5.w, S2);
+        P *= 1.f - alpha;
+      }
       if (alpha >= tau_core && K > 0) {
         const float4 f4 = s_stage[j * SV + F_QZ / 4];     // qz0..qz3
         const float qz[6] = {f4.x, f4.y, f4.z, f4.w, f5.x, f5.y};
@@ -555,8 +558,9 @@ __device__ __forceinline__ void fwd_tile(const TileInfo &ti, const Ws &w, const 
     }
   }
   // Tail sums: everything minus the core; exactly empty when no fragment
-  // is left over.
-  if (nfrag == ncore) {
+  // is left over, or when the tail is left out (inference without the
+  // tail, Sec. 4.3: the background lies right behind the core).
+  if (no_tail || nfrag == ncore) {
     A = 0.f; S0 = S1 = S2 = 0.f; P = 1.f;
   } else {
     A = fmaxf(A - Ac, 0.f);

@@ -22,6 +22,7 @@ HTGS_FLAG_COST_ORDER = 1
 HTGS_FLAG_GRAD_OVERWRITE = 2
 HTGS_FLAG_TILE_CULL = 4
 HTGS_FLAG_PERSISTENT = 8
+HTGS_FLAG_NO_TAIL = 16
 MAX_VIEWS = 16
 
 EXPORTED = (
@@ -145,7 +146,8 @@ def config_struct(st) -> Config:
     c.flags = ((HTGS_FLAG_COST_ORDER if getattr(st, "cost_order", False) else 0)
                | (HTGS_FLAG_GRAD_OVERWRITE if getattr(st, "grad_overwrite", False) else 0)
                | (HTGS_FLAG_TILE_CULL if getattr(st, "tile_cull", False) else 0)
-               | (HTGS_FLAG_PERSISTENT if getattr(st, "persistent", False) else 0))
+               | (HTGS_FLAG_PERSISTENT if getattr(st, "persistent", False) else 0)
+               | (HTGS_FLAG_NO_TAIL if getattr(st, "no_tail", False) else 0))
     return c
 
 

@@ -97,6 +97,7 @@ class RenderSettings:
     grad_overwrite: bool = False  # backward writes gradients instead of adding to them
     tile_cull: bool = False     # drop box tiles that the rho_c-ellipse does not reach
     persistent: bool = False    # raster workgroups pull tiles from an atomic queue
+    no_tail: bool = False       # inference without the tail (forward only)
 
 
 def look_at(eye, target, up_world, fov_x_deg, width, height, z_near=0.2) -> Camera:

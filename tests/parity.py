@@ -89,16 +89,21 @@ def _admissible(rec, core, st):
 
 def recompute_with_branch(rec, core, st, gpu_rgb):
     """Smallest max-abs error over admissible branch choices (None if the
-    GPU core is inadmissible or too many inclusion ties)."""
+    GPU core is inadmissible or too many inclusion ties). Without the tail
+    (st.no_tail) only the core is blended."""
     adm = _admissible(rec, core, st)
     if adm is None:
         return None
     idx, clear_in, amb_in, alpha = adm
     core_set = set(idx)
     amb_free = [i for i in np.nonzero(amb_in)[0] if i not in core_set]
+    if getattr(st, 'no_tail', False):
+        amb_free = []
     if len(amb_free) > 6:
         return None
     base_tail = [i for i in np.nonzero(clear_in & ~amb_in)[0] if i not in core_set]
+    if getattr(st, 'no_tail', False):
+        base_tail = []
     col = rec['colour']
     best = np.inf
     for r in range(len(amb_free) + 1):

@@ -58,7 +58,7 @@ def test_workspace_and_state_sizes():
 
 @pytest.mark.parametrize("field,value", [
     ("K", 33), ("K", -1), ("tile_w", 12), ("tau_alpha", 0.0), ("alpha_max", 1.0),
-    ("flags", 16), ("lds_batch", 7), ("lds_batch", 512),
+    ("flags", 1 << 10), ("lds_batch", 7), ("lds_batch", 512),
 ])
 def test_bad_config_rejected(field, value):
     sc, cams, st = _small()
@@ -159,6 +159,10 @@ def test_backward_and_batched_argument_errors():
     gr2.means = 0x2008
     assert L.htgs_render_backward(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(cfg), fake,
                                   1 << 30, fake, fake, ctypes.byref(gr2), None) == -1
+    # inference without the tail has no backward
+    nt = htgs.config_struct(scenes.RenderSettings(K=4, no_tail=True))
+    assert L.htgs_render_backward(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(nt), fake,
+                                  1 << 30, fake, fake, ctypes.byref(gr), None) == -1
     assert L.htgs_read_status(None, 0, None, None, None, None) == -1
     assert L.htgs_profile_read(None, None, 0) == -1
     n = ctypes.c_int64()

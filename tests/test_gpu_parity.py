@@ -105,6 +105,26 @@ def test_small_image_parity_variants(K, tile, bg):
     log(f"  {stats}")
 
 
+@pytest.mark.parametrize("K,tile", [(4, 16), (16, 8), (8, (16, 8)), (32, 8)])
+def test_no_tail_image_parity(K, tile):
+    """Inference without the tail (Sec. 4.3): only the core is blended, the
+    background right behind it."""
+    sc, cams, st = scenes.workload_small()
+    tw, th = _shape(tile)
+    st = scenes.RenderSettings(K=K, tile_w=tw, tile_h=th, bg=(0.3, 0.2, 0.1), no_tail=True,
+                               cost_order=True)
+    cam = cams[0].crop(13, 29, 91, 67)
+    log(f"no tail: K={K} tile={tile}")
+    params, frame = gpu_forward(sc, [cam], st)
+    ref, info = oracle.render.render_scene(sc, cam, st, info=True)
+    stats = parity.check_image(frame.images[0].cpu().numpy(), core_of(frame), ref.numpy(), info, st)
+    log(f"  {stats}")
+    assert stats['max_err_clean'] < 1e-4
+    full = scenes.RenderSettings(**{**st.__dict__, 'no_tail': False})
+    _, frame_t = gpu_forward(sc, [cam], full)
+    assert float((frame_t.images[0] - frame.images[0]).abs().max()) > 1e-3   # the tail mattered
+
+
 # ---------------------------------------------------------------------------
 # 1080p workload: 1M clustered Gaussians, SH 3
 # ---------------------------------------------------------------------------

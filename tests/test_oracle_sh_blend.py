@@ -201,3 +201,52 @@ def test_degenerate_splats_finite_image_and_gradients():
 
 
 
+
+
+# ---------------------------------------------------------------------------
+# Inference without the tail (Sec. 4.3, Table ablations)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("K", [1, 3, 8])
+def test_no_tail_is_sorted_blending_of_the_core_alone(K):
+    """Per pixel: the K nearest fragments with alpha >= tau_K (ties by
+    index), alpha-blended in depth order over the background; every other
+    fragment is ignored."""
+    sc = H.tiny_random_scene(16, seed=31)
+    cam = H.simple_camera(18, 18, 28.0)
+    bg = (0.25, 0.5, 0.9)
+    st = H.settings(K=K, bg=bg, no_tail=True)
+    img = oracle.render.render_scene(sc, cam, st, cull=False).numpy()
+    full = oracle.render.render_scene(sc, cam, H.settings(K=K, bg=bg), cull=False).numpy()
+    prep, z, frag, alpha = _pixel_fragments(sc, cam, st)
+    col = prep.colour.numpy()
+    n_diff = 0
+    for p in range(cam.width * cam.height):
+        ids = [int(i) for i in np.nonzero(frag[p] & (alpha[p] >= st.tau_core))[0]]
+        core = sorted(ids, key=lambda i: (z[p, i], int(prep.idx[i])))[:K]
+        ref = H.sorted_blend(alpha[p, core], col[core], z[p, core], bg)
+        j, i = divmod(p, cam.width)
+        assert np.abs(img[:, j, i] - ref).max() < 1e-14
+        n_diff += int(np.abs(img[:, j, i] - full[:, j, i]).max() > 1e-6)
+    assert n_diff > 10     # the tail does matter somewhere in this scene
+
+
+def test_no_tail_equals_hybrid_when_the_tail_is_empty():
+    """K at least the fragment count and tau_K = 0: the core holds every
+    fragment, the tail is empty, so both modes give exact sorted blending."""
+    sc = H.tiny_random_scene(12, seed=32)
+    cam = H.simple_camera(16, 16, 25.0)
+    st = H.settings(K=32, tau_core=0.0, bg=(0.1, 0.2, 0.3))
+    a = oracle.render.render_scene(sc, cam, st, cull=False).numpy()
+    b = oracle.render.render_scene(sc, cam, H.settings(K=32, tau_core=0.0, bg=(0.1, 0.2, 0.3),
+                                                       no_tail=True), cull=False).numpy()
+    assert np.abs(a - b).max() < 1e-14
+
+
+def test_no_tail_with_empty_core_is_background():
+    sc = H.tiny_random_scene(12, seed=33)
+    cam = H.simple_camera(16, 16, 25.0)
+    bg = (0.4, 0.3, 0.2)
+    img = oracle.render.render_scene(sc, cam, H.settings(K=0, bg=bg, no_tail=True),
+                                     cull=False).numpy()
+    assert np.abs(img - np.array(bg)[:, None, None]).max() == 0.0
