@@ -60,7 +60,21 @@ enum {
  *  sh             [n,(sh_degree+1)^2,3]  real SH coefficients, index l*l+l+m,
  *                 orthonormal basis without the Condon-Shortley phase;
  *                 colour = max(0, sum k_lm Y_lm(dir) + 0.5), dir = unit vector
- *                 from the camera centre to the mean. */
+ *                 from the camera centre to the mean.
+ *  filter_var     [n] or NULL (4-byte aligned): variance f >= 0 of the 3D
+ *                 smoothing filter (Mip-Splatting, which the paper uses in
+ *                 place of a screen-space filter, Sec. 4.2), normally
+ *                 derived by the caller from the training cameras' sampling
+ *                 rates. Each covariance R diag(s^2) R^T becomes
+ *                 R diag(s^2 + f) R^T and the opacity o prod_k s_k /
+ *                 sqrt(s_k^2 + f) (the peak of the density convolved with
+ *                 an isotropic unit-mass Gaussian of variance f); gradients
+ *                 flow through both to log_scales and opacity_logits.
+ * With HTGS_FLAG_BAKED ("baked" inputs, frame-rate appendix) log_scales
+ * holds the scales themselves, quats unit quaternions and opacity_logits
+ * the opacities: the activations are skipped; filter_var must then be NULL
+ * (bake the filter into the scales and opacities), and there is no
+ * backward. */
 typedef struct htgs_gaussians {
   int64_t n;
   int32_t sh_degree; /* 0..3 */
@@ -70,6 +84,7 @@ typedef struct htgs_gaussians {
   const float *quats;
   const float *opacity_logits;
   const float *sh;
+  const float *filter_var;
 } htgs_gaussians;
 
 /* Pinhole camera. world_to_cam is the row-major 3x4 [R|t] (host memory, part
@@ -119,7 +134,9 @@ typedef struct htgs_camera {
  *             "Hybrid Transparency Ablations"): C = sum over the core of
  *             alpha_i T_i c_i + T_{n+1} c_bg, every non-core fragment left
  *             out; the state then holds an empty tail. Forward only: the
- *             backward rejects it with HTGS_E_INVAL */
+ *             backward rejects it with HTGS_E_INVAL;
+ *             HTGS_FLAG_BAKED: the parameter arrays hold activated values
+ *             (see htgs_gaussians). Forward only */
 typedef struct htgs_config {
   int32_t K;
   float tau_alpha;
@@ -137,16 +154,27 @@ typedef struct htgs_config {
 #define HTGS_FLAG_TILE_CULL 4u
 #define HTGS_FLAG_PERSISTENT 8u
 #define HTGS_FLAG_NO_TAIL 16u
+#define HTGS_FLAG_BAKED 32u
 
 /* Gradient outputs, same shapes as htgs_gaussians. The backward ADDS into
  * them (+=), or overwrites them with HTGS_FLAG_GRAD_OVERWRITE; any pointer
- * may be NULL to skip that parameter. */
+ * may be NULL to skip that parameter.
+ * Densification sums (Sec. 4.2; [n] each, 4-byte aligned, or NULL), always
+ * ADDED to, whatever the flags, so that they gather over training steps:
+ *  mean_grad_stat  per view v of the call, |dL_v/dmu| * |mu - c_v| / 2: the
+ *                  gradient of the mean scaled by half the distance of the
+ *                  mean from the camera centre (the paper's replacement for
+ *                  the screen-space mean gradient of 3DGS)
+ *  visible_count   per view, 1 where the Gaussian survives culling and its
+ *                  screen box (Sec. 3.2) holds a pixel centre */
 typedef struct htgs_grads {
   float *means;
   float *log_scales;
   float *quats;
   float *opacity_logits;
   float *sh;
+  float *mean_grad_stat;
+  float *visible_count;
 } htgs_grads;
 
 /* Bytes of workspace for n Gaussians, the given views and settings, and room
@@ -248,6 +276,13 @@ int htgs_debug_export_bins(const htgs_gaussians *g, const htgs_camera *cams, int
                            uint32_t *keys_out, uint32_t *values_out, int64_t max_out,
                            int32_t *rects_out, int64_t *instances_out, void *stream);
 
+/* Opacity decay of the densification phase (Sec. 4.2: opacities are
+ * multiplied by lambda_o = 0.9995 every 50 iterations instead of being
+ * reset): opacity_logits[i] <- logit(lambda * sigmoid(opacity_logits[i])),
+ * in place, DEVICE pointer, n entries, 0 < lambda <= 1; computed in float64
+ * and finite for every finite input. Asynchronous on stream. */
+int htgs_opacity_decay(float *opacity_logits, int64_t n, float lambda, void *stream);
+
 /* Debugging and testing.
  * htgs_debug_set_spin_limit: look-back rounds (each one memory round trip
  *   and a short sleep) after which a workgroup waiting for its
@@ -266,7 +301,7 @@ int htgs_debug_fragment_counts(const void *ws, int64_t ws_bytes, int64_t *forwar
 /* Static description of an error code. */
 const char *htgs_strerror(int code);
 
-/* ABI version, currently 1. */
+/* ABI version, currently 2 (htgs_gaussians gained filter_var). */
 int htgs_version(void);
 
 #ifdef __cplusplus

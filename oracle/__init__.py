@@ -19,5 +19,7 @@ Modules
   blend   hybrid-transparency composite (Sec. 3.3)
   render  the brute-force renderer and crop culling
   bins    the tile/key-list reference (bbox -> pixel-centre rect -> tiles)
+  densify training-side quantities beside the renderer: the densification
+          statistic of the splat means and the opacity decay (Sec. 4.2)
 """
-from . import splat, sh, rays, blend, render, bins  # noqa: F401
+from . import splat, sh, rays, blend, render, bins, densify  # noqa: F401

@@ -46,10 +46,11 @@ def pixel_rects(prep, cam):
     return rect, ok, margin
 
 
-def tile_lists(means, log_scales, quats, opacity_logits, cam, settings):
+def tile_lists(means, log_scales, quats, opacity_logits, cam, settings, filter_var=None):
     """Sorted (keys, values) of all instances, the per-Gaussian tile rects
     [tx0, ty0, tx1, ty1] (inclusive, -1 where empty) and edge margins."""
-    prep = splat.prepare(means, log_scales, quats, opacity_logits, cam, settings.tau_alpha)
+    prep = splat.prepare(means, log_scales, quats, opacity_logits, cam, settings.tau_alpha,
+                         filter_var, getattr(settings, 'baked', False))
     rect, ok, margin = pixel_rects(prep, cam)
     tw, th = int(settings.tile_w), int(settings.tile_h)
     tiles_x = math.ceil(cam.width / tw)

@@ -55,11 +55,14 @@ def frustum_candidates(prep, cam):
 
 
 def prepare(means, log_scales, quats, opacity_logits, sh_coeffs, sh_degree, cam,
-            settings, cull=True):
+            settings, cull=True, filter_var=None):
     """Per-Gaussian float64 quantities for the renderer, restricted to the
-    Gaussians that pass the paper's culling (and the crop cull if asked)."""
+    Gaussians that pass the paper's culling (and the crop cull if asked).
+    ``filter_var``: the 3D filter's per-Gaussian variance (or None);
+    ``settings.baked``: the inputs hold activated values."""
     means = _f64(means)
-    pre = splat.prepare(means, log_scales, quats, opacity_logits, cam, settings.tau_alpha)
+    pre = splat.prepare(means, log_scales, quats, opacity_logits, cam, settings.tau_alpha,
+                        filter_var, getattr(settings, 'baked', False))
     keep = pre['visible']
     if cull:
         keep = keep & frustum_candidates(pre, cam)
@@ -85,12 +88,12 @@ def evaluate(prep: Prepared, xs, ys, settings):
 
 
 def render(means, log_scales, quats, opacity_logits, sh_coeffs, sh_degree, cam, settings,
-           cull=True, chunk=256, info=False, near_band=1e-3):
+           cull=True, chunk=256, info=False, near_band=1e-3, filter_var=None):
     """Render ``cam`` (whole window). Returns the image [3,H,W] (float64,
     differentiable w.r.t. any parameter tensor passed with requires_grad)
     and, if ``info``, per-pixel fragment records for parity checks."""
     prep = prepare(means, log_scales, quats, opacity_logits, sh_coeffs, sh_degree, cam,
-                   settings, cull)
+                   settings, cull, filter_var)
     W, H = int(cam.width), int(cam.height)
     jj, ii = torch.meshgrid(torch.arange(H, dtype=F64), torch.arange(W, dtype=F64),
                             indexing='ij')
@@ -147,6 +150,7 @@ def _merge_records(recs, n_pix):
 
 def render_scene(scene, cam, settings, **kw):
     """Convenience wrapper taking a ``scenes.Scene``-like object."""
+    kw.setdefault('filter_var', getattr(scene, 'filter_var', None))
     return render(scene.means, scene.log_scales, scene.quats, scene.opacity_logits,
                   scene.sh, scene.sh_degree, cam, settings, **kw)
 

@@ -5,6 +5,17 @@ scales, normalised quaternion); the splat-to-world matrix T and the screen
 transform T' = V P M T of Eq. (T_matrix); the opacity-aware cutoff
 rho_c = 2 ln(o / tau_alpha) and the inversion-free dual-quadric bounding box
 (s, f, p_i, h_i) of Sec. 3.2.
+
+Two input options of Sec. 4.2 and the frame-rate appendix:
+  * the 3D smoothing filter (Mip-Splatting, used by the paper in place of a
+    screen-space filter): each Gaussian's covariance gets a per-Gaussian
+    isotropic variance f added, Sigma' = Sigma + f I, and its peak opacity
+    is scaled so that the filtered density is the convolution of the
+    unfiltered one with a normalised isotropic Gaussian of variance f:
+    o' = o sqrt(det Sigma / det Sigma'). With Sigma = R diag(s^2) R^T this
+    is s'_i = sqrt(s_i^2 + f) along the same axes and o' = o prod s_i/s'_i;
+  * "baked" inputs: the activations already applied, so the arrays hold
+    the scales, unit quaternions and opacities themselves.
 """
 from __future__ import annotations
 
@@ -34,12 +45,25 @@ def quat_to_rotation(q):
     return R.reshape(q.shape[:-1] + (3, 3))
 
 
-def activations(log_scales, quats, opacity_logits):
+def activations(log_scales, quats, opacity_logits, filter_var=None, baked=False):
     """s = exp(log-scale) (log-scale -inf gives an exactly zero axis),
-    R from the normalised quaternion, o = sigmoid(logit) (Sec. 3.1)."""
-    s = torch.exp(log_scales)
+    R from the normalised quaternion, o = sigmoid(logit) (Sec. 3.1); baked
+    inputs are taken as s, R's quaternion and o directly. With the 3D
+    filter's variance f: s' = sqrt(s^2 + f), o' = o prod s / s'."""
+    if baked:
+        s, o = log_scales, opacity_logits
+    else:
+        s = torch.exp(log_scales)
+        o = torch.sigmoid(opacity_logits)
     R = quat_to_rotation(quats)
-    o = torch.sigmoid(opacity_logits)
+    if filter_var is not None:
+        f = as_f64(filter_var)
+        s_f = torch.sqrt(s * s + f[:, None])
+        # a zero axis with no filter variance keeps its opacity factor 1
+        ratio = torch.where(s_f > 0, s / torch.where(s_f > 0, s_f, torch.ones_like(s_f)),
+                            torch.ones_like(s_f))
+        o = o * torch.prod(ratio, dim=1)
+        s = s_f
     return s, R, o
 
 
@@ -108,7 +132,8 @@ def screen_bbox(Tp, rho_c):
     return s, p, h
 
 
-def prepare(means, log_scales, quats, opacity_logits, cam, tau_alpha):
+def prepare(means, log_scales, quats, opacity_logits, cam, tau_alpha, filter_var=None,
+            baked=False):
     """Per-Gaussian quantities shared by the renderer and the tile lists.
 
     Culling (the paper does not spell it out): a Gaussian is dropped when
@@ -118,7 +143,7 @@ def prepare(means, log_scales, quats, opacity_logits, cam, tau_alpha):
     finite in x or y after round-off is treated the same way."""
     means, log_scales = as_f64(means), as_f64(log_scales)
     quats, opacity_logits = as_f64(quats), as_f64(opacity_logits)
-    s_ax, R, o = activations(log_scales, quats, opacity_logits)
+    s_ax, R, o = activations(log_scales, quats, opacity_logits, filter_var, baked)
     T = splat_to_world(means, s_ax, R)
     M, P, V = camera_matrices(cam)
     MT = M @ T

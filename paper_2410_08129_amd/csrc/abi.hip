@@ -9,6 +9,7 @@
 
 namespace htgs {
 hipError_t launch_fill_zero(void *p, int64_t bytes, hipStream_t s);
+hipError_t launch_opacity_decay(float *x, int64_t n, double lambda, hipStream_t s);
 hipError_t launch_preprocess(const GaussPtrs &gp, const KCfg &cfg, const ViewSet &vs, const Ws &w,
                              hipStream_t s);
 hipError_t launch_preprocess_bwd(const GaussPtrs &gp, const GradPtrs &gr, const KCfg &cfg,
@@ -142,7 +143,7 @@ int check_cfg(const htgs_config *cfg) {
     return HTGS_E_INVAL;
   if (cfg->flags &
       ~(uint32_t)(HTGS_FLAG_COST_ORDER | HTGS_FLAG_GRAD_OVERWRITE | HTGS_FLAG_TILE_CULL |
-                  HTGS_FLAG_PERSISTENT | HTGS_FLAG_NO_TAIL))
+                  HTGS_FLAG_PERSISTENT | HTGS_FLAG_NO_TAIL | HTGS_FLAG_BAKED))
     return HTGS_E_INVAL;
   return HTGS_OK;
 }
@@ -158,6 +159,7 @@ int check_gaussians(const htgs_gaussians *g) {
   if (!aligned16(g->means) || !aligned16(g->log_scales) || !aligned16(g->quats) ||
       !aligned16(g->opacity_logits) || !aligned16(g->sh))
     return HTGS_E_INVAL;
+  if ((reinterpret_cast<uintptr_t>(g->filter_var) & 3u) != 0) return HTGS_E_INVAL;
   return HTGS_OK;
 }
 
@@ -242,11 +244,12 @@ KCfg make_kcfg(const htgs_gaussians *g, const htgs_config *cfg) {
   k.tile_cull = (cfg->flags & HTGS_FLAG_TILE_CULL) ? 1 : 0;
   k.persistent = (cfg->flags & HTGS_FLAG_PERSISTENT) ? 1 : 0;
   k.no_tail = (cfg->flags & HTGS_FLAG_NO_TAIL) ? 1 : 0;
+  k.baked = (cfg->flags & HTGS_FLAG_BAKED) ? 1 : 0;
   return k;
 }
 
 GaussPtrs make_gp(const htgs_gaussians *g) {
-  return GaussPtrs{g->means, g->log_scales, g->quats, g->opacity_logits, g->sh};
+  return GaussPtrs{g->means, g->log_scales, g->quats, g->opacity_logits, g->sh, g->filter_var};
 }
 
 int check_common(const htgs_gaussians *g, const htgs_camera *cams, int32_t n_views,
@@ -254,6 +257,8 @@ int check_common(const htgs_gaussians *g, const htgs_camera *cams, int32_t n_vie
   int e = check_cfg(cfg);
   if (e) return e;
   if ((e = check_gaussians(g))) return e;
+  // baked scales and opacities already hold any 3D filter
+  if ((cfg->flags & HTGS_FLAG_BAKED) && g->filter_var) return HTGS_E_INVAL;
   if ((e = check_cams(cams, n_views, cfg))) return e;
   if (total_tiles_of(cams, n_views, cfg) >= (1ll << 31)) return HTGS_E_KEYWIDTH;
   return HTGS_OK;
@@ -359,9 +364,12 @@ int backward_impl(const htgs_gaussians *g, const htgs_camera *cams, int32_t n_vi
   if (e) return e;
   if (!ws || !state || !grad_rgb || !grads) return HTGS_E_INVAL;
   // inference-only modes have no backward
-  if (cfg->flags & HTGS_FLAG_NO_TAIL) return HTGS_E_INVAL;
+  if (cfg->flags & (HTGS_FLAG_NO_TAIL | HTGS_FLAG_BAKED)) return HTGS_E_INVAL;
   if (!aligned16(grads->means) || !aligned16(grads->log_scales) || !aligned16(grads->quats) ||
       !aligned16(grads->opacity_logits) || !aligned16(grads->sh))
+    return HTGS_E_INVAL;
+  if (((reinterpret_cast<uintptr_t>(grads->mean_grad_stat) |
+        reinterpret_cast<uintptr_t>(grads->visible_count)) & 3u) != 0)
     return HTGS_E_INVAL;
   for (int v = 0; v < n_views; ++v)
     if (!grad_rgb[v]) return HTGS_E_INVAL;
@@ -382,7 +390,7 @@ int backward_impl(const htgs_gaussians *g, const htgs_camera *cams, int32_t n_vi
   // The preprocess backward sums the instance partials per (Gaussian, view)
   // itself.
   const GradPtrs gr{grads->means, grads->log_scales, grads->quats, grads->opacity_logits,
-                    grads->sh};
+                    grads->sh, grads->mean_grad_stat, grads->visible_count};
   StageTimer t(HTGS_STAGE_PREPROCESS_BWD, s);
   HIP_TRY(launch_preprocess_bwd(make_gp(g), gr, k, vs, w, s));
   return HTGS_OK;
@@ -395,7 +403,7 @@ using namespace htgs;
 
 extern "C" {
 
-int htgs_version(void) { return 1; }
+int htgs_version(void) { return 2; }
 
 const char *htgs_strerror(int code) {
   switch (code) {
@@ -502,6 +510,12 @@ int htgs_read_status(const void *ws, int64_t ws_bytes, uint32_t *flags_out,
   *flags_out = flags & kStatusPublic;
   if (instances_out) *instances_out = (int64_t)counts[0];
   if (fragments_out) *fragments_out = (int64_t)counts[1];
+  return HTGS_OK;
+}
+
+int htgs_opacity_decay(float *opacity_logits, int64_t n, float lambda, void *stream) {
+  if (n < 0 || (n > 0 && !opacity_logits) || !(lambda > 0.f && lambda <= 1.f)) return HTGS_E_INVAL;
+  HIP_TRY(launch_opacity_decay(opacity_logits, n, (double)lambda, static_cast<hipStream_t>(stream)));
   return HTGS_OK;
 }
 

@@ -86,15 +86,21 @@ struct KCfg {
   int32_t tile_cull;       // drop rect tiles that no fragment can reach (rects of <= 64 tiles)
   int32_t persistent;      // raster workgroups pull tiles from an atomic queue
   int32_t no_tail;         // forward leaves the tail out (inference)
+  int32_t baked;           // inputs hold scales, unit quaternions and opacities
 };
 
 struct GaussPtrs {
   const float *means, *log_scales, *quats, *logits, *sh;
+  const float *filter_var;   // 3D filter variance per Gaussian, or null
 };
 
 struct GradPtrs {
   float *means, *log_scales, *quats, *logits, *sh;
+  float *mean_grad_stat, *visible_count;   // densification sums, or null
 };
+
+// Ws::cflags bit: the Gaussian's screen box holds a pixel centre of the view.
+constexpr uint32_t kCflagVisible = 8u;
 
 // Device addresses inside the caller's workspace.
 struct Ws {
@@ -111,7 +117,8 @@ struct Ws {
   float *records;              // [views][n][32]
   int4 *rects;                 // [views][n] tile rect (tx0, ty0, tx1, ty1), empty if tx0 > tx1
   uint4 *tslots;               // [views][n] tile-slot descriptor (see below)
-  uint8_t *cflags;             // [views][n] bit c: colour channel c was clamped at 0
+  uint8_t *cflags;             // [views][n] bit c < 3: colour channel c was clamped at 0;
+                               // kCflagVisible: the pixel rect is not empty
   void *keys[2];
   uint32_t *vals[2];
   float *partials;             // [capacity][24]

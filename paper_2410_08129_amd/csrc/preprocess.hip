@@ -75,21 +75,46 @@ struct Activated {
   double mu[3], s[3], q[4], qnorm, R[3][3], o;
 };
 
-__device__ inline void activate(const GaussPtrs &gp, int64_t g, Activated &a) {
+// Unfiltered scale and opacity: the activations of Sec. 3.1, or the baked
+// values themselves.
+__device__ __forceinline__ double raw_scale(const GaussPtrs &gp, const KCfg &cfg, int64_t g,
+                                            int k) {
+  const double x = (double)gp.log_scales[3 * g + k];
+  return cfg.baked ? x : exp(x);
+}
+__device__ __forceinline__ double raw_opacity(const GaussPtrs &gp, const KCfg &cfg, int64_t g) {
+  const double x = (double)gp.logits[g];
+  return cfg.baked ? x : 1.0 / (1.0 + exp(-x));
+}
+
+// s = exp(log-scale), R from the normalised quaternion, o = sigmoid(logit)
+// (baked inputs: s, the unit quaternion and o as given). With the 3D filter
+// (variance f per Gaussian, Mip-Splatting as used in Sec. 4.2) the
+// covariance R diag(s^2) R^T gets f I added: s' = sqrt(s^2 + f) along the
+// same axes, o' = o prod s/s' (the peak of the convolved density).
+__device__ inline void activate(const GaussPtrs &gp, const KCfg &cfg, int64_t g, Activated &a) {
   for (int k = 0; k < 3; ++k) {
     a.mu[k] = (double)gp.means[3 * g + k];
-    a.s[k] = exp((double)gp.log_scales[3 * g + k]);
+    a.s[k] = raw_scale(gp, cfg, g, k);
   }
   double qq = 0.0;
   for (int k = 0; k < 4; ++k) {
     a.q[k] = (double)gp.quats[4 * g + k];
     qq += a.q[k] * a.q[k];
   }
-  a.qnorm = sqrt(qq);
+  a.qnorm = cfg.baked ? 1.0 : sqrt(qq);
   double qn[4];
   for (int k = 0; k < 4; ++k) qn[k] = a.q[k] / a.qnorm;
   quat_to_rot(qn, a.R);
-  a.o = 1.0 / (1.0 + exp(-(double)gp.logits[g]));
+  a.o = raw_opacity(gp, cfg, g);
+  if (gp.filter_var) {
+    const double f = (double)gp.filter_var[g];
+    for (int k = 0; k < 3; ++k) {
+      const double sf = sqrt(a.s[k] * a.s[k] + f);
+      a.o *= sf > 0.0 ? a.s[k] / sf : 1.0;
+      a.s[k] = sf;
+    }
+  }
 }
 
 // What the backward's view loop needs of an activated Gaussian: the mean
@@ -301,6 +326,7 @@ __device__ inline uint32_t preprocess_view(const GaussPtrs &gp, const KCfg &cfg,
   const int64_t vg = (int64_t)v * cfg.n + g;
   if (count == 0) {
     w.rects[vg] = rect;
+    w.cflags[vg] = 0u;   // not visible in this view
     *mask_out = 0ull;
     return 0;
   }
@@ -380,7 +406,7 @@ __device__ inline uint32_t preprocess_view(const GaussPtrs &gp, const KCfg &cfg,
     col[c] = acc;
   }
   dst[R_RGB / 4] = make_float4(col[0], col[1], col[2], __uint_as_float(flags));
-  w.cflags[(int64_t)v * cfg.n + g] = (uint8_t)flags;
+  w.cflags[(int64_t)v * cfg.n + g] = (uint8_t)(flags | kCflagVisible);
 
   unsigned long long mask = 0ull;
   if (cull) {
@@ -438,7 +464,7 @@ __global__ void __launch_bounds__(kPreThreads) k_preprocess(GaussPtrs gp, KCfg c
   const int lane = tid & 63, wave = tid >> 6;
   if (g < cfg.n) {
     Activated a;
-    activate(gp, g, a);
+    activate(gp, cfg, g, a);
     for (int v = 0; v < nviews; ++v) {
       uint32_t packed = 0;
       unsigned long long mk = 0ull;
@@ -805,7 +831,7 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(GaussPtrs gp, GradPtrs g
   ViewAct va;
   if (total) {
     Activated a0;
-    activate(gp, g, a0);
+    activate(gp, cfg, g, a0);
     view_act(a0, va);
   }
   // per-view terms are formed in float64 and summed over the views in
@@ -813,6 +839,9 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(GaussPtrs gp, GradPtrs g
   float gA[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
   float gmu[3] = {0, 0, 0};
   float go = 0.f;
+  // densification statistic: sum over views of |dL_v/dmu| |mu - c_v| / 2
+  float dstat = 0.f;
+  const bool want_stat = gr.mean_grad_stat != nullptr;   // uniform
   float gsh[3 * NB];
 #pragma unroll
   for (int k = 0; k < 3 * NB; ++k) gsh[k] = 0.f;
@@ -918,6 +947,7 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(GaussPtrs gp, GradPtrs g
         gm[0] += dot3(gM0, Rv[1]) - dot3(gMv, Rv[2]);
         gm[1] += dot3(gMu, Rv[2]) - dot3(gM0, Rv[0]);
         gm[2] += dot3(gMv, Rv[0]) - dot3(gMu, Rv[1]);
+        double gmv[3];   // this view's dL/dmu
         // Rv = W3 A (A = R diag(s)), mv = W3 mu + t
         for (int i = 0; i < 3; ++i) {
           for (int j = 0; j < 3; ++j) {
@@ -927,7 +957,7 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(GaussPtrs gp, GradPtrs g
           }
           double sm = 0.0;
           for (int k = 0; k < 3; ++k) sm += (double)V.w2c[4 * k + i] * gm[k];
-          gmu[i] += (float)sm;
+          gmv[i] = sm;
         }
         // Colour: SH coefficients and the viewing direction.
         const uint32_t flags = w.cflags[(int64_t)v * cfg.n + g];
@@ -942,12 +972,27 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(GaussPtrs gp, GradPtrs g
         sh_dots<NB>(shrow, gc, wsv);
         sh_backward<DEG>(wsv, dir, gc, gsh, gdir);
         const double radial = dot3(gdir, dir);
-        for (int j = 0; j < 3; ++j) gmu[j] += (float)((gdir[j] - dir[j] * radial) / dn);
+        for (int j = 0; j < 3; ++j) {
+          gmv[j] += (gdir[j] - dir[j] * radial) / dn;
+          gmu[j] += (float)gmv[j];
+        }
+        if (want_stat) dstat += (float)(sqrt(dot3(gmv, gmv)) * dn * 0.5);
       }
       __builtin_amdgcn_wave_barrier();
     }
   }
   if (!live) return;
+  if (ok) {
+    // running sums for densification: always added to (they gather over
+    // training steps), views counted where the screen box holds a pixel
+    if (want_stat) gr.mean_grad_stat[g] += dstat;
+    if (gr.visible_count) {
+      float nvis = 0.f;
+      for (int v = 0; v < nviews; ++v)
+        nvis += (w.cflags[(int64_t)v * cfg.n + g] & kCflagVisible) ? 1.f : 0.f;
+      gr.visible_count[g] += nvis;
+    }
+  }
   if (total == 0) {
     if (cfg.grad_overwrite) {
       const float z[4] = {0.f, 0.f, 0.f, 0.f};
@@ -960,13 +1005,30 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(GaussPtrs gp, GradPtrs g
   }
   // A = R diag(s): to rotation, scales and quaternion.
   Activated a;
-  activate(gp, g, a);
+  activate(gp, cfg, g, a);
   double gRot[3][3], gs[3] = {0, 0, 0};
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) {
       gRot[i][j] = gA[i][j] * a.s[j];
       gs[j] += gA[i][j] * a.R[i][j];
     }
+  // d(log-scale) and d(logit). Unfiltered: s = exp(l), o = sigmoid(x), so
+  // dL/dl = s dL/ds and dL/dx = o (1 - o) dL/do. Through the 3D filter
+  // (s' = sqrt(s^2 + f), o' = o0 prod s/s'): dL/dl_k = dL/ds'_k s_k^2 / s'_k
+  // + dL/do' o' f / s'_k^2, and dL/dx = dL/do' o' (1 - o0).
+  double gl[3], glogit;
+  if (gp.filter_var) {
+    const double f = (double)gp.filter_var[g];
+    const double o0 = raw_opacity(gp, cfg, g);
+    for (int k = 0; k < 3; ++k) {
+      const double s0 = raw_scale(gp, cfg, g, k), sf = a.s[k];
+      gl[k] = sf > 0.0 ? gs[k] * s0 * s0 / sf + (double)go * a.o * f / (sf * sf) : 0.0;
+    }
+    glogit = (double)go * a.o * (1.0 - o0);
+  } else {
+    for (int k = 0; k < 3; ++k) gl[k] = gs[k] * a.s[k];
+    glogit = (double)go * a.o * (1.0 - a.o);
+  }
   double qn[4];
   for (int k = 0; k < 4; ++k) qn[k] = a.q[k] / a.qnorm;
   double gqn[4];
@@ -976,11 +1038,35 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(GaussPtrs gp, GradPtrs g
   float fmu[3], fls[3], fq[4];
   for (int k = 0; k < 3; ++k) {
     fmu[k] = (float)gmu[k];
-    fls[k] = (float)(gs[k] * a.s[k]);
+    fls[k] = (float)gl[k];
   }
   for (int k = 0; k < 4; ++k) fq[k] = (float)((gqn[k] - qn[k] * proj) / a.qnorm);
-  emit_grads<NB>(gr, g, fmu, fls, fq, (float)(go * a.o * (1.0 - a.o)), gsh,
-                 cfg.grad_overwrite != 0);
+  emit_grads<NB>(gr, g, fmu, fls, fq, (float)glogit, gsh, cfg.grad_overwrite != 0);
+}
+
+// Opacity decay (Sec. 4.2): o <- lambda o on the logits, x' =
+// logit(lambda sigmoid(x)), in float64 from the two exact rearrangements
+// x' = log lambda - log(e^-x + 1 - lambda) (x >= 0) and
+// x' = x + log lambda - log1p((1 - lambda) e^x) (x < 0), which stay finite
+// for every finite x.
+__global__ void __launch_bounds__(256) k_opacity_decay(float *x, int64_t n, double log_lam,
+                                                        double one_minus_lam) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const double v = (double)x[i];
+    const double r = v >= 0.0 ? log_lam - log(exp(-v) + one_minus_lam)
+                              : v + log_lam - log1p(one_minus_lam * exp(v));
+    x[i] = (float)r;
+  }
+}
+
+hipError_t launch_opacity_decay(float *x, int64_t n, double lambda, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int blocks = (int)((n + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_opacity_decay, dim3(blocks), dim3(256), 0, s, x, n, log(lambda),
+                     1.0 - lambda);
+  return hipGetLastError();
 }
 
 hipError_t launch_fill_zero(void *p, int64_t bytes, hipStream_t s) {

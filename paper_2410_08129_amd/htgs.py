@@ -23,6 +23,7 @@ HTGS_FLAG_GRAD_OVERWRITE = 2
 HTGS_FLAG_TILE_CULL = 4
 HTGS_FLAG_PERSISTENT = 8
 HTGS_FLAG_NO_TAIL = 16
+HTGS_FLAG_BAKED = 32
 MAX_VIEWS = 16
 
 EXPORTED = (
@@ -30,7 +31,7 @@ EXPORTED = (
     "htgs_render_forward", "htgs_render_backward", "htgs_render_forward_batched",
     "htgs_render_backward_batched", "htgs_read_status", "htgs_debug_export_bins",
     "htgs_strerror", "htgs_version", "htgs_profile_enable", "htgs_profile_read",
-    "htgs_debug_set_spin_limit", "htgs_debug_fragment_counts",
+    "htgs_debug_set_spin_limit", "htgs_debug_fragment_counts", "htgs_opacity_decay",
 )
 STAGES = ("fill", "preprocess", "sort", "ranges", "raster_fwd", "raster_bwd", "reduce",
           "preprocess_bwd")
@@ -44,7 +45,7 @@ class Gaussians(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("sh_degree", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("means", ctypes.c_void_p), ("log_scales", ctypes.c_void_p),
                 ("quats", ctypes.c_void_p), ("opacity_logits", ctypes.c_void_p),
-                ("sh", ctypes.c_void_p)]
+                ("sh", ctypes.c_void_p), ("filter_var", ctypes.c_void_p)]
 
 
 class Camera(ctypes.Structure):
@@ -65,7 +66,8 @@ class Config(ctypes.Structure):
 class Grads(ctypes.Structure):
     _fields_ = [("means", ctypes.c_void_p), ("log_scales", ctypes.c_void_p),
                 ("quats", ctypes.c_void_p), ("opacity_logits", ctypes.c_void_p),
-                ("sh", ctypes.c_void_p)]
+                ("sh", ctypes.c_void_p), ("mean_grad_stat", ctypes.c_void_p),
+                ("visible_count", ctypes.c_void_p)]
 
 
 _lib = None
@@ -98,6 +100,7 @@ def lib():
     L.htgs_debug_export_bins.argtypes = [P(Gaussians), P(Camera), i32, P(Config), vp, i64, vp, vp,
                                          i64, vp, P(i64), vp]
     L.htgs_debug_set_spin_limit.argtypes = [i32]
+    L.htgs_opacity_decay.argtypes = [vp, i64, ctypes.c_float, vp]
     L.htgs_debug_fragment_counts.argtypes = [vp, i64, P(i64), P(i64), vp]
     L.htgs_strerror.argtypes = [ctypes.c_int]
     L.htgs_strerror.restype = ctypes.c_char_p
@@ -147,7 +150,8 @@ def config_struct(st) -> Config:
                | (HTGS_FLAG_GRAD_OVERWRITE if getattr(st, "grad_overwrite", False) else 0)
                | (HTGS_FLAG_TILE_CULL if getattr(st, "tile_cull", False) else 0)
                | (HTGS_FLAG_PERSISTENT if getattr(st, "persistent", False) else 0)
-               | (HTGS_FLAG_NO_TAIL if getattr(st, "no_tail", False) else 0))
+               | (HTGS_FLAG_NO_TAIL if getattr(st, "no_tail", False) else 0)
+               | (HTGS_FLAG_BAKED if getattr(st, "baked", False) else 0))
     return c
 
 
@@ -157,7 +161,9 @@ def _dev_f32(t: torch.Tensor, name: str) -> torch.Tensor:
     return t.contiguous()
 
 
-def gaussians_struct(means, log_scales, quats, opacity_logits, sh, sh_degree):
+def gaussians_struct(means, log_scales, quats, opacity_logits, sh, sh_degree, filter_var=None):
+    """The htgs_gaussians struct and the (contiguous) tensors it points to;
+    ``filter_var`` is the optional [n] variance of the 3D filter."""
     ts = [_dev_f32(means, "means"), _dev_f32(log_scales, "log_scales"), _dev_f32(quats, "quats"),
           _dev_f32(opacity_logits, "opacity_logits"), _dev_f32(sh, "sh")]
     n = ts[0].shape[0]
@@ -170,7 +176,19 @@ def gaussians_struct(means, log_scales, quats, opacity_logits, sh, sh_degree):
     g.n = n
     g.sh_degree = int(sh_degree)
     g.means, g.log_scales, g.quats, g.opacity_logits, g.sh = (t.data_ptr() for t in ts)
+    if filter_var is not None:
+        fv = _dev_f32(filter_var, "filter_var")
+        if tuple(fv.shape) != (n,):
+            raise HTGSError(f"filter_var has shape {tuple(fv.shape)}, expected {(n,)}")
+        g.filter_var = fv.data_ptr()
+        ts.append(fv)
     return g, ts
+
+
+def _gstruct(params, sh_degree):
+    """gaussians_struct of (means, log-scales, quats, logits, sh[, filter_var])."""
+    return gaussians_struct(*params[:5], sh_degree,
+                            filter_var=params[5] if len(params) > 5 else None)
 
 
 def stream_handle(stream=None):
@@ -199,7 +217,7 @@ def state_bytes(cams, st) -> int:
 
 
 def count_instances(params, sh_degree, cams, st, stream=None) -> int:
-    g, keep = gaussians_struct(*params, sh_degree)
+    g, keep = _gstruct(params, sh_degree)
     arr = cameras_array(cams)
     ws_b = workspace_bytes(g.n, cams, st, 0)
     ws = torch.empty(ws_b, dtype=torch.uint8, device=keep[0].device)
@@ -220,6 +238,16 @@ def read_status(ws: torch.Tensor, stream=None, fragments=False):
     if fragments:
         return flags.value, n.value, nf.value
     return flags.value, n.value
+
+
+def opacity_decay(opacity_logits: torch.Tensor, lam: float = 0.9995, stream=None):
+    """In place: logits <- logit(lam * sigmoid(logits)) (Sec. 4.2)."""
+    t = _dev_f32(opacity_logits, "opacity_logits")
+    if t.data_ptr() != opacity_logits.data_ptr():
+        raise HTGSError("opacity_logits must be contiguous")
+    check(lib().htgs_opacity_decay(ctypes.c_void_p(t.data_ptr()), t.numel(), float(lam),
+                                   stream_handle(stream)), "opacity_decay")
+    return opacity_logits
 
 
 def fragment_counts(ws: torch.Tensor, stream=None):
@@ -269,7 +297,7 @@ def forward(params, sh_degree, cams, st, ws=None, state=None, images=None, strea
             with_state=True):
     """Renders ``cams`` (a list of 1..16 cameras) into float32 [3,H,W] images.
     Sizes the workspace by counting instances first when ``ws`` is None."""
-    g, keep = gaussians_struct(*params, sh_degree)
+    g, keep = _gstruct(params, sh_degree)
     dev = keep[0].device
     if ws is None:
         ws = alloc_workspace(g.n, cams, st, count_instances(params, sh_degree, cams, st, stream), dev)
@@ -293,13 +321,20 @@ def forward(params, sh_degree, cams, st, ws=None, state=None, images=None, strea
     return Frame(ws, state, images, cams, st, sh_degree)
 
 
-def backward(params, frame: Frame, grad_images, grads=None, stream=None):
-    """Adds dL/dparams for dL/dimages into ``grads`` (zeros if None)."""
-    g, keep = gaussians_struct(*params, frame.sh_degree)
+def backward(params, frame: Frame, grad_images, grads=None, stream=None, densify=None):
+    """Adds dL/dparams for dL/dimages into ``grads`` (zeros if None);
+    ``densify``: optional ([n] mean-gradient statistic, [n] visible count)
+    float32 tensors that the densification sums are added to."""
+    g, keep = _gstruct(params, frame.sh_degree)
     if grads is None:
-        grads = [torch.zeros_like(t) for t in keep]
+        grads = [torch.zeros_like(t) for t in keep[:5]]
     gg = Grads()
     gg.means, gg.log_scales, gg.quats, gg.opacity_logits, gg.sh = (t.data_ptr() for t in grads)
+    if densify is not None:
+        stat, cnt = (_dev_f32(t, "densify") for t in densify)
+        if stat.shape != (g.n,) or cnt.shape != (g.n,):
+            raise HTGSError("densify tensors must have shape [n]")
+        gg.mean_grad_stat, gg.visible_count = stat.data_ptr(), cnt.data_ptr()
     gis = [_dev_f32(gi, "grad_rgb") for gi in grad_images]
     arr = cameras_array(frame.cams)
     cfg = config_struct(frame.st)
@@ -325,7 +360,7 @@ def export_bins(params, sh_degree, cams, st, ws, stream=None):
     """Sorted tile keys and Gaussian indices of the last forward (host numpy),
     the instance count, and view 0's tile rects."""
     import numpy as np
-    g, keep = gaussians_struct(*params, sh_degree)
+    g, keep = _gstruct(params, sh_degree)
     flags, n_inst = read_status(ws, stream)
     keys = np.zeros(max(n_inst, 1), np.uint32)
     vals = np.zeros(max(n_inst, 1), np.uint32)
@@ -376,30 +411,37 @@ def state_planes(frame: Frame, view: int = 0):
 
 class _Render(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, st, cams, sh_degree, means, log_scales, quats, opacity_logits, sh):
+    def forward(ctx, st, cams, sh_degree, filter_var, means, log_scales, quats, opacity_logits,
+                sh):
         params = (means, log_scales, quats, opacity_logits, sh)
-        frame = forward(params, sh_degree, cams, st)
+        full = params if filter_var is None else params + (filter_var,)
+        frame = forward(full, sh_degree, cams, st)
         flags, _ = read_status(frame.ws)
         if flags:
             raise HTGSError(f"render_forward status flags {flags}")
         ctx.frame = frame
+        ctx.filter_var = filter_var
         ctx.save_for_backward(*params)
         return tuple(frame.images)
 
     @staticmethod
     def backward(ctx, *grad_images):
-        params = ctx.saved_tensors
+        params = tuple(ctx.saved_tensors)
+        if ctx.filter_var is not None:
+            params = params + (ctx.filter_var,)
         gis = [gi.contiguous() if gi is not None else torch.zeros_like(im)
                for gi, im in zip(grad_images, ctx.frame.images)]
         grads = backward(params, ctx.frame, gis)
         ctx.frame = None
-        return (None, None, None, *grads)
+        return (None, None, None, None, *grads)
 
 
-def render(means, log_scales, quats, opacity_logits, sh, sh_degree, cam, settings):
+def render(means, log_scales, quats, opacity_logits, sh, sh_degree, cam, settings,
+           filter_var=None):
     """Differentiable render of one camera (or a list of up to 16 cameras,
-    returning a list of images)."""
+    returning a list of images). ``filter_var``: optional [n] variance of the
+    3D filter (an input, not differentiated)."""
     cams = cam if isinstance(cam, (list, tuple)) else [cam]
-    outs = _Render.apply(settings, list(cams), int(sh_degree), means, log_scales, quats,
-                         opacity_logits, sh)
+    outs = _Render.apply(settings, list(cams), int(sh_degree), filter_var, means, log_scales,
+                         quats, opacity_logits, sh)
     return list(outs) if isinstance(cam, (list, tuple)) else outs[0]

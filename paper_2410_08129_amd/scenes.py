@@ -98,6 +98,7 @@ class RenderSettings:
     tile_cull: bool = False     # drop box tiles that the rho_c-ellipse does not reach
     persistent: bool = False    # raster workgroups pull tiles from an atomic queue
     no_tail: bool = False       # inference without the tail (forward only)
+    baked: bool = False         # inputs hold scales, unit quaternions and opacities
 
 
 def look_at(eye, target, up_world, fov_x_deg, width, height, z_near=0.2) -> Camera:

@@ -24,7 +24,7 @@ def test_library_exports_every_declared_entry_point():
     for n in names:
         assert hasattr(L, n), n
     assert set(htgs.EXPORTED) == set(names)
-    assert L.htgs_version() == 1
+    assert L.htgs_version() == 2
 
 
 def test_strerror_codes():
@@ -159,10 +159,30 @@ def test_backward_and_batched_argument_errors():
     gr2.means = 0x2008
     assert L.htgs_render_backward(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(cfg), fake,
                                   1 << 30, fake, fake, ctypes.byref(gr2), None) == -1
-    # inference without the tail has no backward
-    nt = htgs.config_struct(scenes.RenderSettings(K=4, no_tail=True))
-    assert L.htgs_render_backward(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(nt), fake,
-                                  1 << 30, fake, fake, ctypes.byref(gr), None) == -1
+    # inference without the tail, and baked inputs, have no backward
+    for flags in (dict(no_tail=True), dict(baked=True)):
+        nt = htgs.config_struct(scenes.RenderSettings(K=4, **flags))
+        assert L.htgs_render_backward(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(nt), fake,
+                                      1 << 30, fake, fake, ctypes.byref(gr), None) == -1
+    # baked inputs already hold any 3D filter
+    gf = _fake_gaussians()
+    gf.filter_var = 0x3000
+    bk = htgs.config_struct(scenes.RenderSettings(K=4, baked=True))
+    assert L.htgs_render_forward(ctypes.byref(gf), ctypes.byref(cam), ctypes.byref(bk), fake,
+                                 1 << 30, None, fake, None) == -1
+    gf.filter_var = 0x3002     # the filter variance array must be 4-byte aligned
+    assert L.htgs_render_forward(ctypes.byref(gf), ctypes.byref(cam), ctypes.byref(cfg), fake,
+                                 1 << 30, None, fake, None) == -1
+    # densification sums must be 4-byte aligned
+    gr3 = htgs.Grads()
+    gr3.visible_count = 0x2002
+    assert L.htgs_render_backward(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(cfg), fake,
+                                  1 << 30, fake, fake, ctypes.byref(gr3), None) == -1
+    # opacity decay: lambda in (0, 1], no work for n = 0
+    assert L.htgs_opacity_decay(fake, 10, ctypes.c_float(1.5), None) == -1
+    assert L.htgs_opacity_decay(fake, 10, ctypes.c_float(0.0), None) == -1
+    assert L.htgs_opacity_decay(None, 10, ctypes.c_float(0.9), None) == -1
+    assert L.htgs_opacity_decay(None, 0, ctypes.c_float(0.9), None) == 0
     assert L.htgs_read_status(None, 0, None, None, None, None) == -1
     assert L.htgs_profile_read(None, None, 0) == -1
     n = ctypes.c_int64()
