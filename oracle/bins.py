@@ -10,6 +10,11 @@ id and value = Gaussian index; the list is ordered by key and, within a key,
 by ascending Gaussian index. The margin of a Gaussian is the smallest
 distance of its four box edges (minus 1/2) from an integer; a disagreement
 about a rect with a margin above 1e-9 is a real bug, below it a round-off tie.
+
+For sorted blending (the paper's "w/o per-pixel HT" configuration, Sec. 4.3
+and Table splat_eval) each tile's list is instead ordered front to back by
+the view depth of the Gaussians' means, as a float32 key (3DGS's order),
+ties by ascending index.
 """
 from __future__ import annotations
 
@@ -69,9 +74,17 @@ def tile_lists(means, log_scales, quats, opacity_logits, cam, settings, filter_v
     tx = trect[owner, 0] + rank % wr
     ty = trect[owner, 1] + rank // wr
     keys = ty * tiles_x + tx
-    order = np.lexsort((owner, keys))
+    zkey = None
+    if getattr(settings, 'sorted_blend', False):
+        # sorted blending: inside a tile, front to back by the float32 view
+        # depth of the means, ties by index (3DGS's per-tile order)
+        zkey = splat.mean_view_depth32(means, cam)
+        order = np.lexsort((owner, zkey[owner], keys))
+    else:
+        order = np.lexsort((owner, keys))
     counts = np.zeros(rect.shape[0], np.int64)
     counts[g] = cnt
     return dict(keys=keys[order], values=owner[order], tile_rect=trect, pixel_rect=rect,
                 nonempty=ok, margin=margin, counts=counts, tiles_x=tiles_x,
-                tiles_y=math.ceil(cam.height / th))
+                tiles_y=math.ceil(cam.height / th), depth32=zkey)
+

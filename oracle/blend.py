@@ -16,6 +16,11 @@ T_{n+1} c_bg; equal depths are ordered by ascending Gaussian index.
 Inference without the tail (Sec. 4.3, "Hybrid Transparency Ablations",
 Table ablations): the tail term is left out, so the background lies
 directly behind the core, C = sum_{i<=n} alpha_i T_i c_i + T_{n+1} c_bg.
+
+Sorted blending (``sorted_alpha``, the paper's "w/o per-pixel HT"
+configuration): no core and no tail; Eq. alpha_blending over each pixel's
+fragments in the global front-to-back order of the Gaussians' mean depths,
+with the 3DGS early stop at a transmittance threshold.
 """
 from __future__ import annotations
 
@@ -89,3 +94,49 @@ def hybrid(alpha, colour, depth, frag, K, tau_core, bg, tail=True):
                     torch.zeros_like(c_tail)) + P[:, None] * bg[None, :]
     C = core_sum + T_n1[:, None] * X
     return C, core_ids
+
+
+def sorted_alpha(alpha, colour, frag, order, tau_T, bg):
+    """Alpha blending in one global order with an early stop (Sec. 4.3,
+    "Perspectively Correct Splat Evaluation", Table splat_eval: the
+    per-pixel evaluation of Sec. 3.2 combined with the approximately
+    depth-ordered blending of 3DGS instead of hybrid transparency; Sec. 5,
+    "Limitations and Future Work": plain alpha blending may stop once the
+    transmittance falls below a preset threshold).
+
+    ``order`` [G] lists the Gaussians front to back by the view depth of
+    their means (the same order for every pixel; ties by ascending index,
+    the caller's stable sort). Per pixel, Eq. alpha_blending runs over its
+    fragments in that order; the first fragment that would bring the
+    transmittance below tau_T is left out, and so is everything after it
+    (the 3DGS rule). C = sum_blended alpha_i T_i c_i + T_end c_bg.
+
+    alpha/frag [P,G] (alpha = 0 off the fragments), colour [G,3]. Returns C
+    [P,3], the number of blended fragments per pixel and the index (into
+    the G columns) of the fragment the stop left out, -1 if none."""
+    Pn, G = alpha.shape
+    bg = torch.as_tensor(bg, dtype=F64)
+    a = alpha[:, order]
+    f = frag[:, order]
+    one_minus = 1.0 - a
+    T_incl = torch.cumprod(one_minus, dim=1)
+    T_excl = torch.cat([torch.ones((Pn, 1), dtype=F64), T_incl[:, :-1]], dim=1)
+    stop_here = f & (T_incl.detach() < tau_T)
+    # everything from the first stop on is left out
+    stopped = torch.cumsum(stop_here.to(torch.int64), dim=1) > 0
+    blended = f & ~stopped
+    w = torch.where(blended, a * T_excl, torch.zeros_like(a))
+    C = w @ colour[order]
+    # transmittance after the last blended fragment
+    T_end = torch.prod(torch.where(blended, one_minus, torch.ones_like(one_minus)), dim=1)
+    C = C + T_end[:, None] * bg[None, :]
+    first = torch.where(stop_here.any(1), stop_here.to(torch.int64).argmax(1),
+                        torch.full((Pn,), -1, dtype=torch.int64))
+    stop_col = torch.where(first >= 0, order[first.clamp(min=0)], first)
+    return C, blended.sum(1), stop_col
+
+
+def depth_order(mean_depth32):
+    """Front-to-back order of Gaussians by the float32 view depth of their
+    means, ties by ascending index (a stable sort)."""
+    return torch.sort(torch.as_tensor(mean_depth32), stable=True).indices

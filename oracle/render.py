@@ -8,6 +8,8 @@ Steps, in the paper's order:
   4. fragment iff the Gaussian is not culled, |d| > 0 and rho^2 <= rho_c;
      alpha = min(alpha_max, o exp(-rho^2 / 2))   (Eq. gauss_alpha_computation)
   5. hybrid-transparency composite                                   (blend.py)
+     (or, with settings.sorted_blend, alpha blending in the global order
+     of the means' view depths with an early stop: blend.sorted_alpha)
 
 The only thing added for speed is an optional, conservative crop cull that
 is independent of the paper's box: a Gaussian is skipped when the sphere of
@@ -91,7 +93,10 @@ def render(means, log_scales, quats, opacity_logits, sh_coeffs, sh_degree, cam, 
            cull=True, chunk=256, info=False, near_band=1e-3, filter_var=None):
     """Render ``cam`` (whole window). Returns the image [3,H,W] (float64,
     differentiable w.r.t. any parameter tensor passed with requires_grad)
-    and, if ``info``, per-pixel fragment records for parity checks."""
+    and, if ``info``, per-pixel fragment records for parity checks. The
+    info's ``core`` is [H,W,K] core Gaussian ids for hybrid transparency;
+    with sorted blending it is [H,W,2]: the number of blended fragments
+    and the id of the fragment the early stop left out (-1 if none)."""
     prep = prepare(means, log_scales, quats, opacity_logits, sh_coeffs, sh_degree, cam,
                    settings, cull, filter_var)
     W, H = int(cam.width), int(cam.height)
@@ -100,6 +105,11 @@ def render(means, log_scales, quats, opacity_logits, sh_coeffs, sh_degree, cam, 
     xs_all = (ii + 0.5).flatten()
     ys_all = (jj + 0.5).flatten()
     G = int(prep.idx.numel())
+    sorted_mode = bool(getattr(settings, 'sorted_blend', False))
+    if sorted_mode:
+        # the Gaussians front to back by the view depth of their means
+        # (float32, as a per-Gaussian sort key), ties by index
+        order = blend.depth_order(splat.mean_view_depth32(means, cam)[prep.idx.numpy()])
     outs, core_list, recs = [], [], []
     for start in range(0, H * W, chunk):
         xs = xs_all[start:start + chunk]
@@ -112,10 +122,19 @@ def render(means, log_scales, quats, opacity_logits, sh_coeffs, sh_degree, cam, 
                 recs.append(None)
             continue
         rho2, z, frag, raw, alpha = evaluate(prep, xs, ys, settings)
-        C, core = blend.hybrid(alpha, prep.colour, z, frag, settings.K, settings.tau_core,
-                               settings.bg, tail=not getattr(settings, 'no_tail', False))
+        if sorted_mode:
+            C, nb, stop = blend.sorted_alpha(alpha, prep.colour, frag, order, settings.tau_T,
+                                             settings.bg)
+            core = torch.stack([nb, stop], 1)
+        else:
+            C, core = blend.hybrid(alpha, prep.colour, z, frag, settings.K, settings.tau_core,
+                                   settings.bg, tail=not getattr(settings, 'no_tail', False))
         outs.append(C)
-        if info:
+        if info and sorted_mode:
+            gid = prep.idx[stop.clamp(min=0)]
+            core_list.append(torch.stack([nb, torch.where(stop >= 0, gid,
+                                                          torch.full_like(gid, -1))], 1))
+        elif info:
             gid = prep.idx[core.clamp(min=0)]
             core_list.append(torch.where(core >= 0, gid, torch.full_like(gid, -1)))
             band = (rho2 <= prep.rho_c[None, :] * (1.0 + near_band)) & torch.isfinite(rho2)
@@ -130,7 +149,7 @@ def render(means, log_scales, quats, opacity_logits, sh_coeffs, sh_degree, cam, 
     img = torch.cat(outs, dim=0).reshape(H, W, 3).permute(2, 0, 1)
     if not info:
         return img
-    K = max(int(settings.K), 0)
+    K = 2 if sorted_mode else max(int(settings.K), 0)
     cores = torch.cat(core_list, dim=0).reshape(H, W, -1)[..., :K] if core_list else None
     frags = _merge_records(recs, H * W)
     return img, dict(core=cores, frags=frags, n_candidates=G)

@@ -155,3 +155,15 @@ def prepare(means, log_scales, quats, opacity_logits, cam, tau_alpha, filter_var
     visible = (o > tau_alpha) & (z_view > cam.z_near) & (s_q < 0) & finite
     return dict(scales=s_ax, R=R, o=o, T=T, MT=MT, Tp=Tp, rho_c=rho_c,
                 s=s_q, p=p, h=h, visible=visible, z_view=z_view)
+
+
+def mean_view_depth32(means, cam):
+    """Sort key of sorted blending: the view depth of each mean, the third
+    row of the world-to-camera transform applied to mu in float64 (the
+    products of the float32 inputs are exact; the sum is taken x, y, z,
+    then the translation), rounded to float32. [n] numpy float32."""
+    mu = as_f64(means).detach().numpy()
+    w = as_f64(cam.world_to_cam).numpy()
+    z = ((w[2, 0] * mu[:, 0] + w[2, 1] * mu[:, 1]) + w[2, 2] * mu[:, 2]) + w[2, 3]
+    return z.astype('float32')
+

@@ -99,6 +99,8 @@ class RenderSettings:
     persistent: bool = False    # raster workgroups pull tiles from an atomic queue
     no_tail: bool = False       # inference without the tail (forward only)
     baked: bool = False         # inputs hold scales, unit quaternions and opacities
+    sorted_blend: bool = False  # alpha blending in per-tile mean-depth order instead of HT
+    tau_T: float = 1.0e-4       # sorted blending stops before transmittance drops below this
 
 
 def look_at(eye, target, up_world, fov_x_deg, width, height, z_near=0.2) -> Camera:
