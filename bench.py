@@ -93,8 +93,14 @@ def cpu_baseline(sc, cam, st, min_seconds=10.0, max_crops=64, size=64):
     dt = time.perf_counter() - t0
     per_px = dt / (n_crops * size * size)
     frame_ms = per_px * cam.width * cam.height * 1e3
+    cpu_model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu_model = next(ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
     return dict(value=frame_ms, unit="ms/frame (extrapolated)", cores=torch.get_num_threads(),
-                kind="oracle",
+                cpu_model=cpu_model, kind="oracle",
                 sample=f"{n_crops} seeded {size}x{size} crops, fwd + autograd bwd, {dt:.1f} s "
                        f"total, extrapolated by pixel count to {cam.width}x{cam.height}")
 
@@ -163,16 +169,26 @@ def run_single(args):
 
     htgs.profile_enable(True)
     htgs.profile_read()
+    # an event between steps on the stream the library launches on (the
+    # current stream) gives the per-step spread
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    evs[0].record()
+    for i in range(args.steps):
         step()
+        evs[i + 1].record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = htgs.profile_read()
     htgs.profile_enable(False)
     ms_step = (t1 - t0) * 1e3 / args.steps
-    log(f"bench: {args.steps} steps, {ms_step:.3f} ms/step")
+    per_step = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)])
+    spread = dict(median=round(float(np.median(per_step)), 4),
+                  p10=round(float(np.percentile(per_step, 10)), 4),
+                  p90=round(float(np.percentile(per_step, 90)), 4),
+                  mean=round(float(per_step.mean()), 4))
+    log(f"bench: {args.steps} steps, {ms_step:.3f} ms/step, per-step events {spread}")
 
     # Algorithmic work of the rasterizer: candidate pairs from the tile lists.
     keys, _, _, _ = htgs.export_bins(params, sc.sh_degree, [cam], st, ws)
@@ -251,6 +267,7 @@ def run_single(args):
                    "height": cam.height, "K": st.K, **settings_desc(st)},
         "roofline": roofline,
         "binning_roofline": binning,
+        "ms_per_step_events": spread,
         "stages_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in stages.items()},
         "instances": n_inst,
         "fragments": n_frag,
@@ -270,9 +287,72 @@ def run_single(args):
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = {"read": src.numel() * 4, "write": dst.numel() * 4}
         del src, dst
-    del ws, state, grads, params
+    del ws, state, grads
+    if not args.no_variants and not args.forward_only:
+        out["variants"] = run_variants(args, params, sc, cam, st, target)
+    del params
     torch.cuda.empty_cache()
     return out, (sc, cam, st)
+
+
+def run_variants(args, params, sc, cam, st0, target, steps=10, warmup=3):
+    """Other blending modes on the same frame and schedule: hybrid
+    transparency with K = 8, 16, 32 (fwd+bwd and forward only), inference
+    without the tail (forward), and sorted alpha blending with the early
+    stop (forward); each with its own workspace, timed over `steps`."""
+    import torch
+
+    from paper_2410_08129_amd import htgs
+
+    dev = params[0].device
+    out = {}
+
+    def one(name, st, backward):
+        n_inst = htgs.count_instances(params, sc.sh_degree, [cam], st)
+        ws = htgs.alloc_workspace(sc.n, [cam], st, n_inst, dev)
+        state = torch.empty(htgs.state_bytes([cam], st) // 4, dtype=torch.float32, device=dev)
+        img = torch.empty((3, cam.height, cam.width), dtype=torch.float32, device=dev)
+        gimg = torch.empty_like(img)
+        grads = [torch.zeros_like(p) for p in params]
+
+        def step():
+            fr = htgs.forward(params, sc.sh_degree, [cam], st, ws=ws, state=state, images=[img])
+            if backward:
+                torch.sub(img, target, out=gimg)
+                gimg.sign_().mul_(1.0 / img.numel())
+                htgs.backward(params, fr, [gimg], grads=grads)
+
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        flags, _, n_frag = htgs.read_status(ws, fragments=True)
+        htgs.profile_enable(True)
+        htgs.profile_read()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        prof = htgs.profile_read()
+        htgs.profile_enable(False)
+        out[name] = dict(ms_per_step=round(ms, 4), pass_="fwd+bwd" if backward else "fwd",
+                         K=st.K, instances=n_inst, fragments=n_frag, status_flags=flags,
+                         stages_ms={k: round(v[0] / steps, 4) for k, v in prof.items() if v[1]})
+        log(f"bench: variant {name}: {ms:.3f} ms")
+        del ws, state, grads
+
+    for K in (8, 16, 32):
+        st = dataclasses.replace(st0, K=K)
+        if K > 16 and st.tile_w * st.tile_h > 128:
+            st = dataclasses.replace(st, tile_w=8, tile_h=8, lds_batch=0)
+        one(f"ht_K{K}_fwd_bwd", st, True)
+        one(f"ht_K{K}_fwd", st, False)
+    one("no_tail_K8_fwd", dataclasses.replace(st0, K=8, no_tail=True, grad_overwrite=False), False)
+    one("sorted_fwd", dataclasses.replace(st0, sorted_blend=True, grad_overwrite=False), False)
+    for v in out.values():
+        v["pass"] = v.pop("pass_")
+    return out
 
 
 def run_multiview(args, steps=3, warmup=1):
@@ -390,6 +470,8 @@ def main():
                     help="fixed schedule by autotune name (e.g. tile8x8_batch1x_xcd_cull_queue)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-multiview", action="store_true")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the other blending modes (K sweep, no tail, sorted)")
     ap.add_argument("--forward-only", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB elementwise copy (reference for HBM counters)")

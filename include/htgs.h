@@ -136,7 +136,18 @@ typedef struct htgs_camera {
  *             out; the state then holds an empty tail. Forward only: the
  *             backward rejects it with HTGS_E_INVAL;
  *             HTGS_FLAG_BAKED: the parameter arrays hold activated values
- *             (see htgs_gaussians). Forward only */
+ *             (see htgs_gaussians). Forward only;
+ *             HTGS_FLAG_SORTED: sorted alpha blending instead of hybrid
+ *             transparency, the paper's "w/o per-pixel HT" configuration
+ *             (Sec. 4.3, Table splat_eval): every tile's list holds its
+ *             Gaussians front to back by the view depth of their means
+ *             (the means' view z in float64, rounded to float32; ties by
+ *             ascending index), and each pixel alpha-blends its fragments
+ *             in that order (Eq. alpha_blending), C = sum alpha_i T_i c_i +
+ *             T c_bg, leaving out the first fragment that would take T
+ *             below tau_T and everything after it (the early stop plain
+ *             alpha blending allows, Sec. 5). K and tau_core are unused.
+ *             One view per call; forward only */
 typedef struct htgs_config {
   int32_t K;
   float tau_alpha;
@@ -147,6 +158,7 @@ typedef struct htgs_config {
   int32_t tile_h;
   int32_t lds_batch;
   uint32_t flags;
+  float tau_T;       /* HTGS_FLAG_SORTED: transmittance threshold of the early stop, [0,1) */
 } htgs_config;
 
 #define HTGS_FLAG_COST_ORDER 1u
@@ -155,6 +167,7 @@ typedef struct htgs_config {
 #define HTGS_FLAG_PERSISTENT 8u
 #define HTGS_FLAG_NO_TAIL 16u
 #define HTGS_FLAG_BAKED 32u
+#define HTGS_FLAG_SORTED 64u
 
 /* Gradient outputs, same shapes as htgs_gaussians. The backward ADDS into
  * them (+=), or overwrites them with HTGS_FLAG_GRAD_OVERWRITE; any pointer
@@ -187,7 +200,12 @@ int htgs_workspace_bytes(int64_t n, const htgs_camera *cams, int32_t n_views,
                          int64_t *bytes_out);
 
 /* Bytes of the per-pixel forward state of ALL views (caller-owned, kept from
- * forward to backward): per pixel 24K+24 bytes, 6K+6 float32 values: K core
+ * forward to backward). With HTGS_FLAG_SORTED: 7 values per pixel, T after
+ * the last blended fragment, the blended colour sum (3 float32), the list
+ * position after the last blended fragment, the number of blended
+ * fragments and the index of the Gaussian the early stop left out (-1:
+ * none) (int32 each), in the tile-major layout below. Otherwise per pixel
+ * 24K+24 bytes, 6K+6 float32 values: K core
  * Gaussian ids (int32, -1 = empty, front to back), K core alphas, K core
  * positions in the pixel's tile list (int32, used by the backward), K core
  * colours (r, g, b each), T_{n+1}, tail sum of alpha, tail sum of
@@ -261,7 +279,9 @@ enum {
   HTGS_STAGE_FILL = 0, HTGS_STAGE_PREPROCESS = 1, HTGS_STAGE_SORT = 2, HTGS_STAGE_RANGES = 3,
   HTGS_STAGE_RASTER_FWD = 4, HTGS_STAGE_RASTER_BWD = 5,
   HTGS_STAGE_REDUCE = 6, /* kept for numbering; no separate reduction pass is launched */
-  HTGS_STAGE_PREPROCESS_BWD = 7, HTGS_NUM_STAGES = 8
+  HTGS_STAGE_PREPROCESS_BWD = 7,
+  HTGS_STAGE_DEPTH_SORT = 8, /* sorted blending: depth keys and their four sort passes */
+  HTGS_NUM_STAGES = 9
 };
 int htgs_profile_enable(int on);
 int htgs_profile_read(double *ms_out, int64_t *launches_out, int32_t n_stages);
@@ -281,7 +301,7 @@ int htgs_debug_export_bins(const htgs_gaussians *g, const htgs_camera *cams, int
  * reset): opacity_logits[i] <- logit(lambda * sigmoid(opacity_logits[i])),
  * in place, DEVICE pointer, n entries, 0 < lambda <= 1; computed in float64
  * and finite for every finite input. Asynchronous on stream. */
-int htgs_opacity_decay(float *opacity_logits, int64_t n, float lambda, void *stream);
+int htgs_opacity_decay(float *opacity_logits, int64_t n, double lambda, void *stream);
 
 /* Debugging and testing.
  * htgs_debug_set_spin_limit: look-back rounds (each one memory round trip
@@ -301,7 +321,7 @@ int htgs_debug_fragment_counts(const void *ws, int64_t ws_bytes, int64_t *forwar
 /* Static description of an error code. */
 const char *htgs_strerror(int code);
 
-/* ABI version, currently 2 (htgs_gaussians gained filter_var). */
+/* ABI version, currently 3 (htgs_config gained tau_T). */
 int htgs_version(void);
 
 #ifdef __cplusplus

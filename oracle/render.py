@@ -137,6 +137,7 @@ def render(means, log_scales, quats, opacity_logits, sh_coeffs, sh_degree, cam, 
         elif info:
             gid = prep.idx[core.clamp(min=0)]
             core_list.append(torch.where(core >= 0, gid, torch.full_like(gid, -1)))
+        if info:
             band = (rho2 <= prep.rho_c[None, :] * (1.0 + near_band)) & torch.isfinite(rho2)
             p_i, g_i = torch.nonzero(band, as_tuple=True)
             recs.append(dict(pix=(p_i + start).numpy(), gid=prep.idx[g_i].numpy(),

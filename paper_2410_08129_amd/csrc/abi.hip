@@ -15,6 +15,8 @@ hipError_t launch_preprocess(const GaussPtrs &gp, const KCfg &cfg, const ViewSet
 hipError_t launch_preprocess_bwd(const GaussPtrs &gp, const GradPtrs &gr, const KCfg &cfg,
                                  const ViewSet &vs, const Ws &w, hipStream_t s);
 hipError_t launch_sort_passes(const Ws &w, hipStream_t s);
+hipError_t launch_depth_sort(const Ws &w, const float *means, int64_t n, const float *w2c,
+                             hipStream_t s);
 hipError_t launch_ranges(const Ws &w, int total_tiles, hipStream_t s);
 hipError_t launch_tile_order(const Ws &w, int total_tiles, hipStream_t s);
 hipError_t launch_raster_fwd(const Ws &w, const ViewSet &vs, const KCfg &cfg, float *state,
@@ -33,10 +35,11 @@ constexpr int64_t kMaxCapacity = (1ll << 30) - 1;
 int64_t align_up(int64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  int64_t status, total, pp_look, hist, sort_look, ranges, order_hist, zero_end;
-  int64_t records, rects, tslots, cflags, order, keys0, keys1, vals0, vals1, partials, bytes;
-  int64_t capacity, max_chunks;
-  int32_t key_bits, passes, key16;
+  int64_t status, total, pp_look, hist, sort_look, ranges, order_hist, dhist, dlook, zero_end;
+  int64_t records, rects, tslots, cflags, order, keys0, keys1, vals0, vals1, partials;
+  int64_t dkeys0, dkeys1, dvals0, dvals1, bytes;
+  int64_t capacity, max_chunks, dmax_chunks;
+  int32_t key_bits, passes, key16, sorted;
 };
 
 int bits_for(int64_t tiles) {
@@ -45,24 +48,29 @@ int bits_for(int64_t tiles) {
   return b;
 }
 
-// partials = false: a forward-only layout (no backward partials).
+// partials = false: a forward-only layout (no backward partials); sorted:
+// with the depth sort of sorted blending.
 Layout make_layout(int64_t n, int n_views, int64_t total_tiles, int64_t capacity,
-                   bool partials = true) {
+                   bool partials = true, bool sorted = false) {
   Layout L{};
   L.capacity = capacity;
+  L.sorted = sorted;
+  L.dmax_chunks = sorted ? (n + kSortChunk - 1) / kSortChunk : 0;
   L.key_bits = bits_for(total_tiles);
   L.passes = (L.key_bits + 7) / 8;
   L.key16 = L.key_bits <= 16;
   L.max_chunks = (capacity + kSortChunk - 1) / kSortChunk;
   const int64_t kb = L.key16 ? 2 : 4;
   int64_t o = 0;
-  L.status = o; o = align_up(o + 64);
+  L.status = o; o = align_up(o + 4 * kStatusWords);
   L.total = o; o = align_up(o + 32);   // instances, forward and backward fragments
   L.pp_look = o; o = align_up(o + 8 * ((n + kPreThreads - 1) / kPreThreads));
   L.hist = o; o = align_up(o + 4 * 256 * 4);
   L.sort_look = o; o = align_up(o + (int64_t)L.passes * L.max_chunks * 256 * 4);
   L.ranges = o; o = align_up(o + 8 * total_tiles);
   L.order_hist = o; o = align_up(o + 2 * 32 * 4);
+  L.dhist = o; o = align_up(o + (sorted ? 4 * 256 * 4 : 0));
+  L.dlook = o; o = align_up(o + 4 * L.dmax_chunks * 256 * 4);
   L.zero_end = o;
   L.records = o; o = align_up(o + (int64_t)n_views * n * kRecFloats * 4);
   L.rects = o; o = align_up(o + (int64_t)n_views * n * 16);
@@ -74,19 +82,24 @@ Layout make_layout(int64_t n, int n_views, int64_t total_tiles, int64_t capacity
   L.vals0 = o; o = align_up(o + 4 * capacity);
   L.vals1 = o; o = align_up(o + 4 * capacity);
   L.partials = o; o = align_up(o + (partials ? (int64_t)kPartialFloats * 4 * capacity : 0));
+  const int64_t dn = sorted ? 4 * n : 0;
+  L.dkeys0 = o; o = align_up(o + dn);
+  L.dkeys1 = o; o = align_up(o + dn);
+  L.dvals0 = o; o = align_up(o + dn);
+  L.dvals1 = o; o = align_up(o + dn);
   L.bytes = o;
   return L;
 }
 
 // Largest capacity whose layout fits in ws_bytes, or -1.
 int64_t capacity_for(int64_t n, int n_views, int64_t total_tiles, int64_t ws_bytes,
-                     bool partials = true) {
-  if (make_layout(n, n_views, total_tiles, 0, partials).bytes > ws_bytes) return -1;
+                     bool partials = true, bool sorted = false) {
+  if (make_layout(n, n_views, total_tiles, 0, partials, sorted).bytes > ws_bytes) return -1;
   int64_t lo = 0, hi = kMaxCapacity;
-  if (make_layout(n, n_views, total_tiles, hi, partials).bytes <= ws_bytes) return hi;
+  if (make_layout(n, n_views, total_tiles, hi, partials, sorted).bytes <= ws_bytes) return hi;
   while (hi - lo > 1) {
     const int64_t mid = lo + (hi - lo) / 2;
-    if (make_layout(n, n_views, total_tiles, mid, partials).bytes <= ws_bytes) lo = mid;
+    if (make_layout(n, n_views, total_tiles, mid, partials, sorted).bytes <= ws_bytes) lo = mid;
     else hi = mid;
   }
   return lo;
@@ -114,6 +127,16 @@ Ws make_ws(void *base, const Layout &L) {
   w.vals[0] = reinterpret_cast<uint32_t *>(b + L.vals0);
   w.vals[1] = reinterpret_cast<uint32_t *>(b + L.vals1);
   w.partials = reinterpret_cast<float *>(b + L.partials);
+  if (L.sorted) {
+    w.dkeys[0] = reinterpret_cast<uint32_t *>(b + L.dkeys0);
+    w.dkeys[1] = reinterpret_cast<uint32_t *>(b + L.dkeys1);
+    w.dvals[0] = reinterpret_cast<uint32_t *>(b + L.dvals0);
+    w.dvals[1] = reinterpret_cast<uint32_t *>(b + L.dvals1);
+    w.dhist = reinterpret_cast<uint32_t *>(b + L.dhist);
+    w.dlook = reinterpret_cast<uint32_t *>(b + L.dlook);
+    w.perm = w.dvals[0];   // after the four depth-sort passes
+    w.dmax_chunks = L.dmax_chunks;
+  }
   w.capacity = L.capacity;
   w.max_chunks = L.max_chunks;
   w.key_bits = L.key_bits;
@@ -143,9 +166,18 @@ int check_cfg(const htgs_config *cfg) {
     return HTGS_E_INVAL;
   if (cfg->flags &
       ~(uint32_t)(HTGS_FLAG_COST_ORDER | HTGS_FLAG_GRAD_OVERWRITE | HTGS_FLAG_TILE_CULL |
-                  HTGS_FLAG_PERSISTENT | HTGS_FLAG_NO_TAIL | HTGS_FLAG_BAKED))
+                  HTGS_FLAG_PERSISTENT | HTGS_FLAG_NO_TAIL | HTGS_FLAG_BAKED | HTGS_FLAG_SORTED))
+    return HTGS_E_INVAL;
+  if ((cfg->flags & HTGS_FLAG_SORTED) && !(cfg->tau_T >= 0.f && cfg->tau_T < 1.f))
     return HTGS_E_INVAL;
   return HTGS_OK;
+}
+
+bool sorted_of(const htgs_config *cfg) { return (cfg->flags & HTGS_FLAG_SORTED) != 0; }
+
+// Forward state values per pixel.
+int state_vals(const htgs_config *cfg) {
+  return sorted_of(cfg) ? kSortedStateValues : state_values(cfg->K);
 }
 
 bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
@@ -221,7 +253,7 @@ ViewSet make_views(const htgs_camera *cams, int32_t n_views, const htgs_config *
     P.out_rgb = out_rgb ? out_rgb[v] : nullptr;
     P.grad_rgb = grad_rgb ? grad_rgb[v] : nullptr;
     tiles += (int64_t)P.tiles_x * P.tiles_y;
-    state_off += (int64_t)state_values(cfg->K) * P.tiles_x * P.tiles_y * cfg->tile_w * cfg->tile_h;
+    state_off += (int64_t)state_vals(cfg) * P.tiles_x * P.tiles_y * cfg->tile_w * cfg->tile_h;
   }
   vs.total_tiles = (int32_t)tiles;
   return vs;
@@ -245,6 +277,8 @@ KCfg make_kcfg(const htgs_gaussians *g, const htgs_config *cfg) {
   k.persistent = (cfg->flags & HTGS_FLAG_PERSISTENT) ? 1 : 0;
   k.no_tail = (cfg->flags & HTGS_FLAG_NO_TAIL) ? 1 : 0;
   k.baked = (cfg->flags & HTGS_FLAG_BAKED) ? 1 : 0;
+  k.sorted = sorted_of(cfg) ? 1 : 0;
+  k.tau_T = cfg->tau_T;
   return k;
 }
 
@@ -261,6 +295,8 @@ int check_common(const htgs_gaussians *g, const htgs_camera *cams, int32_t n_vie
   if ((cfg->flags & HTGS_FLAG_BAKED) && g->filter_var) return HTGS_E_INVAL;
   if ((e = check_cams(cams, n_views, cfg))) return e;
   if (total_tiles_of(cams, n_views, cfg) >= (1ll << 31)) return HTGS_E_KEYWIDTH;
+  // sorted blending: one view (its depth order is per view)
+  if (sorted_of(cfg) && n_views != 1) return HTGS_E_INVAL;
   return HTGS_OK;
 }
 
@@ -315,6 +351,10 @@ int run_front(const htgs_gaussians *g, const ViewSet &vs, const htgs_config *cfg
     StageTimer t(HTGS_STAGE_FILL, s, 1, timed);
     HIP_TRY(launch_fill_zero(ws, L.zero_end, s));
   }
+  if (L.sorted) {
+    StageTimer t(HTGS_STAGE_DEPTH_SORT, s, 5, timed);
+    HIP_TRY(launch_depth_sort(w, g->means, g->n, vs.v[0].w2c, s));
+  }
   {
     StageTimer t(HTGS_STAGE_PREPROCESS, s, 1, timed);
     HIP_TRY(launch_preprocess(make_gp(g), make_kcfg(g, cfg), vs, w, s));
@@ -342,9 +382,10 @@ int forward_impl(const htgs_gaussians *g, const htgs_camera *cams, int32_t n_vie
   for (int v = 0; v < n_views; ++v)
     if (!out_rgb[v]) return HTGS_E_INVAL;
   const int64_t tiles = total_tiles_of(cams, n_views, cfg);
-  const int64_t cap = capacity_for(g->n, n_views, tiles, ws_bytes, partials);
+  const bool srt = sorted_of(cfg);
+  const int64_t cap = capacity_for(g->n, n_views, tiles, ws_bytes, partials, srt);
   if (cap < 0) return HTGS_E_WORKSPACE;
-  const Layout L = make_layout(g->n, n_views, tiles, cap, partials);
+  const Layout L = make_layout(g->n, n_views, tiles, cap, partials, srt);
   const ViewSet vs = make_views(cams, n_views, cfg, out_rgb, nullptr);
   hipStream_t s = static_cast<hipStream_t>(stream);
   if ((e = run_front(g, vs, cfg, L, ws, s, true, partials))) return e;
@@ -364,7 +405,7 @@ int backward_impl(const htgs_gaussians *g, const htgs_camera *cams, int32_t n_vi
   if (e) return e;
   if (!ws || !state || !grad_rgb || !grads) return HTGS_E_INVAL;
   // inference-only modes have no backward
-  if (cfg->flags & (HTGS_FLAG_NO_TAIL | HTGS_FLAG_BAKED)) return HTGS_E_INVAL;
+  if (cfg->flags & (HTGS_FLAG_NO_TAIL | HTGS_FLAG_BAKED | HTGS_FLAG_SORTED)) return HTGS_E_INVAL;
   if (!aligned16(grads->means) || !aligned16(grads->log_scales) || !aligned16(grads->quats) ||
       !aligned16(grads->opacity_logits) || !aligned16(grads->sh))
     return HTGS_E_INVAL;
@@ -403,7 +444,7 @@ using namespace htgs;
 
 extern "C" {
 
-int htgs_version(void) { return 2; }
+int htgs_version(void) { return 3; }
 
 const char *htgs_strerror(int code) {
   switch (code) {
@@ -424,7 +465,8 @@ int htgs_workspace_bytes(int64_t n, const htgs_camera *cams, int32_t n_views,
   if (e) return e;
   if (!bytes_out || n < 0 || max_instances < 0 || max_instances > kMaxCapacity) return HTGS_E_INVAL;
   if ((e = check_cams(cams, n_views, cfg))) return e;
-  *bytes_out = make_layout(n, n_views, total_tiles_of(cams, n_views, cfg), max_instances).bytes;
+  *bytes_out = make_layout(n, n_views, total_tiles_of(cams, n_views, cfg), max_instances, true,
+                           sorted_of(cfg)).bytes;
   return HTGS_OK;
 }
 
@@ -438,7 +480,7 @@ int htgs_state_bytes(const htgs_camera *cams, int32_t n_views, const htgs_config
   for (int v = 0; v < n_views; ++v) {
     const int64_t tx = (cams[v].width + cfg->tile_w - 1) / cfg->tile_w;
     const int64_t ty = (cams[v].height + cfg->tile_h - 1) / cfg->tile_h;
-    b += (int64_t)4 * state_values(cfg->K) * tx * ty * cfg->tile_w * cfg->tile_h;
+    b += (int64_t)4 * state_vals(cfg) * tx * ty * cfg->tile_w * cfg->tile_h;
   }
   *bytes_out = b;
   return HTGS_OK;
@@ -451,10 +493,10 @@ int htgs_count_instances(const htgs_gaussians *g, const htgs_camera *cams, int32
   if (e) return e;
   if (!ws || !instances_out) return HTGS_E_INVAL;
   const int64_t tiles = total_tiles_of(cams, n_views, cfg);
-  const int64_t cap = capacity_for(g->n, n_views, tiles, ws_bytes);
+  const int64_t cap = capacity_for(g->n, n_views, tiles, ws_bytes, true, sorted_of(cfg));
   if (cap < 0) return HTGS_E_WORKSPACE;
   // Count with capacity 0: nothing is emitted, the scan still runs.
-  const Layout L0 = make_layout(g->n, n_views, tiles, 0);
+  const Layout L0 = make_layout(g->n, n_views, tiles, 0, true, sorted_of(cfg));
   const ViewSet vs = make_views(cams, n_views, cfg, nullptr, nullptr);
   hipStream_t s = static_cast<hipStream_t>(stream);
   if ((e = run_front(g, vs, cfg, L0, ws, s, false))) return e;
@@ -496,7 +538,7 @@ int htgs_render_backward_batched(const htgs_gaussians *g, const htgs_camera *cam
 
 int htgs_read_status(const void *ws, int64_t ws_bytes, uint32_t *flags_out,
                      int64_t *instances_out, int64_t *fragments_out, void *stream) {
-  if (!ws || !flags_out || ws_bytes < 512) return HTGS_E_INVAL;
+  if (!ws || !flags_out || ws_bytes < make_layout(0, 1, 1, 0).total + 24) return HTGS_E_INVAL;
   hipStream_t s = static_cast<hipStream_t>(stream);
   uint32_t flags = 0;
   unsigned long long counts[2] = {0, 0};
@@ -513,9 +555,9 @@ int htgs_read_status(const void *ws, int64_t ws_bytes, uint32_t *flags_out,
   return HTGS_OK;
 }
 
-int htgs_opacity_decay(float *opacity_logits, int64_t n, float lambda, void *stream) {
-  if (n < 0 || (n > 0 && !opacity_logits) || !(lambda > 0.f && lambda <= 1.f)) return HTGS_E_INVAL;
-  HIP_TRY(launch_opacity_decay(opacity_logits, n, (double)lambda, static_cast<hipStream_t>(stream)));
+int htgs_opacity_decay(float *opacity_logits, int64_t n, double lambda, void *stream) {
+  if (n < 0 || (n > 0 && !opacity_logits) || !(lambda > 0.0 && lambda <= 1.0)) return HTGS_E_INVAL;
+  HIP_TRY(launch_opacity_decay(opacity_logits, n, lambda, static_cast<hipStream_t>(stream)));
   return HTGS_OK;
 }
 
@@ -526,7 +568,8 @@ int htgs_debug_set_spin_limit(int32_t limit) {
 
 int htgs_debug_fragment_counts(const void *ws, int64_t ws_bytes, int64_t *forward_out,
                                int64_t *backward_out, void *stream) {
-  if (!ws || !forward_out || !backward_out || ws_bytes < 512) return HTGS_E_INVAL;
+  if (!ws || !forward_out || !backward_out || ws_bytes < make_layout(0, 1, 1, 0).total + 24)
+    return HTGS_E_INVAL;
   hipStream_t s = static_cast<hipStream_t>(stream);
   unsigned long long counts[3] = {0, 0, 0};
   const Layout L = make_layout(0, 1, 1, 0);
@@ -578,9 +621,9 @@ int htgs_debug_export_bins(const htgs_gaussians *g, const htgs_camera *cams, int
   if (e) return e;
   if (!ws || !keys_out || !values_out || !instances_out || max_out < 0) return HTGS_E_INVAL;
   const int64_t tiles = total_tiles_of(cams, n_views, cfg);
-  const int64_t cap = capacity_for(g->n, n_views, tiles, ws_bytes);
+  const int64_t cap = capacity_for(g->n, n_views, tiles, ws_bytes, true, sorted_of(cfg));
   if (cap < 0) return HTGS_E_WORKSPACE;
-  const Layout L = make_layout(g->n, n_views, tiles, cap);
+  const Layout L = make_layout(g->n, n_views, tiles, cap, true, sorted_of(cfg));
   const char *b = static_cast<const char *>(ws);
   hipStream_t s = static_cast<hipStream_t>(stream);
   unsigned long long total = 0;

@@ -87,6 +87,8 @@ struct KCfg {
   int32_t persistent;      // raster workgroups pull tiles from an atomic queue
   int32_t no_tail;         // forward leaves the tail out (inference)
   int32_t baked;           // inputs hold scales, unit quaternions and opacities
+  int32_t sorted;          // alpha blending in mean-depth order with an early stop
+  float tau_T;             // sorted blending stops before T falls below this
 };
 
 struct GaussPtrs {
@@ -104,7 +106,7 @@ constexpr uint32_t kCflagVisible = 8u;
 
 // Device addresses inside the caller's workspace.
 struct Ws {
-  uint32_t *status;            // [0] flags, [1] preprocess ticket, [2..5] sort tickets
+  uint32_t *status;            // [kStatusWords]: flags, tickets, raster queues (see below)
   unsigned long long *total;   // instance count (64-bit)
   unsigned long long *frags;   // fragments counted by the forward raster
   unsigned long long *frags_bwd;  // fragments counted by the backward raster
@@ -122,6 +124,15 @@ struct Ws {
   void *keys[2];
   uint32_t *vals[2];
   float *partials;             // [capacity][24]
+  // Sorted blending: the Gaussians' mean-depth sort keys, sorted (key,
+  // index) pairs (ping-pong; the final index buffer is the order the
+  // preprocess walks), its digit histograms and look-back words.
+  uint32_t *dkeys[2];
+  uint32_t *dvals[2];
+  uint32_t *dhist;             // [4][256]
+  uint32_t *dlook;             // [4][dmax_chunks][256]
+  const uint32_t *perm;        // Gaussians front to back (null: index order)
+  int64_t dmax_chunks;
   int64_t capacity;
   int64_t max_chunks;
   int32_t key_bits, passes, key16;
@@ -137,6 +148,11 @@ constexpr int kSpinLimit = 1 << 22;   // default look-back rounds before giving 
 // Forward state values per pixel: K ids, K alphas, K list positions, K rgb
 // triples, T, sum alpha, sum alpha rgb (3), prod (1 - alpha).
 __host__ __device__ constexpr int state_values(int K) { return 6 * K + 6; }
+// Sorted blending's state per pixel: T after the last blended fragment, the
+// blended colour sum (3), the list position after the last blended
+// fragment, the number of blended fragments, the Gaussian the early stop
+// left out (-1: none).
+constexpr int kSortedStateValues = 7;
 
 constexpr int kLookWindow = 4;   // look-back words read per round trip
 
@@ -145,13 +161,27 @@ constexpr int kLookWindow = 4;   // look-back words read per round trip
 // a later launch can tell a give-up of an earlier launch (whose outputs it
 // must not trust) from one of its own concurrent workgroups.
 enum StatusBits : uint32_t {
-  ST_OVERFLOW = 1u, ST_SPIN = 2u, ST_SPIN_PRE = 1u << 8, ST_SPIN_SORT0 = 1u << 9
+  ST_OVERFLOW = 1u, ST_SPIN = 2u, ST_SPIN_PRE = 1u << 8, ST_SPIN_SORT0 = 1u << 9,
+  ST_SPIN_DSORT0 = 1u << 16   // depth sort pass p of sorted blending: bit 16 + p
 };
 constexpr uint32_t kStatusPublic = ST_OVERFLOW | ST_SPIN;
+constexpr uint32_t kSpinDsortAll = 15u << 16;
 // give-up bits of the stages before sort pass p
 __host__ __device__ constexpr uint32_t spin_bits_before_sort(int p) {
-  return ST_SPIN_PRE | (((1u << p) - 1u) << 9);
+  return kSpinDsortAll | ST_SPIN_PRE | (((1u << p) - 1u) << 9);
 }
+// give-up bits of the depth-sort passes before pass p
+__host__ __device__ constexpr uint32_t spin_bits_before_dsort(int p) {
+  return ((1u << p) - 1u) << 16;
+}
+// Status words (512 bytes, four 128-byte cache lines). The flags word has a
+// line of its own: every workgroup of the later stages reads it, and when
+// it shared a line with the tickets that each workgroup increments, the
+// reads queued behind the atomics (a sort pass took 30% longer). [0]
+// flags; [32] preprocess ticket, [33..36] sort tickets, [37..40] depth-sort
+// tickets; [64..67] / [68..71] the raster queues.
+constexpr int kStatusWords = 128;
+constexpr int kTicketPre = 32, kTicketSort = 33, kDsortTicket = 37;
 // outputs of the front end are unusable: overflow or any give-up
 __device__ __forceinline__ bool front_failed(const Ws &w) {
   return (__hip_atomic_load(&w.status[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
@@ -159,7 +189,7 @@ __device__ __forceinline__ bool front_failed(const Ws &w) {
 }
 // status words of the persistent raster queues (16-byte aligned, cleared
 // before each raster launch)
-constexpr int kQueueFwd = 8, kQueueBwd = 12;
+constexpr int kQueueFwd = 64, kQueueBwd = 68;
 
 __device__ __forceinline__ uint32_t ld_acq_u32(const uint32_t *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -449,11 +449,26 @@ __global__ void __launch_bounds__(kPreThreads) k_preprocess(GaussPtrs gp, KCfg c
   __shared__ unsigned long long s_base;
 
   const int tid = threadIdx.x;
-  if (tid == 0) s_ticket = atomicAdd(&w.status[1], 1u);
+  if (tid == 0) s_ticket = atomicAdd(&w.status[kTicketPre], 1u);
   for (int i = tid; i < 4 * 256; i += kPreThreads) (&s_hist[0][0])[i] = 0u;
   __syncthreads();
   const int64_t blk = s_ticket;
-  const int64_t g = blk * kPreThreads + tid;
+  // Position tid of the workgroup holds Gaussian g: the index itself, or,
+  // for sorted blending, the Gaussian at that place of the front-to-back
+  // order (so instances are emitted in that order, and the stable tile sort
+  // keeps it inside each tile). A give-up of the depth sort leaves no usable
+  // order: every Gaussian is then treated as culled.
+  const int64_t pos = blk * kPreThreads + tid;
+  int64_t g = pos;
+  bool live = pos < cfg.n;
+  if (w.perm) {
+    live = live && (ld_acq_u32(&w.status[0]) & kSpinDsortAll) == 0u;
+    const uint32_t x = live ? w.perm[pos] : 0xffffffffu;
+    live = live && (int64_t)x < cfg.n;
+    g = live ? (int64_t)x : pos;
+  }
+  __shared__ uint32_t s_gidx[kPreThreads];
+  s_gidx[tid] = (uint32_t)g;
   const int nviews = MV ? vs.n : 1;
 
   // Slot layout: the workgroup's 64-Gaussian groups (one per wave) in
@@ -462,7 +477,7 @@ __global__ void __launch_bounds__(kPreThreads) k_preprocess(GaussPtrs gp, KCfg c
   // relative first slot of every (group, view, lane), in slot order, plus
   // the workgroup total at the end; it first holds the counts.
   const int lane = tid & 63, wave = tid >> 6;
-  if (g < cfg.n) {
+  if (live) {
     Activated a;
     activate(gp, cfg, g, a);
     for (int v = 0; v < nviews; ++v) {
@@ -527,7 +542,7 @@ __global__ void __launch_bounds__(kPreThreads) k_preprocess(GaussPtrs gp, KCfg c
     const int grp = lo / (64 * nviews);
     const int v = MV ? (lo >> 6) - grp * nviews : 0;
     const int owner = grp * 64 + (lo & 63);
-    gid = (uint32_t)(blk * kPreThreads + owner);
+    gid = w.perm ? s_gidx[owner] : (uint32_t)(blk * kPreThreads + owner);
     const uint32_t pr = s_vrect[v][owner];
     const uint32_t rw = pr >> 20;
     // With a tile mask, the rank-th surviving tile is the rank-th set bit.
@@ -617,7 +632,7 @@ __global__ void __launch_bounds__(kPreThreads) k_preprocess(GaussPtrs gp, KCfg c
   }
   __syncthreads();
   const unsigned long long base = s_base;
-  if (g < cfg.n) {
+  if (live) {
     // Tile-slot descriptors: first slot of each (view, Gaussian), clamped
     // at 2^31 so that base + rank cannot wrap (slots at or past the
     // capacity are never written).

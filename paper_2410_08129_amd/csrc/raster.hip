@@ -592,6 +592,150 @@ __device__ __forceinline__ void fwd_tile(const TileInfo &ti, const Ws &w, const 
 }
 
 // ---------------------------------------------------------------------------
+// Forward, sorted blending
+// ---------------------------------------------------------------------------
+// The paper's "w/o per-pixel HT" configuration (Sec. 4.3, Table splat_eval):
+// the per-pixel evaluation of Sec. 3.2 with plain alpha blending (Eq.
+// alpha_blending) in the order of the tile's list, which the front end has
+// sorted front to back by the view depth of the Gaussians' means. A pixel
+// stops before the fragment that would take its transmittance below tau_T
+// (the early stop plain alpha blending allows, Sec. 5), and the workgroup
+// stops staging batches once every pixel of its tile has stopped.
+template <int TW, int TH>
+__device__ __forceinline__ void fwd_tile_sorted(const TileInfo &ti, const Ws &w,
+                                                const ViewSet &vs, const KCfg &cfg,
+                                                float *__restrict__ state,
+                                                const uint32_t *__restrict__ vals) {
+  constexpr int NT = TW * TH;
+  constexpr int NW = NT / 64;
+  constexpr int BX = TW / 8;
+  constexpr int SV = F_FLOATS / 4;
+  __shared__ float4 s_stage[NT * SV];
+  __shared__ uint16_t s_list[NW][NT];
+  __shared__ uint32_t s_nfrag;
+
+  const ViewParams &V = vs.v[ti.v];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int bx = (wave % BX) * 8, by = (wave / BX) * 8;
+  const int lx = bx + (lane & 7), ly = by + (lane >> 3);
+  const int px0 = ti.tx * TW, py0 = ti.ty * TH;
+  const int px = px0 + lx, py = py0 + ly;
+  const bool inside = (px < V.width) && (py < V.height);
+  const uint2 rg = front_failed(w) ? make_uint2(0u, 0u) : w.ranges[ti.t];
+  PixQ u;
+  u.x = (float)lx - 0.5f * (float)(TW - 1);
+  u.y = (float)ly - 0.5f * (float)(TH - 1);
+  u.xx = u.x * u.x; u.xy = u.x * u.y; u.yy = u.y * u.y;
+  const int cx2 = 2 * px0 + TW - 1, cy2 = 2 * py0 + TH - 1;
+  const float amax = cfg.alpha_max, tau_T = cfg.tau_T;
+  const float *recs = w.records + (int64_t)ti.v * cfg.n * kRecFloats;
+  const uint64_t lanemask_lt = (1ull << lane) - 1ull;
+
+  float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
+  bool done = !inside;
+  int nb = 0, end_pos = 0, stop_pos = -1;
+  if (tid == 0) s_nfrag = 0u;
+
+  for (uint32_t base = rg.x; base < rg.y; base += NT) {
+    // (also the barrier before the stage is overwritten)
+    if (__syncthreads_and(done)) break;
+    const int cnt = (int)min((uint32_t)NT, rg.y - base);
+    if (tid < cnt) {
+      const uint32_t gid = vals[base + tid];
+      float rec[kRecFloats];
+      load_record(recs, gid, rec);
+      float st[F_FLOATS];
+      stage_fwd(rec, cx2, cy2, st);
+      const uint32_t b0 = __float_as_uint(rec[R_BB0]), b1 = __float_as_uint(rec[R_BB1]);
+      st[F_BB + 0] = __int_as_float((int)(b0 & 0xffffu) - px0);
+      st[F_BB + 1] = __int_as_float((int)(b0 >> 16) - py0);
+      st[F_BB + 2] = __int_as_float((int)(b1 & 0xffffu) - px0);
+      st[F_BB + 3] = __int_as_float((int)(b1 >> 16) - py0);
+#pragma unroll
+      for (int k = 0; k < SV; ++k)
+        s_stage[tid * SV + k] = make_float4(st[4 * k], st[4 * k + 1], st[4 * k + 2], st[4 * k + 3]);
+    }
+    __syncthreads();
+    int nlist = cnt;
+    if constexpr (NW > 1) {
+      nlist = 0;
+      for (int j0 = 0; j0 < cnt; j0 += 64) {
+        const int j = j0 + lane;
+        bool hit = false;
+        if (j < cnt) {
+          const float4 b = s_stage[j * SV + F_BB / 4];
+          const float bb[4] = {b.x, b.y, b.z, b.w};
+          hit = rect_meets_block(bb, bx, by);
+        }
+        const uint64_t mk = __ballot(hit);
+        if (hit) s_list[wave][nlist + __popcll(mk & lanemask_lt)] = (uint16_t)j;
+        nlist += __popcll(mk);
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+    if (done) continue;
+    for (int q = 0; q < nlist; ++q) {
+      int j = q;
+      if constexpr (NW > 1) j = s_list[wave][q];
+      float e[4 * F_TEST4];
+#pragma unroll
+      for (int k = 0; k < F_TEST4; ++k) {
+        const float4 t = s_stage[j * SV + k];
+        e[4 * k] = t.x; e[4 * k + 1] = t.y; e[4 * k + 2] = t.z; e[4 * k + 3] = t.w;
+      }
+      const float dd = eval_dd(e + F_QD, u);
+      const float mm = eval_mm(e + F_QM, u);
+      if (!is_fragment(dd, mm, e[F_RC])) continue;
+      const float alpha = frag_alpha(e[F_O], mm, rcp_fast(dd), amax);
+      const float tn = T * (1.f - alpha);
+      const int pos = (int)(base - rg.x) + j;
+      if (tn < tau_T) {
+        done = true;
+        stop_pos = pos;
+        break;
+      }
+      const float4 f5 = s_stage[j * SV + F_QZ / 4 + 1];   // qz4, qz5, g, b
+      const float wgt = alpha * T;
+      C0 = fmaf(wgt, e[F_R], C0);
+      C1 = fmaf(wgt, f5.z, C1);
+      C2 = fmaf(wgt, f5.w, C2);
+      T = tn;
+      ++nb;
+      end_pos = pos + 1;
+    }
+  }
+  __syncthreads();
+  if (nb) atomicAdd(&s_nfrag, (uint32_t)nb);
+  __syncthreads();
+  if (tid == 0 && s_nfrag) atomicAdd(w.frags, (unsigned long long)s_nfrag);
+  if (!inside) return;
+  const int64_t npix = (int64_t)V.width * V.height;
+  const int64_t pix = (int64_t)py * V.width + px;
+  V.out_rgb[pix] = fmaf(T, cfg.bg[0], C0);
+  V.out_rgb[npix + pix] = fmaf(T, cfg.bg[1], C1);
+  V.out_rgb[2 * npix + pix] = fmaf(T, cfg.bg[2], C2);
+  if (state) {
+    float *sp = state + tile_state_off(V, ti, kSortedStateValues, NT) + wave * 64 + lane;
+    sp[0] = T;
+    sp[NT] = C0;
+    sp[2 * NT] = C1;
+    sp[3 * NT] = C2;
+    sp[4 * NT] = __int_as_float(end_pos);
+    sp[5 * NT] = __int_as_float(nb);
+    sp[6 * NT] = __int_as_float(stop_pos >= 0 ? (int)vals[rg.x + (uint32_t)stop_pos] : -1);
+  }
+}
+
+template <int TW, int TH, bool PERSIST>
+__global__ void __launch_bounds__(TW * TH)
+    k_raster_fwd_sorted(Ws w, ViewSet vs, KCfg cfg, float *__restrict__ state,
+                        const uint32_t *__restrict__ vals) {
+#define HTGS_FWDS_BODY(T) fwd_tile_sorted<TW, TH>(T, w, vs, cfg, state, vals)
+  HTGS_FOR_TILES(PERSIST, kQueueFwd, HTGS_FWDS_BODY);
+#undef HTGS_FWDS_BODY
+}
+
+// ---------------------------------------------------------------------------
 // Backward
 // ---------------------------------------------------------------------------
 template <int KMAX>
@@ -875,20 +1019,30 @@ __device__ __forceinline__ void bwd_tile(const TileInfo &ti, const Ws &w, const 
         const float s2 = fmaf(qm[4], Y, qm[5]);
         const float rm0 = fmaf(s2, s2, qm[0]);
         const float rm1 = fmaf(qm[2], Y, qm[3]);
-        const bool row_in = hitb && row < rows_in;
+        // (bitwise ands: both pixels of a column pair are tested before
+        // either fragment path branches, and no test branches on its own)
+        const bool row_in = hitb & (row < rows_in);
         float rs[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int col = 0; col < 8; ++col) {
-          const float X = (fbx + (float)col) - hx, XX = X * X;
-          const float dd = fmaf(X, rd1, fmaf(XX, qd[3], rd0));
-          const float s1 = fmaf(qm[1], X, rm1);
-          const float mm = fmaf(s1, s1, rm0);
-          const bool f = row_in && col < cols_in && is_fragment(dd, mm, rc);
-          if (f) {
+        for (int col = 0; col < 8; col += 2) {
+          const float X0 = (fbx + (float)col) - hx, X1 = X0 + 1.f;
+          const float dd0 = fmaf(X0, rd1, fmaf(X0 * X0, qd[3], rd0));
+          const float dd1 = fmaf(X1, rd1, fmaf(X1 * X1, qd[3], rd0));
+          const float s10 = fmaf(qm[1], X0, rm1), s11 = fmaf(qm[1], X1, rm1);
+          const float mm0 = fmaf(s10, s10, rm0), mm1 = fmaf(s11, s11, rm0);
+          const bool f0 = row_in & (col < cols_in) & (dd0 >= FLT_MIN) & (mm0 <= rc * dd0);
+          const bool f1 = row_in & (col + 1 < cols_in) & (dd1 >= FLT_MIN) & (mm1 <= rc * dd1);
+          const int q = row * 8 + col;
+          const float *P0 = sp_all + ((by + row) * TW + bx + col) * L::kStride;
+          if (f0) {
             ++nfr;
-            const int q = row * 8 + col;
-            bwd_fragment<KMAX>(op, rgb, sp_all + ((by + row) * TW + bx + col) * L::kStride, col,
-                               dd, mm, (int)s_slot[wave][q][lane] - 1, amax, rs, acc);
+            bwd_fragment<KMAX>(op, rgb, P0, col, dd0, mm0, (int)s_slot[wave][q][lane] - 1, amax,
+                               rs, acc);
+          }
+          if (f1) {
+            ++nfr;
+            bwd_fragment<KMAX>(op, rgb, P0 + L::kStride, col + 1, dd1, mm1,
+                               (int)s_slot[wave][q + 1][lane] - 1, amax, rs, acc);
           }
         }
         if constexpr (BX > 1) {
@@ -1008,14 +1162,11 @@ __global__ void __launch_bounds__((64 * bwd_waves<TW, TH>()), (bwd_simd_waves<KM
 #define HTGS_BWD_BODY(T) bwd_tile<KMAX, TW, TH, EXACT>(T, w, vs, cfg, state, vals, nfr)
   HTGS_FOR_TILES(PERSIST, kQueueBwd, HTGS_BWD_BODY);
 #undef HTGS_BWD_BODY
-  // one atomic per workgroup
-  __shared__ uint32_t s_nfr;
-  __syncthreads();
-  if (threadIdx.x == 0) s_nfr = 0u;
-  __syncthreads();
-  if (nfr) atomicAdd(&s_nfr, nfr);
-  __syncthreads();
-  if (threadIdx.x == 0 && s_nfr) atomicAdd(w.frags_bwd, (unsigned long long)s_nfr);
+  // one atomic per wave (a word of LDS would take the 8x8 and 16x8 kernels
+  // past 16 and 32 KiB, one workgroup per CU fewer)
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) nfr += (uint32_t)__shfl_xor((int)nfr, off, 64);
+  if ((threadIdx.x & 63) == 0 && nfr) atomicAdd(w.frags_bwd, (unsigned long long)nfr);
 }
 
 // ---------------------------------------------------------------------------
@@ -1128,8 +1279,29 @@ int kmax_for(int K) {
     }                                                                            \
   } while (0)
 
+template <int TW, int TH>
+static hipError_t fwd_sorted_launch(const Ws &w, const ViewSet &vs, const KCfg &cfg, float *state,
+                                    const uint32_t *vals, hipStream_t s) {
+  if (cfg.persistent) {
+    auto *kern = k_raster_fwd_sorted<TW, TH, true>;
+    const int blocks = resident_blocks((const void *)kern, TW * TH, vs.total_tiles);
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(TW * TH), 0, s, w, vs, cfg, state, vals);
+  } else {
+    auto *kern = k_raster_fwd_sorted<TW, TH, false>;
+    const int blocks = 8 * ((vs.total_tiles + 7) / 8);
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(TW * TH), 0, s, w, vs, cfg, state, vals);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_raster_fwd(const Ws &w, const ViewSet &vs, const KCfg &cfg, float *state,
                              const uint32_t *vals, hipStream_t s) {
+  if (cfg.sorted) {
+    if (cfg.tile_w == 8 && cfg.tile_h == 8) return fwd_sorted_launch<8, 8>(w, vs, cfg, state, vals, s);
+    if (cfg.tile_w == 16 && cfg.tile_h == 8) return fwd_sorted_launch<16, 8>(w, vs, cfg, state, vals, s);
+    if (cfg.tile_w == 32 && cfg.tile_h == 8) return fwd_sorted_launch<32, 8>(w, vs, cfg, state, vals, s);
+    return fwd_sorted_launch<16, 16>(w, vs, cfg, state, vals, s);
+  }
   HTGS_DISPATCH(fwd_launch, w, vs, cfg, state, vals, s);
 }
 

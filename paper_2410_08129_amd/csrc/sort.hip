@@ -1,5 +1,8 @@
 // Stable LSD radix sort of the (tile key, Gaussian index) instances and the
-// per-tile ranges (Sec. 4.3: plain tile-id keys, no depth sort).
+// per-tile ranges (Sec. 4.3: plain tile-id keys, no depth sort). The same
+// pass kernel sorts the Gaussians by the view depth of their means for
+// sorted blending (the 3DGS order that the paper's "w/o per-pixel HT"
+// configuration blends in, Sec. 4.3, Table splat_eval).
 //
 // One launch per 8-bit digit. Each workgroup takes a chunk of 4096 keys (in
 // ticket order), ranks them stably inside each 64-lane wave with ballots
@@ -17,8 +20,27 @@ namespace htgs {
 
 constexpr int kSortWaves = kSortThreads / 64;
 
+// What one sort pass works on: the item count (a device word, or a fixed
+// number), the capacity beyond which nothing is sorted, the global digit
+// histograms, look-back words and tickets of its passes, and the status
+// bits that cancel a pass (a give-up of an earlier stage) or that a give-up
+// of this pass sets.
+struct SortJob {
+  const unsigned long long *count;  // null: n_fixed items
+  uint64_t n_fixed;
+  int64_t capacity;
+  const uint32_t *hist;             // [passes][256]
+  uint32_t *look;                   // [passes][max_chunks][256]
+  uint32_t *tickets;                // one per pass
+  uint32_t *status;
+  int64_t max_chunks;
+  uint32_t cancel[4];               // per pass
+  uint32_t spin[4];                 // per pass
+  int32_t spin_limit;
+};
+
 template <typename KeyT>
-__global__ void __launch_bounds__(kSortThreads) k_sort_pass(Ws w, int pass, int nbits,
+__global__ void __launch_bounds__(kSortThreads) k_sort_pass(SortJob job, int pass, int nbits,
                                                              const KeyT *__restrict__ kin,
                                                              const uint32_t *__restrict__ vin,
                                                              KeyT *__restrict__ kout,
@@ -33,21 +55,21 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_pass(Ws w, int pass, int 
   __shared__ uint32_t s_val[kSortChunk];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const unsigned long long tot = *w.total;
+  const unsigned long long tot = job.count ? *job.count : job.n_fixed;
   // On overflow only part of the keys exist while the histograms count all
   // of them; after a give-up of the preprocess or an earlier pass the keys
   // (and their slots) are not the counted ones. Nothing is sorted then, and
   // the status word reports why. (A give-up inside this pass only moves
   // positions down within [0, I): every later launch sees its flag.)
-  if (tot > (unsigned long long)w.capacity) return;
-  if (ld_acq_u32(&w.status[0]) & spin_bits_before_sort(pass)) return;
+  if (tot > (unsigned long long)job.capacity) return;
+  if (ld_acq_u32(&job.status[0]) & job.cancel[pass]) return;
   const uint64_t I = tot;
   const uint64_t nchunks = (I + kSortChunk - 1) / kSortChunk;
-  if (tid == 0) s_ticket = atomicAdd(&w.status[2 + pass], 1u);
+  if (tid == 0) s_ticket = atomicAdd(&job.tickets[pass], 1u);
   for (int i = tid; i < kSortWaves * 256; i += kSortThreads) (&s_wh[0][0])[i] = 0u;
 
   // Exclusive scan of the global digit histogram of this pass.
-  const uint32_t hv = w.hist[pass * 256 + tid];
+  const uint32_t hv = job.hist[pass * 256 + tid];
   uint32_t x = hv;
 #pragma unroll
   for (int off = 1; off < 64; off <<= 1) {
@@ -105,7 +127,7 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_pass(Ws w, int pass, int 
   uint32_t cnt = 0;
 #pragma unroll
   for (int k = 0; k < kSortWaves; ++k) cnt += s_wh[k][d];
-  uint32_t *look = w.sort_look + ((size_t)pass * (size_t)w.max_chunks) * 256;
+  uint32_t *look = job.look + ((size_t)pass * (size_t)job.max_chunks) * 256;
   st_rel_u32(&look[chunk * 256 + d], (chunk == 0 ? kFlagP32 : kFlagA32) | cnt);
   uint32_t c = cnt;
 #pragma unroll
@@ -147,8 +169,8 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_pass(Ws w, int pass, int 
     int64_t j = (int64_t)chunk - 1;
     int spins = 0;
     while (true) {
-      if (spins > w.spin_limit) {  // give up (a negative limit: at once)
-        atomicOr(&w.status[0], (uint32_t)ST_SPIN | ((uint32_t)ST_SPIN_SORT0 << pass));
+      if (spins > job.spin_limit) {  // give up (a negative limit: at once)
+        atomicOr(&job.status[0], job.spin[pass]);
         break;
       }
       uint32_t sv[kLookWindow];
@@ -294,14 +316,97 @@ hipError_t launch_tile_order(const Ws &w, int total_tiles, hipStream_t s) {
 
 template <typename KeyT>
 static hipError_t sort_impl(const Ws &w, hipStream_t s) {
+  SortJob job{};
+  job.count = w.total;
+  job.capacity = w.capacity;
+  job.hist = w.hist;
+  job.look = w.sort_look;
+  job.tickets = w.status + kTicketSort;
+  job.status = w.status;
+  job.max_chunks = w.max_chunks;
+  job.spin_limit = w.spin_limit;
+  for (int p = 0; p < 4; ++p) {
+    job.cancel[p] = spin_bits_before_sort(p);
+    job.spin[p] = (uint32_t)ST_SPIN | ((uint32_t)ST_SPIN_SORT0 << p);
+  }
   const int blocks = (int)(w.max_chunks > 0 ? w.max_chunks : 1);
   for (int p = 0; p < w.passes; ++p) {
     const int nbits = (w.key_bits - 8 * p) < 8 ? (w.key_bits - 8 * p) : 8;
     const KeyT *kin = reinterpret_cast<const KeyT *>(w.keys[p & 1]);
     KeyT *kout = reinterpret_cast<KeyT *>(w.keys[(p + 1) & 1]);
-    hipLaunchKernelGGL(k_sort_pass<KeyT>, dim3(blocks), dim3(kSortThreads), 0, s, w, p, nbits,
+    hipLaunchKernelGGL(k_sort_pass<KeyT>, dim3(blocks), dim3(kSortThreads), 0, s, job, p, nbits,
                        kin, w.vals[p & 1], kout, w.vals[(p + 1) & 1]);
     hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Sort key of sorted blending: the view depth of the mean, the third row of
+// the world-to-camera transform applied to it in float64 (x, y and z terms
+// in that order, then the translation; the products of float32 values are
+// exact) and rounded to float32, as an unsigned integer of the same order
+// (-0 taken as +0). Each workgroup also counts its keys' four digits.
+__global__ void __launch_bounds__(256) k_depth_keys(const float *__restrict__ means, int64_t n,
+                                                     float r0, float r1, float r2, float t,
+                                                     uint32_t *__restrict__ keys,
+                                                     uint32_t *__restrict__ idx,
+                                                     uint32_t *__restrict__ hist) {
+  __shared__ uint32_t s_hist[4][256];
+  for (int i = threadIdx.x; i < 4 * 256; i += blockDim.x) (&s_hist[0][0])[i] = 0u;
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n; g += stride) {
+    const double z = (((double)r0 * (double)means[3 * g] + (double)r1 * (double)means[3 * g + 1]) +
+                      (double)r2 * (double)means[3 * g + 2]) + (double)t;
+    float zf = (float)z;
+    if (zf == 0.0f) zf = 0.0f;
+    const uint32_t u = __float_as_uint(zf);
+    const uint32_t key = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+    keys[g] = key;
+    idx[g] = (uint32_t)g;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) atomicAdd(&s_hist[p][(key >> (8 * p)) & 255u], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 4 * 256; i += blockDim.x) {
+    const uint32_t c = (&s_hist[0][0])[i];
+    if (c) atomicAdd(&hist[i], c);
+  }
+}
+
+// The Gaussians front to back by the view depth of their means, ties by
+// index (a stable sort of the index order): depth keys, then four 8-bit
+// passes; the order ends in w.dvals[0].
+hipError_t launch_depth_sort(const Ws &w, const float *means, int64_t n, const float *w2c,
+                             hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  int blocks = (int)((n + 255) / 256);
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(k_depth_keys, dim3(blocks), dim3(256), 0, s, means, n, w2c[8], w2c[9],
+                     w2c[10], w2c[11], w.dkeys[0], w.dvals[0], w.dhist);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  SortJob job{};
+  job.count = nullptr;
+  job.n_fixed = (uint64_t)n;
+  job.capacity = n;
+  job.hist = w.dhist;
+  job.look = w.dlook;
+  job.tickets = w.status + kDsortTicket;
+  job.status = w.status;
+  job.max_chunks = w.dmax_chunks;
+  job.spin_limit = w.spin_limit;
+  for (int p = 0; p < 4; ++p) {
+    job.cancel[p] = spin_bits_before_dsort(p);
+    job.spin[p] = (uint32_t)ST_SPIN | ((uint32_t)ST_SPIN_DSORT0 << p);
+  }
+  const int sblocks = (int)((n + kSortChunk - 1) / kSortChunk);
+  for (int p = 0; p < 4; ++p) {
+    hipLaunchKernelGGL(k_sort_pass<uint32_t>, dim3(sblocks), dim3(kSortThreads), 0, s, job, p, 8,
+                       w.dkeys[p & 1], w.dvals[p & 1], w.dkeys[(p + 1) & 1],
+                       w.dvals[(p + 1) & 1]);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

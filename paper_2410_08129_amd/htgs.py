@@ -24,6 +24,7 @@ HTGS_FLAG_TILE_CULL = 4
 HTGS_FLAG_PERSISTENT = 8
 HTGS_FLAG_NO_TAIL = 16
 HTGS_FLAG_BAKED = 32
+HTGS_FLAG_SORTED = 64
 MAX_VIEWS = 16
 
 EXPORTED = (
@@ -34,7 +35,7 @@ EXPORTED = (
     "htgs_debug_set_spin_limit", "htgs_debug_fragment_counts", "htgs_opacity_decay",
 )
 STAGES = ("fill", "preprocess", "sort", "ranges", "raster_fwd", "raster_bwd", "reduce",
-          "preprocess_bwd")
+          "preprocess_bwd", "depth_sort")
 
 
 class HTGSError(RuntimeError):
@@ -60,7 +61,7 @@ class Config(ctypes.Structure):
                 ("tau_core", ctypes.c_float), ("alpha_max", ctypes.c_float),
                 ("bg", ctypes.c_float * 3), ("tile_w", ctypes.c_int32),
                 ("tile_h", ctypes.c_int32), ("lds_batch", ctypes.c_int32),
-                ("flags", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("tau_T", ctypes.c_float)]
 
 
 class Grads(ctypes.Structure):
@@ -100,7 +101,7 @@ def lib():
     L.htgs_debug_export_bins.argtypes = [P(Gaussians), P(Camera), i32, P(Config), vp, i64, vp, vp,
                                          i64, vp, P(i64), vp]
     L.htgs_debug_set_spin_limit.argtypes = [i32]
-    L.htgs_opacity_decay.argtypes = [vp, i64, ctypes.c_float, vp]
+    L.htgs_opacity_decay.argtypes = [vp, i64, ctypes.c_double, vp]
     L.htgs_debug_fragment_counts.argtypes = [vp, i64, P(i64), P(i64), vp]
     L.htgs_strerror.argtypes = [ctypes.c_int]
     L.htgs_strerror.restype = ctypes.c_char_p
@@ -151,7 +152,9 @@ def config_struct(st) -> Config:
                | (HTGS_FLAG_TILE_CULL if getattr(st, "tile_cull", False) else 0)
                | (HTGS_FLAG_PERSISTENT if getattr(st, "persistent", False) else 0)
                | (HTGS_FLAG_NO_TAIL if getattr(st, "no_tail", False) else 0)
-               | (HTGS_FLAG_BAKED if getattr(st, "baked", False) else 0))
+               | (HTGS_FLAG_BAKED if getattr(st, "baked", False) else 0)
+               | (HTGS_FLAG_SORTED if getattr(st, "sorted_blend", False) else 0))
+    c.tau_T = float(getattr(st, "tau_T", 0.0))
     return c
 
 
@@ -383,7 +386,8 @@ def state_planes(frame: Frame, view: int = 0):
     ([values, H, W]); the state itself is tile-major (see htgs.h)."""
     K = int(frame.st.K)
     tw, th = int(frame.st.tile_w), int(frame.st.tile_h)
-    nval = 6 * K + 6
+    sorted_mode = bool(getattr(frame.st, "sorted_blend", False))
+    nval = 7 if sorted_mode else 6 * K + 6
 
     def tiles(c):
         return (c.width + tw - 1) // tw, (c.height + th - 1) // th
@@ -399,6 +403,9 @@ def state_planes(frame: Frame, view: int = 0):
     # [tile row, tile col, value, block row, block col, row, col]
     blk = blk.view(ty, tx, nval, by, bx, 8, 8).permute(2, 0, 3, 5, 1, 4, 6)
     blk = blk.reshape(nval, ty * th, tx * tw)[:, :cam.height, :cam.width].contiguous()
+    if sorted_mode:
+        return dict(T=blk[0], S=blk[1:4], end_pos=blk[4].view(torch.int32),
+                    n_blended=blk[5].view(torch.int32), stop_id=blk[6].view(torch.int32))
     return dict(core_ids=blk[:K].view(torch.int32), core_alpha=blk[K:2 * K],
                 core_pos=blk[2 * K:3 * K].view(torch.int32),
                 core_rgb=blk[3 * K:6 * K].reshape(K, 3, cam.height, cam.width),

@@ -24,7 +24,7 @@ def test_library_exports_every_declared_entry_point():
     for n in names:
         assert hasattr(L, n), n
     assert set(htgs.EXPORTED) == set(names)
-    assert L.htgs_version() == 2
+    assert L.htgs_version() == 3
 
 
 def test_strerror_codes():
@@ -179,10 +179,10 @@ def test_backward_and_batched_argument_errors():
     assert L.htgs_render_backward(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(cfg), fake,
                                   1 << 30, fake, fake, ctypes.byref(gr3), None) == -1
     # opacity decay: lambda in (0, 1], no work for n = 0
-    assert L.htgs_opacity_decay(fake, 10, ctypes.c_float(1.5), None) == -1
-    assert L.htgs_opacity_decay(fake, 10, ctypes.c_float(0.0), None) == -1
-    assert L.htgs_opacity_decay(None, 10, ctypes.c_float(0.9), None) == -1
-    assert L.htgs_opacity_decay(None, 0, ctypes.c_float(0.9), None) == 0
+    assert L.htgs_opacity_decay(fake, 10, ctypes.c_double(1.5), None) == -1
+    assert L.htgs_opacity_decay(fake, 10, ctypes.c_double(0.0), None) == -1
+    assert L.htgs_opacity_decay(None, 10, ctypes.c_double(0.9), None) == -1
+    assert L.htgs_opacity_decay(None, 0, ctypes.c_double(0.9), None) == 0
     assert L.htgs_read_status(None, 0, None, None, None, None) == -1
     assert L.htgs_profile_read(None, None, 0) == -1
     n = ctypes.c_int64()
@@ -196,3 +196,4 @@ def test_binding_refuses_cpu_tensors():
     params = [torch.tensor(a) for a in sc.arrays()]
     with pytest.raises(htgs.HTGSError):
         htgs.forward(params, sc.sh_degree, cams, st)
+

@@ -150,3 +150,90 @@ def test_ambiguous_pixels_marks_each_kind_of_tie():
     info = _info_of([plain, ztie, cut, elig, clamp, deep])
     amb = parity.ambiguous_pixels(info, 1, 6, ST)[0]
     assert amb.tolist() == [False, True, True, True, True, False]
+
+
+# ---------------------------------------------------------------------------
+# Sorted blending (alpha blending in mean-depth order with an early stop)
+# ---------------------------------------------------------------------------
+
+def sorted_settings(tau_T):
+    return H.settings(K=2, bg=(0.1, 0.2, 0.3), sorted_blend=True, tau_T=tau_T)
+
+
+def blend_in_order(r, gids, st):
+    """Float64 Eq. alpha_blending over the given Gaussians, then the
+    background."""
+    a = np.minimum(st.alpha_max, r['raw'])
+    pos = {int(g): i for i, g in enumerate(r['gid'])}
+    T, C = 1.0, np.zeros(3)
+    for g in gids:
+        i = pos[g]
+        C = C + a[i] * T * r['colour'][i]
+        T *= 1.0 - a[i]
+    return C + T * np.asarray(st.bg)
+
+
+# mean depths that order the Gaussians 8, 3, 5, 9 (index ties broken by index)
+ORDER_KEY = np.zeros(16, np.float32)
+ORDER_KEY[[8, 3, 5, 9]] = [1.0, 2.0, 3.0, 4.0]
+FRAGS = [(3, 1.0, 9.0, 0.6, 2.0, R), (5, 2.0, 9.0, 0.5, 3.0, G), (8, 3.0, 9.0, 0.4, 4.0, B),
+         (9, 1.5, 9.0, 0.9, 1.0, W)]
+
+
+def test_sorted_accepts_the_plain_branch_and_rejects_wrong_ones():
+    r = rec(FRAGS)
+    st = sorted_settings(1e-4)
+    # transmittance stays above 1e-4: all four blended in the order 8, 3, 5, 9
+    rgb = blend_in_order(r, [8, 3, 5, 9], st)
+    assert parity.sorted_branch_error(r, ORDER_KEY, st, 4, -1, rgb) < 1e-12
+    # index order instead of depth order
+    bad = blend_in_order(r, [3, 5, 8, 9], st)
+    assert parity.sorted_branch_error(r, ORDER_KEY, st, 4, -1, bad) > 1e-3
+    # a stop the transmittance does not call for
+    assert parity.sorted_branch_error(r, ORDER_KEY, st, 2, 5,
+                                      blend_in_order(r, [8, 3], st)) is None
+    # a count that does not match the stop position
+    assert parity.sorted_branch_error(r, ORDER_KEY, st, 3, -1, rgb) is None
+
+
+def test_sorted_early_stop_branch():
+    r = rec(FRAGS)
+    # after 8 and 3: T = 0.6 * 0.4 = 0.24; 5 would take it to 0.12
+    st = sorted_settings(0.15)
+    rgb = blend_in_order(r, [8, 3], st)
+    assert parity.sorted_branch_error(r, ORDER_KEY, st, 2, 5, rgb) < 1e-12
+    # blending past the stop is wrong
+    assert parity.sorted_branch_error(r, ORDER_KEY, st, 3, 9,
+                                      blend_in_order(r, [8, 3, 5], st)) is None
+    # stopping a fragment early is wrong too
+    assert parity.sorted_branch_error(r, ORDER_KEY, st, 1, 3,
+                                      blend_in_order(r, [8], st)) is None
+
+
+def test_sorted_accepts_either_side_of_a_threshold_tie():
+    r = rec(FRAGS)
+    # tau_T a hair above T after 8, 3, 5 (0.12): stopping at 5 or not are
+    # both admissible
+    st = sorted_settings(0.12 * (1 + 3e-5))
+    stop = blend_in_order(r, [8, 3], st)
+    go_on = blend_in_order(r, [8, 3, 5], st)
+    assert parity.sorted_branch_error(r, ORDER_KEY, st, 2, 5, stop) < 1e-12
+    assert parity.sorted_branch_error(r, ORDER_KEY, st, 3, 9, go_on) < 1e-12
+    # but not far from the threshold
+    st_far = sorted_settings(0.13)
+    assert parity.sorted_branch_error(r, ORDER_KEY, st_far, 3, 9,
+                                      blend_in_order(r, [8, 3, 5], st_far)) is None
+
+
+def test_sorted_inclusion_tie_either_way_but_not_a_clear_miss():
+    # Gaussian 5 sits at the inclusion boundary; Gaussian 9 clearly outside
+    frags = [(3, 1.0, 9.0, 0.6, 2.0, R), (5, 9.0 * (1 + 5e-5), 9.0, 0.5, 3.0, G),
+             (8, 3.0, 9.0, 0.4, 4.0, B), (9, 9.5, 9.0, 0.9, 1.0, W)]
+    r = rec(frags)
+    st = sorted_settings(1e-4)
+    assert parity.sorted_branch_error(r, ORDER_KEY, st, 3, -1,
+                                      blend_in_order(r, [8, 3, 5], st)) < 1e-12
+    assert parity.sorted_branch_error(r, ORDER_KEY, st, 2, -1,
+                                      blend_in_order(r, [8, 3], st)) < 1e-12
+    e = parity.sorted_branch_error(r, ORDER_KEY, st, 3, -1, blend_in_order(r, [8, 3, 9], st))
+    assert e is None or e > 1e-3
