@@ -39,7 +39,8 @@ enum {
   HTGS_E_KEYWIDTH = -3,   /* total tile count exceeds the 32-bit key range */
   HTGS_E_HIP = -4,        /* a HIP call or kernel launch failed */
   HTGS_E_OVERFLOW = -5,   /* (status) more instances than the workspace holds */
-  HTGS_E_TOO_MANY_VIEWS = -6
+  HTGS_E_TOO_MANY_VIEWS = -6,
+  HTGS_E_TOO_LARGE = -7   /* htgs_render_forward_noalloc: beyond its fixed workspace */
 };
 
 /* Status flags reported by htgs_read_status(). */
@@ -234,6 +235,33 @@ int htgs_count_instances(const htgs_gaussians *g, const htgs_camera *cams, int32
 int htgs_render_forward(const htgs_gaussians *g, const htgs_camera *cam,
                         const htgs_config *cfg, void *ws, int64_t ws_bytes, void *state,
                         float *out_rgb, void *stream);
+
+/* Bytes of the library-owned device workspace of htgs_render_forward_noalloc
+ * (one copy per GPU, held from the library's load until the process ends). */
+#define HTGS_NOALLOC_WS_BYTES (64ll << 20)
+
+/* Allocation-free forward render of one view, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc). Same image as htgs_render_forward() with
+ * state = NULL (inference; no backward), but with no caller workspace: the
+ * library uses its own device array of HTGS_NOALLOC_WS_BYTES on the current
+ * device (which must be the stream's device), and this call allocates
+ * nothing (no hipMalloc, no events). The device address of that array is
+ * looked up on the first call on each device.
+ *  out_rgb     [3,H,W] DEVICE float32, caller-owned
+ *  status_out  DEVICE uint32 or NULL (4-byte aligned): receives the
+ *              HTGS_STATUS_* flags of this call (asynchronously, on stream);
+ *              HTGS_STATUS_OVERFLOW means the instances did not fit in the
+ *              array and the image is invalid
+ * Returns HTGS_E_TOO_LARGE when the per-splat data (about 160 bytes per
+ * Gaussian) and the image's tiles alone exceed the array (so at most about
+ * 400,000 Gaussians, fewer as instances need room too). Every call on one GPU shares that GPU's
+ * array: calls that overlap on one GPU (two streams, two threads) race and
+ * give wrong images; serialise them. Each call clears the array's headers
+ * itself, so no call depends on the one before. */
+int htgs_render_forward_noalloc(const htgs_gaussians *g, const htgs_camera *cam,
+                                const htgs_config *cfg, float *out_rgb, uint32_t *status_out,
+                                void *stream);
 
 /* Backward of the last htgs_render_forward() on this workspace and state
  * (Sec. 3.3, last paragraph: the core's fragments are re-evaluated from the

@@ -2,6 +2,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
 #include <vector>
 
 #include "../../include/htgs.h"
@@ -437,6 +438,38 @@ int backward_impl(const htgs_gaussians *g, const htgs_camera *cams, int32_t n_vi
   return HTGS_OK;
 }
 
+// Workspace of the allocation-free forward: a file-scope device array, one
+// copy per GPU (each device that loads the library holds it until the
+// process ends). Host code never uses the array's name as an address: the
+// device address of each GPU's copy is looked up once per device with
+// hipGetSymbolAddress and kept in g_scratch_ptr.
+constexpr int64_t kScratchBytes = (int64_t)HTGS_NOALLOC_WS_BYTES;
+constexpr int kMaxDevices = 64;
+}  // namespace
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's copy of `scratch` (looked up on
+// the first call on that device), or null if the lookup fails.
+void *scratch_of_current_device() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
+
+// Public status flags of a workspace to a caller's device word.
+__global__ void k_copy_status(const uint32_t *__restrict__ status, uint32_t *__restrict__ out) {
+  if (threadIdx.x == 0) *out = status[0] & kStatusPublic;
+}
+
 }  // namespace
 }  // namespace htgs
 
@@ -455,6 +488,9 @@ const char *htgs_strerror(int code) {
     case HTGS_E_HIP: return "HIP error";
     case HTGS_E_OVERFLOW: return "instance capacity exceeded";
     case HTGS_E_TOO_MANY_VIEWS: return "too many views";
+    case HTGS_E_TOO_LARGE:
+      return "scene or image too large for the library-owned workspace of the allocation-free "
+             "forward";
     default: return "unknown error";
   }
 }
@@ -512,6 +548,33 @@ int htgs_render_forward(const htgs_gaussians *g, const htgs_camera *cam, const h
                         void *ws, int64_t ws_bytes, void *state, float *out_rgb, void *stream) {
   float *outs[1] = {out_rgb};
   return forward_impl(g, cam, 1, cfg, ws, ws_bytes, state, outs, stream);
+}
+
+int htgs_render_forward_noalloc(const htgs_gaussians *g, const htgs_camera *cam,
+                                const htgs_config *cfg, float *out_rgb, uint32_t *status_out,
+                                void *stream) {
+  int e = check_common(g, cam, 1, cfg);
+  if (e) return e;
+  if (!out_rgb) return HTGS_E_INVAL;
+  if ((reinterpret_cast<uintptr_t>(status_out) & 3u) != 0) return HTGS_E_INVAL;
+  // the forward-only layout with no instance must fit; instances beyond
+  // what fits are reported as an overflow in the status word
+  if (make_layout(g->n, 1, total_tiles_of(cam, 1, cfg), 0, false, sorted_of(cfg)).bytes >
+      kScratchBytes)
+    return HTGS_E_TOO_LARGE;
+  void *ws = scratch_of_current_device();
+  if (!ws) return HTGS_E_HIP;
+  float *outs[1] = {out_rgb};
+  if ((e = forward_impl(g, cam, 1, cfg, ws, kScratchBytes, nullptr, outs, stream, false)))
+    return e;
+  if (status_out) {
+    const Layout L = make_layout(0, 1, 1, 0);
+    hipLaunchKernelGGL(k_copy_status, dim3(1), dim3(64), 0, static_cast<hipStream_t>(stream),
+                       reinterpret_cast<const uint32_t *>(static_cast<char *>(ws) + L.status),
+                       status_out);
+    HIP_TRY(hipGetLastError());
+  }
+  return HTGS_OK;
 }
 
 int htgs_render_backward(const htgs_gaussians *g, const htgs_camera *cam, const htgs_config *cfg,

@@ -33,6 +33,7 @@ EXPORTED = (
     "htgs_render_backward_batched", "htgs_read_status", "htgs_debug_export_bins",
     "htgs_strerror", "htgs_version", "htgs_profile_enable", "htgs_profile_read",
     "htgs_debug_set_spin_limit", "htgs_debug_fragment_counts", "htgs_opacity_decay",
+    "htgs_render_forward_noalloc",
 )
 STAGES = ("fill", "preprocess", "sort", "ranges", "raster_fwd", "raster_bwd", "reduce",
           "preprocess_bwd", "depth_sort")
@@ -89,6 +90,7 @@ def lib():
     L.htgs_state_bytes.argtypes = [P(Camera), i32, P(Config), P(i64)]
     L.htgs_count_instances.argtypes = [P(Gaussians), P(Camera), i32, P(Config), vp, i64, P(i64), vp]
     L.htgs_render_forward.argtypes = [P(Gaussians), P(Camera), P(Config), vp, i64, vp, vp, vp]
+    L.htgs_render_forward_noalloc.argtypes = [P(Gaussians), P(Camera), P(Config), vp, vp, vp]
     L.htgs_render_backward.argtypes = [P(Gaussians), P(Camera), P(Config), vp, i64, vp, vp,
                                        P(Grads), vp]
     L.htgs_render_forward_batched.argtypes = [P(Gaussians), P(Camera), i32, P(Config), vp, i64,
@@ -322,6 +324,27 @@ def forward(params, sh_degree, cams, st, ws=None, state=None, images=None, strea
                                                  outs, stream_handle(stream))
     check(code, "render_forward")
     return Frame(ws, state, images, cams, st, sh_degree)
+
+
+def forward_noalloc(params, sh_degree, cam, st, out, status=None, stream=None):
+    """Allocation-free inference render of one camera into ``out`` ([3,H,W]
+    float32, caller-allocated) with the library's own workspace; ``status``:
+    an optional int32 device tensor of one element that receives the status
+    flags."""
+    g, keep = _gstruct(params, sh_degree)
+    out = _dev_f32(out, "out")
+    if tuple(out.shape) != (3, cam.height, cam.width):
+        raise HTGSError(f"out has shape {tuple(out.shape)}, expected {(3, cam.height, cam.width)}")
+    sp = 0
+    if status is not None:
+        if not (status.is_cuda and status.dtype == torch.int32 and status.numel() >= 1):
+            raise HTGSError("status must be an int32 device tensor")
+        sp = status.data_ptr()
+    arr = cameras_array([cam])
+    check(lib().htgs_render_forward_noalloc(ctypes.byref(g), arr, ctypes.byref(config_struct(st)),
+                                            ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(sp),
+                                            stream_handle(stream)), "render_forward_noalloc")
+    return out
 
 
 def backward(params, frame: Frame, grad_images, grads=None, stream=None, densify=None):

@@ -197,3 +197,27 @@ def test_binding_refuses_cpu_tensors():
     with pytest.raises(htgs.HTGSError):
         htgs.forward(params, sc.sh_degree, cams, st)
 
+
+def test_noalloc_forward_argument_errors_before_device_work():
+    """The allocation-free forward rejects bad arguments, and scenes whose
+    per-splat data alone exceed its fixed workspace, before any device call."""
+    sc, cams, st = _small()
+    L = htgs.lib()
+    cam = htgs.camera_struct(cams[0])
+    cfg = htgs.config_struct(st)
+    fake = ctypes.c_void_p(0x2000)
+    g = _fake_gaussians()
+    assert L.htgs_render_forward_noalloc(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(cfg),
+                                         None, None, None) == -1
+    # misaligned status word
+    assert L.htgs_render_forward_noalloc(ctypes.byref(g), ctypes.byref(cam), ctypes.byref(cfg),
+                                         fake, ctypes.c_void_p(0x2002), None) == -1
+    bad = htgs.camera_struct(cams[0])
+    bad.height = -3
+    assert L.htgs_render_forward_noalloc(ctypes.byref(g), ctypes.byref(bad), ctypes.byref(cfg),
+                                         fake, None, None) == -1
+    # 1M Gaussians: ~160 MB of per-splat data, beyond the 64 MiB array
+    big = _fake_gaussians(n=1_000_000)
+    assert L.htgs_render_forward_noalloc(ctypes.byref(big), ctypes.byref(cam), ctypes.byref(cfg),
+                                         fake, None, None) == -7
+    assert b"too large" in L.htgs_strerror(-7)
