@@ -36,8 +36,8 @@ constexpr int64_t kMaxCapacity = (1ll << 30) - 1;
 int64_t align_up(int64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  int64_t status, total, pp_look, hist, sort_look, ranges, order_hist, dhist, dlook, zero_end;
-  int64_t records, rects, tslots, cflags, order, keys0, keys1, vals0, vals1, partials;
+  int64_t status, total, frags, pp_look, hist, sort_look, ranges, order_hist, dhist, dlook, zero_end;
+  int64_t records, rects, tslots, refpix, cflags, order, keys0, keys1, vals0, vals1, partials;
   int64_t dkeys0, dkeys1, dvals0, dvals1, bytes;
   int64_t capacity, max_chunks, dmax_chunks;
   int32_t key_bits, passes, key16, sorted;
@@ -64,7 +64,8 @@ Layout make_layout(int64_t n, int n_views, int64_t total_tiles, int64_t capacity
   const int64_t kb = L.key16 ? 2 : 4;
   int64_t o = 0;
   L.status = o; o = align_up(o + 4 * kStatusWords);
-  L.total = o; o = align_up(o + 32);   // instances, forward and backward fragments
+  L.total = o; o = align_up(o + 8);   // instance count
+  L.frags = o; o = align_up(o + 2 * 8 * kCounterSpread * kCounterStride);  // fragment counters
   L.pp_look = o; o = align_up(o + 8 * ((n + kPreThreads - 1) / kPreThreads));
   L.hist = o; o = align_up(o + 4 * 256 * 4);
   L.sort_look = o; o = align_up(o + (int64_t)L.passes * L.max_chunks * 256 * 4);
@@ -75,6 +76,7 @@ Layout make_layout(int64_t n, int n_views, int64_t total_tiles, int64_t capacity
   L.zero_end = o;
   L.records = o; o = align_up(o + (int64_t)n_views * n * kRecFloats * 4);
   L.rects = o; o = align_up(o + (int64_t)n_views * n * 16);
+  L.refpix = o; o = align_up(o + (int64_t)n_views * n * 4);
   L.cflags = o; o = align_up(o + (int64_t)n_views * n);
   L.tslots = o; o = align_up(o + (int64_t)n_views * n * 16);
   L.order = o; o = align_up(o + 4 * total_tiles);
@@ -111,8 +113,8 @@ Ws make_ws(void *base, const Layout &L) {
   Ws w{};
   w.status = reinterpret_cast<uint32_t *>(b + L.status);
   w.total = reinterpret_cast<unsigned long long *>(b + L.total);
-  w.frags = w.total + 1;
-  w.frags_bwd = w.total + 2;
+  w.frags = reinterpret_cast<unsigned long long *>(b + L.frags);
+  w.frags_bwd = w.frags + kCounterSpread * kCounterStride;
   w.pp_look = reinterpret_cast<unsigned long long *>(b + L.pp_look);
   w.hist = reinterpret_cast<uint32_t *>(b + L.hist);
   w.sort_look = reinterpret_cast<uint32_t *>(b + L.sort_look);
@@ -122,6 +124,7 @@ Ws make_ws(void *base, const Layout &L) {
   w.records = reinterpret_cast<float *>(b + L.records);
   w.rects = reinterpret_cast<int4 *>(b + L.rects);
   w.tslots = reinterpret_cast<uint4 *>(b + L.tslots);
+  w.refpix = reinterpret_cast<uint32_t *>(b + L.refpix);
   w.cflags = reinterpret_cast<uint8_t *>(b + L.cflags);
   w.keys[0] = b + L.keys0;
   w.keys[1] = b + L.keys1;
@@ -406,7 +409,7 @@ int backward_impl(const htgs_gaussians *g, const htgs_camera *cams, int32_t n_vi
   if (e) return e;
   if (!ws || !state || !grad_rgb || !grads) return HTGS_E_INVAL;
   // inference-only modes have no backward
-  if (cfg->flags & (HTGS_FLAG_NO_TAIL | HTGS_FLAG_BAKED | HTGS_FLAG_SORTED)) return HTGS_E_INVAL;
+  if (cfg->flags & (HTGS_FLAG_NO_TAIL | HTGS_FLAG_BAKED)) return HTGS_E_INVAL;
   if (!aligned16(grads->means) || !aligned16(grads->log_scales) || !aligned16(grads->quats) ||
       !aligned16(grads->opacity_logits) || !aligned16(grads->sh))
     return HTGS_E_INVAL;
@@ -416,9 +419,9 @@ int backward_impl(const htgs_gaussians *g, const htgs_camera *cams, int32_t n_vi
   for (int v = 0; v < n_views; ++v)
     if (!grad_rgb[v]) return HTGS_E_INVAL;
   const int64_t tiles = total_tiles_of(cams, n_views, cfg);
-  const int64_t cap = capacity_for(g->n, n_views, tiles, ws_bytes);
+  const int64_t cap = capacity_for(g->n, n_views, tiles, ws_bytes, true, sorted_of(cfg));
   if (cap < 0) return HTGS_E_WORKSPACE;
-  const Layout L = make_layout(g->n, n_views, tiles, cap);
+  const Layout L = make_layout(g->n, n_views, tiles, cap, true, sorted_of(cfg));
   const ViewSet vs = make_views(cams, n_views, cfg, nullptr, grad_rgb);
   const Ws w = make_ws(ws, L);
   const KCfg k = make_kcfg(g, cfg);
@@ -435,6 +438,22 @@ int backward_impl(const htgs_gaussians *g, const htgs_camera *cams, int32_t n_vi
                     grads->sh, grads->mean_grad_stat, grads->visible_count};
   StageTimer t(HTGS_STAGE_PREPROCESS_BWD, s);
   HIP_TRY(launch_preprocess_bwd(make_gp(g), gr, k, vs, w, s));
+  return HTGS_OK;
+}
+
+// Sums of the spread fragment counters (forward, backward). Synchronises.
+int read_counters(const void *ws, const Layout &L, int64_t *fwd, int64_t *bwd, hipStream_t s) {
+  unsigned long long c[2 * kCounterSpread * kCounterStride];
+  HIP_TRY(hipMemcpyAsync(c, static_cast<const char *>(ws) + L.frags, sizeof(c),
+                         hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  unsigned long long f = 0, b = 0;
+  for (int k = 0; k < kCounterSpread; ++k) {
+    f += c[k * kCounterStride];
+    b += c[(kCounterSpread + k) * kCounterStride];
+  }
+  *fwd = (int64_t)f;
+  *bwd = (int64_t)b;
   return HTGS_OK;
 }
 
@@ -601,20 +620,25 @@ int htgs_render_backward_batched(const htgs_gaussians *g, const htgs_camera *cam
 
 int htgs_read_status(const void *ws, int64_t ws_bytes, uint32_t *flags_out,
                      int64_t *instances_out, int64_t *fragments_out, void *stream) {
-  if (!ws || !flags_out || ws_bytes < make_layout(0, 1, 1, 0).total + 24) return HTGS_E_INVAL;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  uint32_t flags = 0;
-  unsigned long long counts[2] = {0, 0};
   // status and counters sit at fixed offsets at the start of every layout
   const Layout L = make_layout(0, 1, 1, 0);
+  if (!ws || !flags_out || ws_bytes < L.pp_look) return HTGS_E_INVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  uint32_t flags = 0;
+  unsigned long long total = 0;
+  int64_t fwd = 0, bwd = 0;
   HIP_TRY(hipMemcpyAsync(&flags, static_cast<const char *>(ws) + L.status, 4,
                          hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipMemcpyAsync(counts, static_cast<const char *>(ws) + L.total, 16,
+  HIP_TRY(hipMemcpyAsync(&total, static_cast<const char *>(ws) + L.total, 8,
                          hipMemcpyDeviceToHost, s));
+  if (fragments_out) {
+    int e = read_counters(ws, L, &fwd, &bwd, s);
+    if (e) return e;
+  }
   HIP_TRY(hipStreamSynchronize(s));
   *flags_out = flags & kStatusPublic;
-  if (instances_out) *instances_out = (int64_t)counts[0];
-  if (fragments_out) *fragments_out = (int64_t)counts[1];
+  if (instances_out) *instances_out = (int64_t)total;
+  if (fragments_out) *fragments_out = fwd;
   return HTGS_OK;
 }
 
@@ -631,17 +655,9 @@ int htgs_debug_set_spin_limit(int32_t limit) {
 
 int htgs_debug_fragment_counts(const void *ws, int64_t ws_bytes, int64_t *forward_out,
                                int64_t *backward_out, void *stream) {
-  if (!ws || !forward_out || !backward_out || ws_bytes < make_layout(0, 1, 1, 0).total + 24)
-    return HTGS_E_INVAL;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  unsigned long long counts[3] = {0, 0, 0};
   const Layout L = make_layout(0, 1, 1, 0);
-  HIP_TRY(hipMemcpyAsync(counts, static_cast<const char *>(ws) + L.total, 24,
-                         hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  *forward_out = (int64_t)counts[1];
-  *backward_out = (int64_t)counts[2];
-  return HTGS_OK;
+  if (!ws || !forward_out || !backward_out || ws_bytes < L.pp_look) return HTGS_E_INVAL;
+  return read_counters(ws, L, forward_out, backward_out, static_cast<hipStream_t>(stream));
 }
 
 int htgs_profile_enable(int on) {

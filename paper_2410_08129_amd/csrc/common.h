@@ -8,7 +8,7 @@ namespace htgs {
 
 constexpr int kMaxViews = 16;
 constexpr int kRecFloats = 32;      // per (view, Gaussian) raster record
-constexpr int kPartialFloats = 24;  // per-instance backward partials (22 used)
+constexpr int kPartialFloats = 16;  // per-instance backward partials (64 bytes)
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;
 constexpr int kSortChunk = kSortThreads * kSortItems;
@@ -33,25 +33,16 @@ enum RecField {
   R_BB1 = 31    //                     x1 | y1 << 16 (inclusive)
 };
 
-// Per-instance backward partials: the gradient of the loss w.r.t. the
-// record coefficients D0, Du, Dv, M0, Mu, Mv of one (Gaussian, view) in
-// camera coordinates (d = D0 + u Du + v Dv, u = (x - cx)/fx), w.r.t. the
-// opacity and the colour, summed over one tile's pixels; then the segment
-// id (view << 27 | Gaussian). A segmented reduction later sums a segment's
-// slots in place.
+// Per-instance backward partials, summed over one tile's pixels p of one
+// (view, Gaussian): the moments sum_p w(p) (1, dx, dy, dx^2, dx dy, dy^2)
+// of the weights w = dL/d(d) / d and dL/d(m) / m (the loss gradient
+// w.r.t. the Pluecker vectors is w(p) times the vector), with (dx, dy) the
+// pixel's offset from the record's reference pixel (ix, iy) (the covered
+// pixel nearest the centre of the splat's screen box); then
+// dL/do and dL/d(rgb). Moments about one origin add up over the tiles, and
+// the preprocess backward turns the sums into coefficient gradients once.
 enum PartialField {
-  P_D0 = 0, P_DX = 3, P_DY = 6, P_M0 = 9, P_MX = 12, P_MY = 15, P_O = 18, P_C = 19,
-  P_SEG = 22
-};
-
-// Record as the raster backward holds it in registers: tile-centred affine
-// coefficients of d and m, cutoff, opacity, colour and the pixel rect
-// relative to the tile (the forward stages quadratic forms instead).
-enum StageField {
-  S_D0 = 0, S_DU = 3, S_DV = 6, S_M0 = 9, S_MU = 12, S_MV = 15, S_RC = 18, S_O = 19,
-  S_RGB = 24,
-  S_BB0 = 28, S_BB1 = 29, S_BB2 = 30, S_BB3 = 31,  // tile-local x0, y0, x1, y1 (int bits)
-  S_FLOATS = 32
+  P_MD = 0, P_MM = 6, P_O = 12, P_C = 13
 };
 
 struct ViewParams {
@@ -108,8 +99,8 @@ constexpr uint32_t kCflagVisible = 8u;
 struct Ws {
   uint32_t *status;            // [kStatusWords]: flags, tickets, raster queues (see below)
   unsigned long long *total;   // instance count (64-bit)
-  unsigned long long *frags;   // fragments counted by the forward raster
-  unsigned long long *frags_bwd;  // fragments counted by the backward raster
+  unsigned long long *frags;   // fragments counted by the forward raster (spread, below)
+  unsigned long long *frags_bwd;  // fragments counted by the backward raster (spread)
   unsigned long long *pp_look; // preprocess look-back words, one per block
   uint32_t *hist;              // [4][256] digit histograms
   uint32_t *sort_look;         // [passes][max_chunks][256]
@@ -119,6 +110,7 @@ struct Ws {
   float *records;              // [views][n][32]
   int4 *rects;                 // [views][n] tile rect (tx0, ty0, tx1, ty1), empty if tx0 > tx1
   uint4 *tslots;               // [views][n] tile-slot descriptor (see below)
+  uint32_t *refpix;            // [views][n] the record's reference pixel ix | iy << 16
   uint8_t *cflags;             // [views][n] bit c < 3: colour channel c was clamped at 0;
                                // kCflagVisible: the pixel rect is not empty
   void *keys[2];
@@ -155,6 +147,17 @@ __host__ __device__ constexpr int state_values(int K) { return 6 * K + 6; }
 constexpr int kSortedStateValues = 7;
 
 constexpr int kLookWindow = 4;   // look-back words read per round trip
+
+// Fragment counters: kCounterSpread words, each in a 128-byte line of its
+// own, added to by workgroup blockIdx % kCounterSpread and summed when
+// read. With one word, the raster's tens of thousands of workgroups queued
+// their end-of-tile atomics on one address (the 8x8 backward ran ~35%
+// slower with one atomic per workgroup).
+constexpr int kCounterSpread = 64;
+constexpr int kCounterStride = 16;   // 64-bit words per 128-byte line
+__device__ __forceinline__ void count_add(unsigned long long *ctr, unsigned long long v) {
+  atomicAdd(ctr + (blockIdx.x % kCounterSpread) * kCounterStride, v);
+}
 
 // Status word. ST_SPIN: some cross-workgroup wait gave up, so some prefix
 // is wrong; the stage bit says where (preprocess, or sort pass p), so that

@@ -380,6 +380,7 @@ __device__ inline uint32_t preprocess_view(const GaussPtrs &gp, const KCfg &cfg,
 #pragma unroll
   for (int k = 0; k < 6; ++k)
     dst[k] = make_float4(rec[4 * k], rec[4 * k + 1], rec[4 * k + 2], rec[4 * k + 3]);
+  w.refpix[vg] = (uint32_t)ixd | ((uint32_t)iyd << 16);
   dst[R_IX / 4] = make_float4(__int_as_float((int)ixd), __int_as_float((int)iyd),
                               __uint_as_float((uint32_t)x0 | ((uint32_t)y0 << 16)),
                               __uint_as_float((uint32_t)x1 | ((uint32_t)y1 << 16)));
@@ -687,7 +688,7 @@ __device__ inline void rot_grad_to_quat(const double qn[4], const double gR[3][3
                y * gR[1][2] + x * gR[2][0] + y * gR[2][1]);
 }
 
-// One step of the wave-wide segmented inclusive scan of the 22 partial
+// One step of the wave-wide segmented inclusive scan of the partial
 // values: lanes enabled by ROW_MASK take the DPP-moved value (CTRL) when
 // the source lane holds the same segment id. Lanes with no source lane keep
 // the complement of their own id, which never matches.
@@ -697,7 +698,7 @@ __device__ __forceinline__ void seg_scan_step(uint32_t seg, float *v) {
                                                              0xf, false);
   const bool take = src == seg;
 #pragma unroll
-  for (int k = 0; k < 22; ++k) {
+  for (int k = 0; k < kPartialFloats; ++k) {
     const float y = __int_as_float(
         __builtin_amdgcn_update_dpp(0, __float_as_int(v[k]), CTRL, ROW_MASK, 0xf, false));
     v[k] += take ? y : 0.f;
@@ -820,23 +821,39 @@ __device__ __forceinline__ void sh_backward(const float *wsv, const double dir[3
 // slots are one contiguous range, view by view). For each view the wave
 // walks that view's part of the range 64 slots at a time with the
 // segmented scan and adds each segment's sum into its owner's LDS column,
-// so the partials are read once, coalesced; then every lane turns its
-// Gaussian's sums for the view into parameter gradients.
+// so the partials are read once, coalesced. A slot's owner is the last
+// Gaussian of the group whose first slot is at or before it (first slots
+// increase with the Gaussian): each owner marks its first slot in LDS and
+// a prefix maximum over the chunk fills the rest. Then every lane turns its
+// Gaussian's summed moments for the view into gradients of the Pluecker
+// coefficients (float64) and those into parameter gradients.
 template <int DEG, bool MV>
 __global__ void __launch_bounds__(256) k_preprocess_bwd(GaussPtrs gp, GradPtrs gr, KCfg cfg,
                                                          ViewSet vs, Ws w) {
   constexpr int NB = (DEG + 1) * (DEG + 1);
-  __shared__ float s_acc[4][22][64];
+  __shared__ float s_acc[4][kPartialFloats][64];
+  __shared__ int s_own[4][64];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t g0 = g - lane;
-  if (g0 >= cfg.n) return;  // uniform over the wave
-  const bool live = g < cfg.n;
+  const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t pos0 = pos - lane;
+  if (pos0 >= cfg.n) return;  // uniform over the wave
   const int nviews = MV ? vs.n : 1;
   const unsigned long long I = *w.total;
   // An overflowed forward, or one whose look-back gave up (both reported
   // by the status word), leaves no usable partials: zero gradient.
   const bool ok = I <= (unsigned long long)w.capacity && !front_failed(w);
+  // Sorted blending emitted the instances in the depth order of its
+  // Gaussians (position p holds Gaussian perm[p]), so a group of 64
+  // positions owns one contiguous slot range; otherwise positions are
+  // Gaussian indices. (Without usable partials the index order serves.)
+  const bool by_perm = w.perm != nullptr && ok;
+  auto gauss_at = [&](int64_t p) -> int64_t {
+    if (!by_perm) return p;
+    const uint32_t x = w.perm[p];
+    return (int64_t)x < cfg.n ? (int64_t)x : p;
+  };
+  const bool live = pos < cfg.n;
+  const int64_t g = live ? gauss_at(pos) : pos;
   uint32_t total = 0;
   if (live && ok)
     for (int v = 0; v < nviews; ++v)
@@ -863,83 +880,123 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(GaussPtrs gp, GradPtrs g
   const float *shrow = gp.sh + g * NB * 3;
 
   if (ok && __ballot(total != 0) != 0ull) {
-    const uint64_t group_end = (g0 + 64 < cfg.n) ? (uint64_t)w.tslots[g0 + 64].x : (uint64_t)I;
+    const int64_t gfirst = gauss_at(pos0);
+    const uint64_t group_end =
+        (pos0 + 64 < cfg.n) ? (uint64_t)w.tslots[gauss_at(pos0 + 64)].x : (uint64_t)I;
     for (int v = 0; v < nviews; ++v) {
-      const uint64_t lo = w.tslots[(int64_t)v * cfg.n + g0].x;
-      const uint64_t hi = min((v + 1 < nviews) ? (uint64_t)w.tslots[(int64_t)(v + 1) * cfg.n + g0].x
+      const uint64_t lo = w.tslots[(int64_t)v * cfg.n + gfirst].x;
+      const uint64_t hi = min((v + 1 < nviews) ? (uint64_t)w.tslots[(int64_t)(v + 1) * cfg.n + gfirst].x
                                                : group_end, (uint64_t)I);
       if (lo >= hi) continue;  // no instance of this group in view v
 #pragma unroll
-      for (int k = 0; k < 22; ++k) s_acc[wave][k][lane] = 0.f;
+      for (int k = 0; k < kPartialFloats; ++k) s_acc[wave][k][lane] = 0.f;
+      // this lane's Gaussian in view v: first slot, instance count
+      const uint4 myd = live ? w.tslots[(int64_t)v * cfg.n + g] : make_uint4(0u, 0u, 0u, 0u);
+      const uint32_t mycnt =
+          (live && total) ? (uint32_t)tile_count(w.rects[(int64_t)v * cfg.n + g], tslot_mask(myd)) : 0u;
       __builtin_amdgcn_wave_barrier();
-      // Partials of slot sl (zeros and no segment past the range).
-      auto load_partial = [&](uint64_t sl, float *v22, uint32_t &seg) {
-        seg = 0xffffffffu;
+      // Partials of slot sl (zeros past the range).
+      auto load_partial = [&](uint64_t sl, float *pv) {
         if (sl < hi) {
           const float4 *P = reinterpret_cast<const float4 *>(w.partials + (int64_t)sl * kPartialFloats);
 #pragma unroll
-          for (int k = 0; k < 5; ++k) {
+          for (int k = 0; k < kPartialFloats / 4; ++k) {
             const float4 t = P[k];
-            v22[4 * k] = t.x; v22[4 * k + 1] = t.y; v22[4 * k + 2] = t.z; v22[4 * k + 3] = t.w;
+            pv[4 * k] = t.x; pv[4 * k + 1] = t.y; pv[4 * k + 2] = t.z; pv[4 * k + 3] = t.w;
           }
-          const float4 t = P[5];
-          v22[20] = t.x; v22[21] = t.y;
-          seg = __float_as_uint(t.z);
         } else {
 #pragma unroll
-          for (int k = 0; k < 22; ++k) v22[k] = 0.f;
+          for (int k = 0; k < kPartialFloats; ++k) pv[k] = 0.f;
         }
       };
       // The next 64 slots are loaded while this chunk is scanned.
-      float nv[22];
-      uint32_t nseg;
-      load_partial(lo + lane, nv, nseg);
+      float nv[kPartialFloats];
+      load_partial(lo + lane, nv);
+      int carry = -1;   // owner of the slot before the chunk
       for (uint64_t base = lo; base < hi; base += 64) {
         const uint64_t sl = base + lane;
         const bool valid = sl < hi;
-        float v22[22];
-        uint32_t seg = nseg;
+        float pv[kPartialFloats];
 #pragma unroll
-        for (int k = 0; k < 22; ++k) v22[k] = nv[k];
-        if (base + 64 < hi) load_partial(base + 64 + lane, nv, nseg);
+        for (int k = 0; k < kPartialFloats; ++k) pv[k] = nv[k];
+        if (base + 64 < hi) load_partial(base + 64 + lane, nv);
+        // owners: marks at first slots, then a prefix maximum
+        s_own[wave][lane] = -1;
+        __builtin_amdgcn_wave_barrier();
+        if (mycnt && (uint64_t)myd.x >= base && (uint64_t)myd.x < base + 64)
+          s_own[wave][myd.x - base] = lane;
+        __builtin_amdgcn_wave_barrier();
+        int own = max(s_own[wave][lane], carry);
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+          const int y = __shfl_up(own, off, 64);
+          if (lane >= off) own = max(own, y);
+        }
+        carry = __shfl(own, 63, 64);
+        const uint32_t seg = valid ? (uint32_t)own : 0xffffffffu;
         // Inclusive segmented scan over the wave with DPP lane moves (no
         // LDS): shifts by 1, 2, 4, 8 inside each row of 16 lanes, then the
         // last lane of row 0 / row 2 into rows 1 / 3, then lane 31 into rows
-        // 2 and 3. Segments are runs of consecutive slots, so equal ids mean
-        // one run; the fixed tree makes the sums deterministic.
-        seg_scan_step<0x111, 0xf>(seg, v22);   // row_shr:1
-        seg_scan_step<0x112, 0xf>(seg, v22);   // row_shr:2
-        seg_scan_step<0x114, 0xf>(seg, v22);   // row_shr:4
-        seg_scan_step<0x118, 0xf>(seg, v22);   // row_shr:8
-        seg_scan_step<0x142, 0xa>(seg, v22);   // row_bcast:15 into rows 1, 3
-        seg_scan_step<0x143, 0xc>(seg, v22);   // row_bcast:31 into rows 2, 3
+        // 2 and 3. Segments are runs of consecutive slots, so equal owners
+        // mean one run; the fixed tree makes the sums deterministic.
+        seg_scan_step<0x111, 0xf>(seg, pv);   // row_shr:1
+        seg_scan_step<0x112, 0xf>(seg, pv);   // row_shr:2
+        seg_scan_step<0x114, 0xf>(seg, pv);   // row_shr:4
+        seg_scan_step<0x118, 0xf>(seg, pv);   // row_shr:8
+        seg_scan_step<0x142, 0xa>(seg, pv);   // row_bcast:15 into rows 1, 3
+        seg_scan_step<0x143, 0xc>(seg, pv);   // row_bcast:31 into rows 2, 3
         const uint32_t sn = __shfl_down(seg, 1, 64);
-        const bool end = valid && (lane == 63 || sn != seg || sl + 1 == hi);
+        const bool end = valid && own >= 0 && (lane == 63 || sn != seg || sl + 1 == hi);
         if (end) {
-          const int owner = (int)((int64_t)(seg & ((1u << 27) - 1u)) - g0);
 #pragma unroll
-          for (int k = 0; k < 22; ++k) s_acc[wave][k][owner] += v22[k];
+          for (int k = 0; k < kPartialFloats; ++k) s_acc[wave][k][own] += pv[k];
         }
         __builtin_amdgcn_wave_barrier();
       }
       __builtin_amdgcn_wave_barrier();
-      const bool mine = total != 0 &&
-          tile_count(w.rects[(int64_t)v * cfg.n + g], tslot_mask(w.tslots[(int64_t)v * cfg.n + g])) > 0;
-      if (mine) {
-        float acc[22];
+      if (mycnt) {
+        float acc[kPartialFloats];
 #pragma unroll
-        for (int k = 0; k < 22; ++k) acc[k] = s_acc[wave][k][lane];
+        for (int k = 0; k < kPartialFloats; ++k) acc[k] = s_acc[wave][k][lane];
         const ViewParams &V = vs.v[v];
-        double gD0[3], gDu[3], gDv[3], gM0[3], gMu[3], gMv[3], gc[3];
-        for (int k = 0; k < 3; ++k) {
-          gD0[k] = acc[P_D0 + k]; gDu[k] = acc[P_DX + k]; gDv[k] = acc[P_DY + k];
-          gM0[k] = acc[P_M0 + k]; gMu[k] = acc[P_MX + k]; gMv[k] = acc[P_MY + k];
-          gc[k] = acc[P_C + k];
-        }
-        go += acc[P_O];
-        // Pluecker coefficients -> view rows of M T.
+        // Pluecker coefficients in camera coordinates (d = D + u Du + v Dv,
+        // u = (x + 1/2 - cx) / fx) and, from the summed moments about the
+        // record's reference pixel (ox, oy), the loss gradients w.r.t. them.
         double Rv[3][3], mv[3];
         view_rows_va(V, va, Rv, mv);
+        double D[3][3], M[3][3];   // [D or M][0: constant, 1: u, 2: v][xyz]
+        cross3(Rv[0], Rv[1], D[0]);
+        cross3(Rv[1], Rv[2], D[1]);
+        cross3(Rv[2], Rv[0], D[2]);
+        for (int k = 0; k < 3; ++k) {
+          M[0][k] = mv[0] * Rv[1][k] - mv[1] * Rv[0][k];
+          M[1][k] = mv[1] * Rv[2][k] - mv[2] * Rv[1][k];
+          M[2][k] = mv[2] * Rv[0][k] - mv[0] * Rv[2][k];
+        }
+        const uint32_t rp = w.refpix[(int64_t)v * cfg.n + g];
+        const double ox = (double)(rp & 0xffffu), oy = (double)(rp >> 16);
+        const double ifx = 1.0 / (double)V.fx, ify = 1.0 / (double)V.fy;
+        const double uo = (ox + 0.5 - (double)V.cx) * ifx, vo = (oy + 0.5 - (double)V.cy) * ify;
+        double gD0[3], gDu[3], gDv[3], gM0[3], gMu[3], gMv[3], gc[3];
+        for (int h = 0; h < 2; ++h) {
+          const double(*C)[3] = h ? M : D;
+          const float *m = acc + (h ? P_MM : P_MD);
+          double *g0v = h ? gM0 : gD0, *guv = h ? gMu : gDu, *gvv = h ? gMv : gDv;
+          for (int k = 0; k < 3; ++k) {
+            // the vector at the origin pixel and its steps per pixel
+            const double c0 = C[0][k] + uo * C[1][k] + vo * C[2][k];
+            const double cx_ = C[1][k] * ifx, cy_ = C[2][k] * ify;
+            const double s0 = c0 * m[0] + cx_ * m[1] + cy_ * m[2];
+            const double sx = c0 * m[1] + cx_ * m[3] + cy_ * m[4];
+            const double sy = c0 * m[2] + cx_ * m[4] + cy_ * m[5];
+            g0v[k] = s0;
+            guv[k] = uo * s0 + sx * ifx;
+            gvv[k] = vo * s0 + sy * ify;
+          }
+        }
+        for (int k = 0; k < 3; ++k) gc[k] = acc[P_C + k];
+        go += acc[P_O];
+        // Pluecker coefficients -> view rows of M T.
         double gR[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
         double gm[3] = {0, 0, 0};
         double t[3];

@@ -31,7 +31,9 @@
 // 18 affine coefficients follows
 // from six moments of dL/d(rho^2)-weights per vector (sum of w, w lx, w ly,
 // w lx^2, w lx ly, w ly^2), accumulated in registers. Each lane writes one
-// partial per instance: no floating-point atomics, deterministic results.
+// partial per instance (the moments about the pixel at the centre of the
+// Gaussian's tile rect, opacity and colour terms): no floating-point
+// atomics, deterministic results.
 #include <float.h>
 
 #include "common.h"
@@ -42,31 +44,6 @@ constexpr float kNegHalfLog2e = -0.72134752044448170368f;  // -1 / (2 ln 2)
 
 __device__ __forceinline__ float exp2_fast(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ float rcp_fast(float x) { return __builtin_amdgcn_rcpf(x); }
-
-// Tile-centred record for the backward: d = D0t + lx Du + ly Dv with
-// (lx, ly) the pixel's integer offset from the tile's first pixel.
-__device__ __forceinline__ void stage_record(const float *__restrict__ rec, int px0, int py0,
-                                             float *st) {
-  const float dx0 = (float)(px0 - __float_as_int(rec[R_IX]));
-  const float dy0 = (float)(py0 - __float_as_int(rec[R_IY]));
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    st[S_D0 + k] = fmaf(dy0, rec[R_DV + k], fmaf(dx0, rec[R_DU + k], rec[R_D0 + k]));
-    st[S_DU + k] = rec[R_DU + k];
-    st[S_DV + k] = rec[R_DV + k];
-    st[S_M0 + k] = fmaf(dy0, rec[R_MV + k], fmaf(dx0, rec[R_MU + k], rec[R_M0 + k]));
-    st[S_MU + k] = rec[R_MU + k];
-    st[S_MV + k] = rec[R_MV + k];
-    st[S_RGB + k] = rec[R_RGB + k];
-  }
-  st[S_O] = rec[R_O];
-  st[S_RC] = rec[R_RC];
-  const uint32_t b0 = __float_as_uint(rec[R_BB0]), b1 = __float_as_uint(rec[R_BB1]);
-  st[S_BB0] = __int_as_float((int)(b0 & 0xffffu) - px0);
-  st[S_BB1] = __int_as_float((int)(b0 >> 16) - py0);
-  st[S_BB2] = __int_as_float((int)(b1 & 0xffffu) - px0);
-  st[S_BB3] = __int_as_float((int)(b1 >> 16) - py0);
-}
 
 // Forward staging. The forward needs, per pixel ray, only |d|^2 and |m|^2
 // (the cutoff test and alpha) and R3 . (d x m) (the depth of the maximum
@@ -483,7 +460,7 @@ __device__ __forceinline__ void fwd_tile(const TileInfo &ti, const Ws &w, const 
   __syncthreads();
   if (nfrag) atomicAdd(&s_nfrag, nfrag);
   __syncthreads();
-  if (tid == 0 && s_nfrag) atomicAdd(w.frags, (unsigned long long)s_nfrag);
+  if (tid == 0 && s_nfrag) count_add(w.frags, (unsigned long long)s_nfrag);
   if (!inside) return;
 
   // Composite (Eq. pixel_color_computation): the core front to back, then
@@ -707,7 +684,7 @@ __device__ __forceinline__ void fwd_tile_sorted(const TileInfo &ti, const Ws &w,
   __syncthreads();
   if (nb) atomicAdd(&s_nfrag, (uint32_t)nb);
   __syncthreads();
-  if (tid == 0 && s_nfrag) atomicAdd(w.frags, (unsigned long long)s_nfrag);
+  if (tid == 0 && s_nfrag) count_add(w.frags, (unsigned long long)s_nfrag);
   if (!inside) return;
   const int64_t npix = (int64_t)V.width * V.height;
   const int64_t pix = (int64_t)py * V.width + px;
@@ -800,6 +777,36 @@ __device__ __forceinline__ void bwd_fragment(float op, const float *rgb, const f
   }
 }
 
+// Writes one instance partial: the lane's moments about the tile's first
+// pixel (acc[0..5] for the d weights, acc[6..11] for the m weights) moved to
+// an origin (a, b) pixels before it (dx = lx + a: sum w dx = S_x + a S,
+// sum w dx^2 = S_xx + 2 a S_x + a^2 S, ...), then dL/do and dL/d(rgb).
+__device__ __forceinline__ void write_partial(const float *acc, float a, float b, float *dstf) {
+  float out[kPartialFloats];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const float *S = acc + 6 * h;
+    float *M = out + (h ? P_MM : P_MD);
+    M[0] = S[0];
+    M[1] = fmaf(a, S[0], S[1]);
+    M[2] = fmaf(b, S[0], S[2]);
+    M[3] = fmaf(a, fmaf(a, S[0], 2.f * S[1]), S[3]);
+    M[4] = fmaf(a, fmaf(b, S[0], S[2]), fmaf(b, S[1], S[4]));
+    M[5] = fmaf(b, fmaf(b, S[0], 2.f * S[2]), S[5]);
+  }
+  out[P_O] = acc[12];
+  out[P_C] = acc[13];
+  out[P_C + 1] = acc[14];
+  out[P_C + 2] = acc[15];
+  float4 *dst = reinterpret_cast<float4 *>(dstf);
+#pragma unroll
+  for (int k = 0; k < kPartialFloats / 4; ++k)
+    dst[k] = make_float4(out[4 * k], out[4 * k + 1], out[4 * k + 2], out[4 * k + 3]);
+}
+
+// Byte swizzle of the backward's core table rows (see bwd_tile).
+__device__ __forceinline__ constexpr int slot_swz(int q) { return ((q >> 1) & 15) << 2; }
+
 // Waves per backward workgroup. A tile's 64-instance chunks are dealt to
 // its waves round-robin, so waves whose share ends early idle until the
 // tile is done: with four waves ~25% of the wave time at 1080p; fewer waves
@@ -833,8 +840,11 @@ __device__ __forceinline__ void bwd_tile(const TileInfo &ti, const Ws &w, const 
   __shared__ float4 s_pix[NT * L::kStride / 4];
   constexpr int BW = bwd_waves<TW, TH>();
   constexpr int BT = 64 * BW;
-  // per wave, for the 8x8 block being walked: [block pixel][lane] = core
-  // index + 1 of the lane's instance at that pixel, 0 if not in the core
+  // per wave, for the 8x8 block being walked: [block pixel][lane ^ swz(pixel)]
+  // = core index + 1 of the lane's instance at that pixel, 0 if not in the
+  // core. The byte swizzle swz(q) = ((q >> 1) & 15) << 2 spreads the fill
+  // (each lane writes its own pixel's 64-byte row) over the banks; the
+  // reads (one row, one byte per lane) stay conflict-free.
   __shared__ uint8_t s_slot[BW][64][64];
 
   const ViewParams &V = vs.v[ti.v];
@@ -954,6 +964,7 @@ __device__ __forceinline__ void bwd_tile(const TileInfo &ti, const Ws &w, const 
 #pragma unroll
     for (int k = 0; k < 6; ++k) { qd[k] = 0.f; qm[k] = 0.f; }
     uint32_t slot = 0, gid = 0;
+    int ox = 0, oy = 0;   // moment origin: the record's reference pixel
     if (active) {
       gid = vals[j];
       float rec[kRecFloats];
@@ -970,7 +981,11 @@ __device__ __forceinline__ void bwd_tile(const TileInfo &ti, const Ws &w, const 
       bb[1] = (int)(b0 >> 16) - py0;
       bb[2] = (int)(b1 & 0xffffu) - px0;
       bb[3] = (int)(b1 >> 16) - py0;
-      if (myblk <= 0) slot = tslot_slot(w.tslots[(int64_t)ti.v * cfg.n + gid], ti.tx, ti.ty);
+      if (myblk <= 0) {
+        slot = tslot_slot(w.tslots[(int64_t)ti.v * cfg.n + gid], ti.tx, ti.ty);
+        ox = __float_as_int(rec[R_IX]);
+        oy = __float_as_int(rec[R_IY]);
+      }
     }
     const float bbf[4] = {__int_as_float(bb[0]), __int_as_float(bb[1]), __int_as_float(bb[2]),
                           __int_as_float(bb[3])};
@@ -998,7 +1013,7 @@ __device__ __forceinline__ void bwd_tile(const TileInfo &ti, const Ws &w, const 
           if (i < K) {
             const int ps = __float_as_int(Pp[L::kPos + i]);
             const uint32_t dl = (uint32_t)(ps - (int)(c * 64u));
-            if (ps >= 0 && dl < 64u) s_slot[wave][lane][dl] = (uint8_t)(i + 1);
+            if (ps >= 0 && dl < 64u) s_slot[wave][lane][dl ^ slot_swz(lane)] = (uint8_t)(i + 1);
           }
         }
         __builtin_amdgcn_wave_barrier();
@@ -1036,13 +1051,13 @@ __device__ __forceinline__ void bwd_tile(const TileInfo &ti, const Ws &w, const 
           const float *P0 = sp_all + ((by + row) * TW + bx + col) * L::kStride;
           if (f0) {
             ++nfr;
-            bwd_fragment<KMAX>(op, rgb, P0, col, dd0, mm0, (int)s_slot[wave][q][lane] - 1, amax,
+            bwd_fragment<KMAX>(op, rgb, P0, col, dd0, mm0, (int)s_slot[wave][q][lane ^ slot_swz(q)] - 1, amax,
                                rs, acc);
           }
           if (f1) {
             ++nfr;
             bwd_fragment<KMAX>(op, rgb, P0 + L::kStride, col + 1, dd1, mm1,
-                               (int)s_slot[wave][q + 1][lane] - 1, amax, rs, acc);
+                               (int)s_slot[wave][q + 1][lane ^ slot_swz(q + 1)] - 1, amax, rs, acc);
           }
         }
         if constexpr (BX > 1) {
@@ -1083,45 +1098,13 @@ __device__ __forceinline__ void bwd_tile(const TileInfo &ti, const Ws &w, const 
       __syncthreads();  // before the block-1 waves rebuild their tables
     }
     if (myblk <= 0 && active && (uint64_t)slot < (uint64_t)w.capacity) {
-      // Gradients of the record coefficients in camera coordinates
-      // u = (x - cx)/fx, v = (y - cy)/fy: d = D0 + u Du + v Dv with
-      // u = ut + lx/fx. The tile-corner affine coefficients come from the
-      // record again (it is still in the cache), which keeps them out of
-      // the registers during the pixel loop.
-      float rec[kRecFloats];
-      load_record(recs, gid, rec);
-      float st[S_FLOATS];
-      stage_record(rec, px0, py0, st);
-      const float ut = ((float)px0 + 0.5f - V.cx) / V.fx, vt = ((float)py0 + 0.5f - V.cy) / V.fy;
-      const float ifx = 1.f / V.fx, ify = 1.f / V.fy;
-      float out[kPartialFloats];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const float D0 = st[S_D0 + k], Du = st[S_DU + k], Dv = st[S_DV + k];
-        const float M0 = st[S_M0 + k], Mu = st[S_MU + k], Mv = st[S_MV + k];
-        const float sd = fmaf(Dv, acc[2], fmaf(Du, acc[1], D0 * acc[0]));
-        const float sdx = fmaf(Dv, acc[4], fmaf(Du, acc[3], D0 * acc[1]));
-        const float sdy = fmaf(Dv, acc[5], fmaf(Du, acc[4], D0 * acc[2]));
-        const float sm = fmaf(Mv, acc[8], fmaf(Mu, acc[7], M0 * acc[6]));
-        const float smx = fmaf(Mv, acc[10], fmaf(Mu, acc[9], M0 * acc[7]));
-        const float smy = fmaf(Mv, acc[11], fmaf(Mu, acc[10], M0 * acc[8]));
-        out[P_D0 + k] = sd;
-        out[P_DX + k] = fmaf(ut, sd, sdx * ifx);
-        out[P_DY + k] = fmaf(vt, sd, sdy * ify);
-        out[P_M0 + k] = sm;
-        out[P_MX + k] = fmaf(ut, sm, smx * ifx);
-        out[P_MY + k] = fmaf(vt, sm, smy * ify);
-      }
-      out[P_O] = acc[12];
-      out[P_C] = acc[13];
-      out[P_C + 1] = acc[14];
-      out[P_C + 2] = acc[15];
-      out[P_SEG] = __uint_as_float(((uint32_t)ti.v << 27) | gid);
-      out[23] = 0.f;
-      float4 *dst = reinterpret_cast<float4 *>(w.partials + (int64_t)slot * kPartialFloats);
-#pragma unroll
-      for (int k = 0; k < kPartialFloats / 4; ++k)
-        dst[k] = make_float4(out[4 * k], out[4 * k + 1], out[4 * k + 2], out[4 * k + 3]);
+      // The tile's moments (about its first pixel) moved to the record's
+      // reference pixel, (a, b) pixels from it (near the splat's centre,
+      // which keeps the moments small): with dx = lx + a,
+      // sum w dx = S_x + a S, sum w dx^2 = S_xx + 2 a S_x + a^2 S, ...
+      const float a = (float)(px0 - ox);
+      const float b = (float)(py0 - oy);
+      write_partial(acc, a, b, w.partials + (int64_t)slot * kPartialFloats);
     }
     __builtin_amdgcn_wave_barrier();
   }
@@ -1166,7 +1149,267 @@ __global__ void __launch_bounds__((64 * bwd_waves<TW, TH>()), (bwd_simd_waves<KM
   // past 16 and 32 KiB, one workgroup per CU fewer)
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) nfr += (uint32_t)__shfl_xor((int)nfr, off, 64);
-  if ((threadIdx.x & 63) == 0 && nfr) atomicAdd(w.frags_bwd, (unsigned long long)nfr);
+  if ((threadIdx.x & 63) == 0 && nfr) count_add(w.frags_bwd, (unsigned long long)nfr);
+}
+
+// ---------------------------------------------------------------------------
+// Backward, sorted blending
+// ---------------------------------------------------------------------------
+// Inclusive scans over the 64 lanes of a wave with DPP lane moves: shifts
+// by 1, 2, 4, 8 inside each row of 16 lanes, then lane 15 into rows 1 and 3
+// and lane 31 into rows 2 and 3. Lanes without a source take the identity.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_move(float x, float identity) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(identity), __float_as_int(x),
+                                                    CTRL, ROW_MASK, 0xf, false));
+}
+__device__ __forceinline__ float wave_scan_mul(float x) {
+  x *= dpp_move<0x111, 0xf>(x, 1.f);
+  x *= dpp_move<0x112, 0xf>(x, 1.f);
+  x *= dpp_move<0x114, 0xf>(x, 1.f);
+  x *= dpp_move<0x118, 0xf>(x, 1.f);
+  x *= dpp_move<0x142, 0xa>(x, 1.f);
+  x *= dpp_move<0x143, 0xc>(x, 1.f);
+  return x;
+}
+__device__ __forceinline__ float wave_scan_add(float x) {
+  x += dpp_move<0x111, 0xf>(x, 0.f);
+  x += dpp_move<0x112, 0xf>(x, 0.f);
+  x += dpp_move<0x114, 0xf>(x, 0.f);
+  x += dpp_move<0x118, 0xf>(x, 0.f);
+  x += dpp_move<0x142, 0xa>(x, 0.f);
+  x += dpp_move<0x143, 0xc>(x, 0.f);
+  return x;
+}
+
+// Adjoint of sorted blending. With the fragments of a pixel blended front
+// to back, C = sum_i alpha_i T_i c_i + T c_bg, T_i = prod_{k<i} (1 -
+// alpha_k):
+//   dC/dc_i = alpha_i T_i,
+//   dC/dalpha_i = T_i c_i - R_i / (1 - alpha_i),  R_i = sum_{k>i} alpha_k T_k
+//                 c_k + T c_bg = C - (sum_{k<=i} alpha_k T_k c_k).
+// The lanes of a wave hold 64 consecutive list entries (splats) of the tile
+// and walk the pixels of their 8x8 block; at a pixel a wave scan over the
+// lanes gives each lane T_i (product of 1 - alpha) and the dot product with
+// G = dL/dC of the prefix colour sum, starting from the pixel's carry of the
+// earlier chunks (kept in LDS), so the chunks of a tile run in list order.
+// A lane's fragment is differentiated iff the forward blended it: its list
+// position lies before the pixel's end position stored by the forward (the
+// same staged forms and arithmetic give the same fragment test and alpha).
+// Partials as in the hybrid backward: moments of the d and m weights, opacity
+// and colour terms, one per instance. One wave per 8x8 block; with several
+// blocks the waves add their sums in LDS and wave 0 writes the partial.
+template <int TW, int TH>
+__device__ __forceinline__ void bwd_tile_sorted(const TileInfo &ti, const Ws &w,
+                                                const ViewSet &vs, const KCfg &cfg,
+                                                const float *__restrict__ state,
+                                                const uint32_t *__restrict__ vals, uint32_t &nfr) {
+  constexpr int NT = TW * TH;
+  constexpr int NB = NT / 64;
+  constexpr int BX = TW / 8;
+  // per pixel: G (3), G . C, then end position, T carry, (G . prefix) carry
+  __shared__ float4 s_pg[NT], s_pc[NT];
+  __shared__ float s_red[NB > 1 ? NB * 16 * 64 : 1];   // [block][value][lane]
+  __shared__ int s_maxend;
+
+  const ViewParams &V = vs.v[ti.v];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int bx = (wave % BX) * 8, by = (wave / BX) * 8;
+  const int px0 = ti.tx * TW, py0 = ti.ty * TH;
+  const float *recs = w.records + (int64_t)ti.v * cfg.n * kRecFloats;
+  const int64_t npix = (int64_t)V.width * V.height;
+  if (tid == 0) s_maxend = 0;
+  __syncthreads();
+  {
+    // this thread's pixel: block `wave`, lane = row-major pixel of the block
+    const int lx = bx + (lane & 7), ly = by + (lane >> 3);
+    const int px = px0 + lx, py = py0 + ly;
+    float4 pg = make_float4(0.f, 0.f, 0.f, 0.f), pc = make_float4(0.f, 1.f, 0.f, 0.f);
+    if (px < V.width && py < V.height) {
+      const int64_t pix = (int64_t)py * V.width + px;
+      const float *sp = state + tile_state_off(V, ti, kSortedStateValues, NT) + wave * 64 + lane;
+      const float T = sp[0], S0 = sp[NT], S1 = sp[2 * NT], S2 = sp[3 * NT];
+      const int end = __float_as_int(sp[4 * NT]);
+      const float G0 = V.grad_rgb[pix], G1 = V.grad_rgb[npix + pix], G2 = V.grad_rgb[2 * npix + pix];
+      const float gC = fmaf(G2, fmaf(T, cfg.bg[2], S2), fmaf(G1, fmaf(T, cfg.bg[1], S1),
+                                                          G0 * fmaf(T, cfg.bg[0], S0)));
+      pg = make_float4(G0, G1, G2, gC);
+      pc = make_float4(__int_as_float(end), 1.f, 0.f, 0.f);
+      if (end > 0) atomicMax(&s_maxend, end);
+    }
+    s_pg[ly * TW + lx] = pg;
+    s_pc[ly * TW + lx] = pc;
+  }
+  __syncthreads();
+  const uint2 rg = w.ranges[ti.t];
+  // no pixel blends past max_end: later list entries get zero partials
+  // (every instance's slot is written, as the preprocess backward sums them)
+  const uint32_t stop = min(rg.y, rg.x + (uint32_t)s_maxend);
+  const float amax = cfg.alpha_max;
+  const int cx2 = 2 * px0 + TW - 1, cy2 = 2 * py0 + TH - 1;
+  const float hx = 0.5f * (float)(TW - 1), hy = 0.5f * (float)(TH - 1);
+  const int cols_in = V.width - (px0 + bx), rows_in = V.height - (py0 + by);
+  for (uint32_t c0 = rg.x; c0 < rg.y; c0 += 64u) {
+    const uint32_t j = c0 + lane;
+    const bool active = j < rg.y;
+    const bool work = j < stop;
+    const int pos = (int)(j - rg.x);
+    float qd[6], qm[6], rc = -1.f, op = 0.f, rgb[3] = {0.f, 0.f, 0.f};
+    int bb[4] = {1 << 20, 1 << 20, -1, -1};
+#pragma unroll
+    for (int k = 0; k < 6; ++k) { qd[k] = 0.f; qm[k] = 0.f; }
+    const uint32_t gid = active ? vals[j] : 0u;
+    int ox = 0, oy = 0;   // moment origin: the record's reference pixel
+    if (work) {
+      float rec[kRecFloats];
+      load_record(recs, gid, rec);
+      ox = __float_as_int(rec[R_IX]);
+      oy = __float_as_int(rec[R_IY]);
+      float sf[F_FLOATS];
+      stage_fwd(rec, cx2, cy2, sf);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) { qd[k] = sf[F_QD + k]; qm[k] = sf[F_QM + k]; }
+      rc = sf[F_RC];
+      op = sf[F_O];
+      rgb[0] = sf[F_R]; rgb[1] = sf[F_G]; rgb[2] = sf[F_B];
+      const uint32_t b0 = __float_as_uint(rec[R_BB0]), b1 = __float_as_uint(rec[R_BB1]);
+      bb[0] = (int)(b0 & 0xffffu) - px0;
+      bb[1] = (int)(b0 >> 16) - py0;
+      bb[2] = (int)(b1 & 0xffffu) - px0;
+      bb[3] = (int)(b1 >> 16) - py0;
+    }
+    const float bbf[4] = {__int_as_float(bb[0]), __int_as_float(bb[1]), __int_as_float(bb[2]),
+                          __int_as_float(bb[3])};
+    const bool hitb = work && rect_meets_block(bbf, bx, by);
+    float acc[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc[k] = 0.f;
+    if (__ballot(hitb) != 0ull) {
+      const float fbx = (float)bx;
+      for (int row = 0; row < 8; ++row) {
+        const float ly = (float)(by + row);
+        const float Y = ly - hy, YY = Y * Y;
+        const float rd0 = fmaf(YY, qd[5], fmaf(Y, qd[2], qd[0]));
+        const float rd1 = fmaf(Y, qd[4], qd[1]);
+        const float s2r = fmaf(qm[4], Y, qm[5]);
+        const float rm0 = fmaf(s2r, s2r, qm[0]);
+        const float rm1 = fmaf(qm[2], Y, qm[3]);
+        const bool row_in = hitb & (row < rows_in);
+        float rs[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int col = 0; col < 8; ++col) {
+          const int p = (by + row) * TW + bx + col;
+          const float4 pc = s_pc[p];
+          const float X = (fbx + (float)col) - hx;
+          const float dd = fmaf(X, rd1, fmaf(X * X, qd[3], rd0));
+          const float s1 = fmaf(qm[1], X, rm1);
+          const float mm = fmaf(s1, s1, rm0);
+          const bool f = row_in & (col < cols_in) & (dd >= FLT_MIN) & (mm <= rc * dd) &
+                         (pos < __float_as_int(pc.x));
+          if (__ballot(f) == 0ull) continue;   // uniform: no blended fragment here
+          const float4 pg = s_pg[p];
+          // alpha exactly as the forward forms it (0 off the fragments)
+          const float inv = rcp_fast(dd);
+          const float r2 = mm * inv;
+          const float e = exp2_fast(r2 * kNegHalfLog2e);
+          const float araw = op * e;
+          const bool unclamped = araw <= amax;
+          const float alpha = f ? (unclamped ? araw : amax) : 0.f;
+          const float om = 1.f - alpha;
+          const float incl = wave_scan_mul(om);
+          float excl = __shfl_up(incl, 1, 64);
+          if (lane == 0) excl = 1.f;
+          const float Ti = pc.y * excl;
+          const float gc = fmaf(pg.z, rgb[2], fmaf(pg.y, rgb[1], pg.x * rgb[0]));
+          const float term = alpha * Ti * gc;
+          const float isum = wave_scan_add(term);
+          const float gP = pc.z + isum;   // G . (colour sum up to and including i)
+          // the pixel's carries past this chunk
+          const float tot_m = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(incl), 63));
+          const float tot_s = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(isum), 63));
+          if (lane == 0) s_pc[p] = make_float4(pc.x, pc.y * tot_m, pc.z + tot_s, 0.f);
+          if (f) {
+            ++nfr;
+            const float dLda = Ti * gc - (pg.w - gP) * rcp_fast(om);
+            const float wc = alpha * Ti;
+            acc[13] = fmaf(wc, pg.x, acc[13]);
+            acc[14] = fmaf(wc, pg.y, acc[14]);
+            acc[15] = fmaf(wc, pg.z, acc[15]);
+            const float g = unclamped ? dLda : 0.f;
+            acc[12] = fmaf(g, e, acc[12]);
+            const float w1 = -alpha * g * inv;   // weight of m
+            const float w2 = -w1 * r2;           // weight of d
+            rs[0] += w2;
+            rs[3] += w1;
+            const float fc = (float)col, fc2 = (float)(col * col);
+            rs[1] = fmaf(fc, w2, rs[1]);
+            rs[2] = fmaf(fc2, w2, rs[2]);
+            rs[4] = fmaf(fc, w1, rs[4]);
+            rs[5] = fmaf(fc2, w1, rs[5]);
+          }
+        }
+        if constexpr (BX > 1) {
+          rs[2] = fmaf(fbx, fmaf(fbx, rs[0], 2.f * rs[1]), rs[2]);
+          rs[1] = fmaf(fbx, rs[0], rs[1]);
+          rs[5] = fmaf(fbx, fmaf(fbx, rs[3], 2.f * rs[4]), rs[5]);
+          rs[4] = fmaf(fbx, rs[3], rs[4]);
+        }
+        const float ly2 = ly * ly;
+        acc[0] += rs[0];
+        acc[1] += rs[1];
+        acc[2] = fmaf(ly, rs[0], acc[2]);
+        acc[3] += rs[2];
+        acc[4] = fmaf(ly, rs[1], acc[4]);
+        acc[5] = fmaf(ly2, rs[0], acc[5]);
+        acc[6] += rs[3];
+        acc[7] += rs[4];
+        acc[8] = fmaf(ly, rs[3], acc[8]);
+        acc[9] += rs[5];
+        acc[10] = fmaf(ly, rs[4], acc[10]);
+        acc[11] = fmaf(ly2, rs[3], acc[11]);
+      }
+    }
+    if constexpr (NB > 1) {
+      // the blocks' sums for each instance, added in block order
+#pragma unroll
+      for (int k = 0; k < 16; ++k) s_red[(wave * 16 + k) * 64 + lane] = acc[k];
+      __syncthreads();
+      if (wave == 0) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+          float t = s_red[k * 64 + lane];
+#pragma unroll
+          for (int b2 = 1; b2 < NB; ++b2) t += s_red[(b2 * 16 + k) * 64 + lane];
+          acc[k] = t;
+        }
+      }
+      __syncthreads();
+    }
+    if (wave == 0 && active) {
+      const int64_t vg = (int64_t)ti.v * cfg.n + gid;
+      const uint32_t slot = tslot_slot(w.tslots[vg], ti.tx, ti.ty);
+      if ((uint64_t)slot < (uint64_t)w.capacity) {
+        // (lanes past the last blended position were not staged: their
+        // moments are zero, so the origin does not matter)
+        write_partial(acc, (float)(px0 - ox), (float)(py0 - oy),
+                      w.partials + (int64_t)slot * kPartialFloats);
+      }
+    }
+  }
+}
+
+template <int TW, int TH, bool PERSIST>
+__global__ void __launch_bounds__(TW * TH)
+    k_raster_bwd_sorted(Ws w, ViewSet vs, KCfg cfg, const float *__restrict__ state,
+                        const uint32_t *__restrict__ vals) {
+  if (front_failed(w)) return;
+  uint32_t nfr = 0;
+#define HTGS_BWDS_BODY(T) bwd_tile_sorted<TW, TH>(T, w, vs, cfg, state, vals, nfr)
+  HTGS_FOR_TILES(PERSIST, kQueueBwd, HTGS_BWDS_BODY);
+#undef HTGS_BWDS_BODY
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) nfr += (uint32_t)__shfl_xor((int)nfr, off, 64);
+  if ((threadIdx.x & 63) == 0 && nfr) count_add(w.frags_bwd, (unsigned long long)nfr);
 }
 
 // ---------------------------------------------------------------------------
@@ -1305,8 +1548,29 @@ hipError_t launch_raster_fwd(const Ws &w, const ViewSet &vs, const KCfg &cfg, fl
   HTGS_DISPATCH(fwd_launch, w, vs, cfg, state, vals, s);
 }
 
+template <int TW, int TH>
+static hipError_t bwd_sorted_launch(const Ws &w, const ViewSet &vs, const KCfg &cfg,
+                                    const float *state, const uint32_t *vals, hipStream_t s) {
+  if (cfg.persistent) {
+    auto *kern = k_raster_bwd_sorted<TW, TH, true>;
+    const int blocks = resident_blocks((const void *)kern, TW * TH, vs.total_tiles);
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(TW * TH), 0, s, w, vs, cfg, state, vals);
+  } else {
+    auto *kern = k_raster_bwd_sorted<TW, TH, false>;
+    const int blocks = 8 * ((vs.total_tiles + 7) / 8);
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(TW * TH), 0, s, w, vs, cfg, state, vals);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_raster_bwd(const Ws &w, const ViewSet &vs, const KCfg &cfg, const float *state,
                              const uint32_t *vals, hipStream_t s) {
+  if (cfg.sorted) {
+    if (cfg.tile_w == 8 && cfg.tile_h == 8) return bwd_sorted_launch<8, 8>(w, vs, cfg, state, vals, s);
+    if (cfg.tile_w == 16 && cfg.tile_h == 8) return bwd_sorted_launch<16, 8>(w, vs, cfg, state, vals, s);
+    if (cfg.tile_w == 32 && cfg.tile_h == 8) return bwd_sorted_launch<32, 8>(w, vs, cfg, state, vals, s);
+    return bwd_sorted_launch<16, 16>(w, vs, cfg, state, vals, s);
+  }
   HTGS_DISPATCH(bwd_launch, w, vs, cfg, state, vals, s);
 }
 

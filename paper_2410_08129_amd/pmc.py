@@ -1,16 +1,26 @@
 """HBM traffic of the renderer's kernels from rocprofv3 counter runs.
 
-Two ``rocprofv3 --pmc`` runs of the same command (one with FETCH_SIZE, one
-with WRITE_SIZE; both report KiB per dispatch) are reduced to bytes per
+Two ``rocprofv3 --pmc`` runs of the same command are reduced to bytes per
 launch for each kernel (each entry keeps the workload and command it was
 measured with; ``--merge`` adds the kernels of another schedule to an
-existing record). Each counter is scaled by the factor that makes a
-plain elementwise copy of known size (run inside the same command) read and
-write exactly its size. The record carries a digest of the kernel sources
-it was measured on, so a reader can tell when the kernels have changed
-since.
+existing record):
 
-    python -m paper_2410_08129_amd.pmc --fetch F.csv --write W.csv \\
+* reads: the L2-to-memory read requests by size, TCC_EA0_RDREQ_32B_sum,
+  TCC_EA0_RDREQ_64B_sum and TCC_EA0_RDREQ_128B_sum (with TCC_EA0_RDREQ_sum,
+  which they should add up to); bytes = 32 n32 + 64 n64 + 128 n128. (The
+  derived FETCH_SIZE of this ROCm counts a 128-byte request as 64 bytes
+  unless the memory reported it as a bubble, so it reads half of a
+  streaming copy's bytes and the right amount of a gather of small
+  requests: no single scale factor fits every kernel.)
+* writes: TCC_EA0_WRREQ_sum and TCC_EA0_WRREQ_64B_sum; bytes = 32 (n - n64)
+  + 64 n64 (the derived WRITE_SIZE).
+
+A plain elementwise copy of known size, run inside the same command, checks
+the byte counts (its ratio is reported; nothing is scaled). The record
+carries a digest of the kernel sources it was measured on, so a reader can
+tell when the kernels have changed since.
+
+    python -m paper_2410_08129_amd.pmc --fetch R.csv --write W.csv \\
         --copy-bytes 268435456 --workload "..." --command "..." --out traffic.json
 """
 from __future__ import annotations
@@ -51,44 +61,61 @@ def source_digest(kernel: str) -> str:
 
 
 def _per_kernel(path):
-    d = collections.defaultdict(list)
+    """{kernel: {counter: [value per dispatch]}}"""
+    d = collections.defaultdict(lambda: collections.defaultdict(list))
     with open(path) as fh:
         for r in csv.DictReader(fh):
-            d[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+            d[r["Kernel_Name"]][r["Counter_Name"]].append(float(r["Counter_Value"]))
     return d
 
 
-def summarize(fetch_csv, write_csv, copy_bytes):
-    fetch, write = _per_kernel(fetch_csv), _per_kernel(write_csv)
-    # the calibration copy: the elementwise kernel whose FETCH_SIZE is
-    # closest to its known size
+def _read_bytes(c):
+    n = [c.get(f"TCC_EA0_RDREQ_{b}B_sum") for b in (32, 64, 128)]
+    if any(v is None for v in n):
+        raise SystemExit("read run lacks TCC_EA0_RDREQ_{32,64,128}B_sum")
+    return [32 * a + 64 * b + 128 * q for a, b, q in zip(*n)]
+
+
+def _write_bytes(c):
+    n, n64 = c.get("TCC_EA0_WRREQ_sum"), c.get("TCC_EA0_WRREQ_64B_sum")
+    if n is None or n64 is None:
+        raise SystemExit("write run lacks TCC_EA0_WRREQ_sum / TCC_EA0_WRREQ_64B_sum")
+    return [32 * (a - b) + 64 * b for a, b in zip(n, n64)]
+
+
+def summarize(read_csv, write_csv, copy_bytes):
+    rd, wr = _per_kernel(read_csv), _per_kernel(write_csv)
+    # the check copy: the elementwise kernel whose read bytes are closest
+    # to its known size
     best = None
-    for k, vals in fetch.items():
+    for k, c in rd.items():
         if "elementwise" not in k:
             continue
-        for i, v in enumerate(vals):
-            ratio = copy_bytes / max(v * 1024.0, 1.0)
+        for i, v in enumerate(_read_bytes(c)):
+            ratio = v / copy_bytes
             if 0.25 < ratio < 4.0 and (best is None or abs(ratio - 1.0) < abs(best[0] - 1.0)):
                 best = (ratio, k, i)
     if best is None:
-        raise SystemExit("no calibration copy found in the counter runs")
+        raise SystemExit("no check copy found in the counter runs")
     _, ck, ci = best
-    sf = copy_bytes / (fetch[ck][ci] * 1024.0)
-    sw = copy_bytes / (write[ck][ci] * 1024.0)
+    copy_read = _read_bytes(rd[ck])[ci] / copy_bytes
+    copy_write = _write_bytes(wr[ck])[ci] / copy_bytes if ck in wr else None
     kernels = {}
-    for k, vals in fetch.items():
+    for k, c in rd.items():
         name = short_name(k)
         if name not in KERNEL_SOURCES:
             continue
-        wv = write.get(k, [0.0])
+        rb = _read_bytes(c)
+        wb = _write_bytes(wr[k]) if k in wr else [0.0]
+        req = c.get("TCC_EA0_RDREQ_sum", [0.0])
+        sizes = {f"rdreq_{b}B": sum(c[f"TCC_EA0_RDREQ_{b}B_sum"]) / len(rb) for b in (32, 64, 128)}
         key = k.replace("void ", "").replace("htgs::", "").split("(")[0]
         kernels[key] = dict(
-            kernel=name, launches=len(vals),
-            fetch_kib=sum(vals) / len(vals), write_kib=sum(wv) / len(wv),
-            read_bytes=sum(vals) / len(vals) * 1024.0 * sf,
-            write_bytes=sum(wv) / len(wv) * 1024.0 * sw,
+            kernel=name, launches=len(rb), rdreq=sum(req) / len(req), **sizes,
+            read_bytes=sum(rb) / len(rb), write_bytes=sum(wb) / len(wb),
             source_sha256=source_digest(name))
-    return dict(scale_fetch=sf, scale_write=sw, copy_bytes=copy_bytes, kernels=kernels)
+    return dict(copy_check=dict(bytes=copy_bytes, read_ratio=copy_read, write_ratio=copy_write),
+                kernels=kernels)
 
 
 def traffic_for(record_path, kernel_key):

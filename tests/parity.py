@@ -271,3 +271,36 @@ def check_sorted_image(gpu_img, gpu_nb, gpu_stop, ref_img, info, order_key, st, 
                  unresolved=unresolved[:10])
     assert len(unresolved) <= max_unresolved, stats
     return stats
+
+
+def sorted_ambiguous_pixels(info, H, W, st, order_key):
+    """[H, W] bool for sorted blending: pixels holding a near-tie that
+    float32 may decide either way (a fragment within DELTA_RHO of rho^2 =
+    rho_c, an alpha within DELTA_A of the clamp, or a step of the float64
+    front-to-back transmittance within DELTA_T of tau_T); gradient windows
+    leave them out of the loss."""
+    fr = info['frags']
+    out = np.zeros(H * W, bool)
+    if fr['pix'].size == 0:
+        return out.reshape(H, W)
+    tau = float(st.tau_T)
+    for p in np.unique(fr['pix']):
+        rec = _pixel_records(fr, int(p))
+        rho2, rc = rec['rho2'], rec['rho_c']
+        if np.any(np.abs(rho2 - rc) <= DELTA_RHO * rc):
+            out[p] = True
+            continue
+        frag = rec['frag'].astype(bool)
+        if np.any(frag & (np.abs(rec['raw'] - st.alpha_max) <= DELTA_A * st.alpha_max)):
+            out[p] = True
+            continue
+        gid = rec['gid'].astype(np.int64)
+        order = [i for i in np.lexsort((gid, order_key[gid])) if frag[i]]
+        T = 1.0
+        for i in order:
+            T *= 1.0 - min(st.alpha_max, rec['raw'][i])
+            if abs(T - tau) <= DELTA_T * tau:
+                out[p] = True
+            if T < tau:
+                break
+    return out.reshape(H, W)

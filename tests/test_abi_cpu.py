@@ -45,8 +45,8 @@ def test_workspace_and_state_sizes():
     b = htgs.workspace_bytes(sc.n, cams, st, 10000)
     c = htgs.workspace_bytes(sc.n, cams, st, 20000)
     assert 0 < a < b < c
-    # 16-bit keys: 2 key buffers x 2 B + 2 value buffers x 4 B + 96 B partials
-    assert abs((c - b) - 10000 * (4 + 8 + 96)) < 4096
+    # 16-bit keys: 2 key buffers x 2 B + 2 value buffers x 4 B + 64 B partials
+    assert abs((c - b) - 10000 * (4 + 8 + 64)) < 4096
     st8 = scenes.RenderSettings(K=8)
     assert htgs.state_bytes(cams, st8) == (24 * 8 + 24) * 128 * 128
     # the state is tile-major, each tile padded to full size at the image edge

@@ -225,6 +225,18 @@ def test_gradients_match_oracle_on_subcrop(seed, tile):
     _check_grads(sub, cam, st, target)
 
 
+@pytest.mark.parametrize("seed,K,tile", [(29, 0, 8), (31, 1, 8), (37, 16, (16, 8)), (41, 32, 8),
+                                         (43, 16, 16)])
+def test_gradients_match_oracle_k_sweep(seed, K, tile):
+    """The core sizes of the paper's ablation (K = 0 is the pure tail, 16 its
+    default, 32 the largest core here) on 256-Gaussian 32x32 sub-crops."""
+    sub, cam, st, target = _subcrop(seed)
+    st.K = K
+    st.tile_w, st.tile_h = _shape(tile)
+    log(f"gradients: K={K}, seed {seed}, tile {tile}")
+    _check_grads(sub, cam, st, target)
+
+
 def test_gradients_dense_two_block_tiles():
     # Two 16x8 tiles with 1,200-1,700 instances each (a tile list of 20-27
     # 64-instance chunks shared by the pairs of backward waves). 300

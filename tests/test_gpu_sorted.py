@@ -15,7 +15,7 @@ import torch
 
 import oracle
 from paper_2410_08129_amd import htgs, scenes
-from tests import parity
+from tests import crops, parity
 
 pytestmark = pytest.mark.gpu
 
@@ -142,12 +142,101 @@ def test_sorted_persistent_and_cull_schedules_match():
             assert torch.equal(pa[k], pb[k]), (kw, k)
 
 
-def test_sorted_rejects_backward_and_batches():
+def test_sorted_rejects_batches():
     sc, cams, st = scenes.workload_small()
     st = sorted_st(st)
     params = to_dev(sc)
-    frame = gpu_forward(params, sc, cams, st)
-    with pytest.raises(htgs.HTGSError):
-        htgs.backward(params, frame, [torch.ones_like(frame.images[0])])
     with pytest.raises(htgs.HTGSError):
         htgs.forward(params, sc.sh_degree, [cams[0], cams[0]], st)
+
+
+# ---------------------------------------------------------------------------
+# Backward of sorted blending
+# ---------------------------------------------------------------------------
+
+NAMES = ("means", "log_scales", "quats", "opacity_logits", "sh")
+
+
+def _sorted_grads(sub, cam, st, target):
+    """GPU gradient (through the autograd binding) and the oracle's float64
+    autograd gradient of sum(G C) with G = sign(C_oracle - target) / (3 H W),
+    near-tie pixels left out on both sides."""
+    F64 = torch.float64
+    ps = [torch.tensor(a, dtype=F64, requires_grad=True) for a in sub.arrays()]
+    ref, info = oracle.render.render(*ps, sub.sh_degree, cam, st, cull=False, info=True)
+    refn = ref.detach().numpy()
+    G = np.sign(refn - target) / (3 * cam.width * cam.height)
+    amb = parity.sorted_ambiguous_pixels(info, cam.height, cam.width, st, order_key(sub, cam))
+    G[:, amb] = 0.0
+    (ref * torch.tensor(G, dtype=F64)).sum().backward()
+    want = [p.grad.numpy() for p in ps]
+    params = [torch.tensor(a, device="cuda", requires_grad=True) for a in sub.arrays()]
+    img = htgs.render(*params, sub.sh_degree, cam, st)
+    (img * torch.tensor(G, dtype=torch.float32, device="cuda")).sum().backward()
+    got = [p.grad.cpu().numpy() for p in params]
+    return img.detach().cpu().numpy(), refn, got, want, int(amb.sum())
+
+
+def _check(got, want):
+    for name, a, b in zip(NAMES, got, want):
+        den = np.linalg.norm(b)
+        rel = np.linalg.norm(a - b) / max(den, 1e-30)
+        elem = np.abs(a - b).max() / max(np.abs(b).max(), 1e-30)
+        log(f"  {name}: |g| {den:.3e}, rel {rel:.2e}, elem {elem:.2e}")
+        assert rel <= 1e-3 and elem <= 1e-3, name
+
+
+@pytest.mark.parametrize("seed,tile,tau_T", [
+    (7, (8, 8), 1e-4), (11, (16, 16), 1e-4), (13, (8, 8), 0.2), (17, (16, 8), 0.05),
+    (19, (32, 8), 1e-4),
+])
+def test_sorted_gradients_match_oracle_on_subcrop(seed, tile, tau_T):
+    """256 Gaussians of the 720p scene on a 32x32 window (tau_T = 0.2 stops
+    most pixels early: the gradient must stop where the image did)."""
+    sub, cam, st, target = crops.subcrop_720p(seed)
+    st = sorted_st(st, tile_w=tile[0], tile_h=tile[1], tau_T=tau_T, bg=(0.1, 0.2, 0.3))
+    log(f"sorted gradients: seed {seed}, tile {tile}, tau_T {tau_T}")
+    img, ref, got, want, n_amb = _sorted_grads(sub, cam, st, target)
+    log(f"  image max-abs {np.abs(img - ref).max():.2e}, near-tie pixels left out {n_amb}")
+    _check(got, want)
+
+
+def test_sorted_gradients_dense_tiles():
+    """Many 64-instance chunks per tile (2,400 Gaussians on 16x16 pixels):
+    each pixel's transmittance and colour carries cross the chunks of its
+    tile in list order."""
+    sub, cam, st, target = crops.subcrop_720p(23, n_sel=300, size=16)
+    sub = sub.subset(np.tile(np.arange(300), 8))
+    r = np.repeat(np.arange(8), 300)[:, None].astype(np.float32)
+    sub.means = (sub.means + r * np.array([0.003, -0.002, 0.004], np.float32)).astype(np.float32)
+    sub.opacity_logits = (sub.opacity_logits - 3.0).astype(np.float32)   # deep blending
+    for tile in ((8, 8), (16, 8)):
+        st2 = sorted_st(st, tile_w=tile[0], tile_h=tile[1], tau_T=1e-4)
+        params = to_dev(sub)
+        frame = gpu_forward(params, sub, [cam], st2)
+        keys, _, _, _ = htgs.export_bins(params, sub.sh_degree, [cam], st2, frame.ws)
+        per_tile = np.bincount(np.asarray(keys, dtype=np.int64))
+        nb = htgs.state_planes(frame)['n_blended']
+        log(f"sorted dense: tile {tile}, instances per tile {per_tile.min()}-{per_tile.max()}, "
+            f"blended per pixel up to {int(nb.max())}")
+        assert per_tile.min() > 300
+        img, ref, got, want, n_amb = _sorted_grads(sub, cam, st2, target)
+        log(f"  image max-abs {np.abs(img - ref).max():.2e}, near-tie pixels left out {n_amb}")
+        _check(got, want)
+
+
+def test_sorted_backward_counts_the_blended_fragments_and_is_deterministic():
+    sc, cams, st = scenes.workload_1080p()
+    st = sorted_st(st, tile_w=8, tile_h=8, cost_order=True, tile_cull=True)
+    params = to_dev(sc)
+    frame = gpu_forward(params, sc, cams, st)
+    G = torch.full_like(frame.images[0], 1e-6)
+    g1 = htgs.backward(params, frame, [G])
+    fwd, bwd = htgs.fragment_counts(frame.ws)
+    nb = int(htgs.state_planes(frame)['n_blended'].sum())
+    log(f"sorted 1080p: blended {nb}, forward counter {fwd}, backward {bwd}")
+    assert fwd == nb and bwd == nb
+    g2 = htgs.backward(params, frame, [G])
+    for a, b in zip(g1, g2):
+        assert torch.equal(a, b)
+        assert torch.isfinite(a).all()
