@@ -224,27 +224,30 @@ def run_single(args):
                     traffic=(round(tr["total"]) if tr else None))
     if tr:
         roofline["traffic_unit"] = "bytes/launch"
-    # HBM-bound front end (algorithmic bytes): per sort pass, keys and
-    # values read and written once; binning + sort as a whole, B_bin =
+    # HBM-bound front end (algorithmic bytes): per sort pass (its count,
+    # scan and scatter launches), keys and values read and written once;
+    # binning + sort as a whole, B_bin =
     # 8 N + I [(k+4) emit + k histogram + 2 P (k+4) sort + k ranges] + 8 tiles;
     # preprocess reads the parameters and writes record, rect and offset.
     n_tiles = tiles_x * tiles_y
     key_bits = max(1, (n_tiles - 1).bit_length())
     passes = (key_bits + 7) // 8
     kb = 2 if key_bits <= 16 else 4
-    sort_bytes_launch = n_inst * 2 * (kb + 4)
+    sort_bytes_pass = n_inst * 2 * (kb + 4)
     b_bin = 8 * sc.n + n_inst * ((kb + 4) + kb + 2 * passes * (kb + 4) + kb) + 8 * n_tiles
     b_pre = sc.n * (4 * (11 + 3 * (sc.sh_degree + 1) ** 2) + 4 * 32 + 16 + 4)
     binning = None
     if "sort" in stages:
-        gbs = sort_bytes_launch / (stages["sort"]["ms_per_launch"] * 1e-3) / 1e9
+        ms_pass = stages["sort"]["ms_per_step"] / passes
+        gbs = sort_bytes_pass / (ms_pass * 1e-3) / 1e9
         t_front = sum(stages[k]["ms_per_step"] for k in ("preprocess", "sort", "ranges")
                       if k in stages)
         gbs_front = (b_bin + b_pre) / (t_front * 1e-3) / 1e9
         t_sort = sum(stages[k]["ms_per_step"] for k in ("sort", "ranges") if k in stages)
         binning = dict(
             kernel="sort_pass", bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS,
-            unit="GB/s", frac=round(gbs / HBM_PEAK_GBS, 4), bytes_per_launch=sort_bytes_launch,
+            unit="GB/s", frac=round(gbs / HBM_PEAK_GBS, 4), bytes_per_pass=sort_bytes_pass,
+            ms_per_pass=round(ms_pass, 4),
             sort_and_ranges=dict(ms=round(t_sort, 4), bytes=n_inst * (2 * passes * (kb + 4) + kb)
                                  + 8 * n_tiles),
             front_end=dict(stages="preprocess+emit+sort+ranges", ms=round(t_front, 4),

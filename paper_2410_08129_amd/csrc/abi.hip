@@ -36,10 +36,10 @@ constexpr int64_t kMaxCapacity = (1ll << 30) - 1;
 int64_t align_up(int64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  int64_t status, total, frags, pp_look, hist, sort_look, ranges, order_hist, dhist, dlook, zero_end;
-  int64_t records, rects, tslots, refpix, cflags, order, keys0, keys1, vals0, vals1, partials;
-  int64_t dkeys0, dkeys1, dvals0, dvals1, bytes;
-  int64_t capacity, max_chunks, dmax_chunks;
+  int64_t status, total, frags, pp_look, hist, ranges, order_hist, dhist, zero_end;
+  int64_t sort_cnt, sort_start, dcnt, dstart, records, rects, tslots, refpix, cflags, order, keys0, keys1, vals0, vals1;
+  int64_t partials, dkeys0, dkeys1, dvals0, dvals1, bytes;
+  int64_t capacity, chunk_stride, dchunk_stride;
   int32_t key_bits, passes, key16, sorted;
 };
 
@@ -56,11 +56,13 @@ Layout make_layout(int64_t n, int n_views, int64_t total_tiles, int64_t capacity
   Layout L{};
   L.capacity = capacity;
   L.sorted = sorted;
-  L.dmax_chunks = sorted ? (n + kSortChunk - 1) / kSortChunk : 0;
+  // rows of the per-chunk digit-count tables: whole 256-byte lines
+  L.dchunk_stride = sorted ? (n + kSortChunk - 1) / kSortChunk : 0;
+  L.dchunk_stride = (L.dchunk_stride + 63) / 64 * 64;
   L.key_bits = bits_for(total_tiles);
   L.passes = (L.key_bits + 7) / 8;
   L.key16 = L.key_bits <= 16;
-  L.max_chunks = (capacity + kSortChunk - 1) / kSortChunk;
+  L.chunk_stride = ((capacity + kSortChunk - 1) / kSortChunk + 63) / 64 * 64;
   const int64_t kb = L.key16 ? 2 : 4;
   int64_t o = 0;
   L.status = o; o = align_up(o + 4 * kStatusWords);
@@ -68,12 +70,14 @@ Layout make_layout(int64_t n, int n_views, int64_t total_tiles, int64_t capacity
   L.frags = o; o = align_up(o + 2 * 8 * kCounterSpread * kCounterStride);  // fragment counters
   L.pp_look = o; o = align_up(o + 8 * ((n + kPreThreads - 1) / kPreThreads));
   L.hist = o; o = align_up(o + 4 * 256 * 4);
-  L.sort_look = o; o = align_up(o + (int64_t)L.passes * L.max_chunks * 256 * 4);
   L.ranges = o; o = align_up(o + 8 * total_tiles);
   L.order_hist = o; o = align_up(o + 2 * 32 * 4);
   L.dhist = o; o = align_up(o + (sorted ? 4 * 256 * 4 : 0));
-  L.dlook = o; o = align_up(o + 4 * L.dmax_chunks * 256 * 4);
   L.zero_end = o;
+  L.sort_cnt = o; o = align_up(o + (int64_t)L.passes * 256 * L.chunk_stride * 4);
+  L.sort_start = o; o = align_up(o + (int64_t)L.passes * 256 * L.chunk_stride * 4);
+  L.dcnt = o; o = align_up(o + 4 * 256 * L.dchunk_stride * 4);
+  L.dstart = o; o = align_up(o + 4 * 256 * L.dchunk_stride * 4);
   L.records = o; o = align_up(o + (int64_t)n_views * n * kRecFloats * 4);
   L.rects = o; o = align_up(o + (int64_t)n_views * n * 16);
   L.refpix = o; o = align_up(o + (int64_t)n_views * n * 4);
@@ -117,7 +121,8 @@ Ws make_ws(void *base, const Layout &L) {
   w.frags_bwd = w.frags + kCounterSpread * kCounterStride;
   w.pp_look = reinterpret_cast<unsigned long long *>(b + L.pp_look);
   w.hist = reinterpret_cast<uint32_t *>(b + L.hist);
-  w.sort_look = reinterpret_cast<uint32_t *>(b + L.sort_look);
+  w.sort_cnt = reinterpret_cast<uint32_t *>(b + L.sort_cnt);
+  w.sort_start = reinterpret_cast<uint32_t *>(b + L.sort_start);
   w.ranges = reinterpret_cast<uint2 *>(b + L.ranges);
   w.order_hist = reinterpret_cast<uint32_t *>(b + L.order_hist);
   w.order = reinterpret_cast<uint32_t *>(b + L.order);
@@ -137,12 +142,13 @@ Ws make_ws(void *base, const Layout &L) {
     w.dvals[0] = reinterpret_cast<uint32_t *>(b + L.dvals0);
     w.dvals[1] = reinterpret_cast<uint32_t *>(b + L.dvals1);
     w.dhist = reinterpret_cast<uint32_t *>(b + L.dhist);
-    w.dlook = reinterpret_cast<uint32_t *>(b + L.dlook);
+    w.dcnt = reinterpret_cast<uint32_t *>(b + L.dcnt);
+    w.dstart = reinterpret_cast<uint32_t *>(b + L.dstart);
     w.perm = w.dvals[0];   // after the four depth-sort passes
-    w.dmax_chunks = L.dmax_chunks;
+    w.dchunk_stride = L.dchunk_stride;
   }
   w.capacity = L.capacity;
-  w.max_chunks = L.max_chunks;
+  w.chunk_stride = L.chunk_stride;
   w.key_bits = L.key_bits;
   w.passes = L.passes;
   w.key16 = L.key16;
@@ -356,7 +362,7 @@ int run_front(const htgs_gaussians *g, const ViewSet &vs, const htgs_config *cfg
     HIP_TRY(launch_fill_zero(ws, L.zero_end, s));
   }
   if (L.sorted) {
-    StageTimer t(HTGS_STAGE_DEPTH_SORT, s, 5, timed);
+    StageTimer t(HTGS_STAGE_DEPTH_SORT, s, 13, timed);
     HIP_TRY(launch_depth_sort(w, g->means, g->n, vs.v[0].w2c, s));
   }
   {
@@ -364,7 +370,7 @@ int run_front(const htgs_gaussians *g, const ViewSet &vs, const htgs_config *cfg
     HIP_TRY(launch_preprocess(make_gp(g), make_kcfg(g, cfg), vs, w, s));
   }
   if (sort && L.capacity > 0) {
-    StageTimer t(HTGS_STAGE_SORT, s, L.passes, timed);
+    StageTimer t(HTGS_STAGE_SORT, s, 3 * L.passes, timed);
     HIP_TRY(launch_sort_passes(w, s));
   }
   if (sort && L.capacity > 0) {

@@ -103,7 +103,9 @@ struct Ws {
   unsigned long long *frags_bwd;  // fragments counted by the backward raster (spread)
   unsigned long long *pp_look; // preprocess look-back words, one per block
   uint32_t *hist;              // [4][256] digit histograms
-  uint32_t *sort_look;         // [passes][max_chunks][256]
+  uint32_t *sort_cnt;          // [passes][chunk_stride][256]: digit counts per chunk
+  uint32_t *sort_start;        // [passes][256][chunk_stride]: global start of each
+                               // (digit, chunk) run
   uint2 *ranges;               // [total_tiles] (start, end)
   uint32_t *order_hist;        // [2][32] cost-bucket counts and cursors
   uint32_t *order;             // [total_tiles] tiles by descending instance count
@@ -118,25 +120,26 @@ struct Ws {
   float *partials;             // [capacity][24]
   // Sorted blending: the Gaussians' mean-depth sort keys, sorted (key,
   // index) pairs (ping-pong; the final index buffer is the order the
-  // preprocess walks), its digit histograms and look-back words.
+  // preprocess walks), its digit histograms and per-chunk counts.
   uint32_t *dkeys[2];
   uint32_t *dvals[2];
   uint32_t *dhist;             // [4][256]
-  uint32_t *dlook;             // [4][dmax_chunks][256]
+  uint32_t *dcnt;              // [4][dchunk_stride][256]
+  uint32_t *dstart;            // [4][256][dchunk_stride]
   const uint32_t *perm;        // Gaussians front to back (null: index order)
-  int64_t dmax_chunks;
+  int64_t dchunk_stride;
   int64_t capacity;
-  int64_t max_chunks;
+  int64_t chunk_stride;        // words per digit row of sort_cnt (>= chunks of capacity)
   int32_t key_bits, passes, key16;
   int32_t final_buf;           // which of keys/vals holds the sorted lists
   int32_t spin_limit;          // look-back rounds before a wait gives up (< 0: at once)
 };
 
 // Look-back words: 2 flag bits on top of the value.
-constexpr uint32_t kFlagA32 = 1u << 30, kFlagP32 = 2u << 30, kMask32 = (1u << 30) - 1u;
 constexpr unsigned long long kFlagA64 = 1ull << 62, kFlagP64 = 2ull << 62,
                              kMask64 = (1ull << 62) - 1ull;
 constexpr int kSpinLimit = 1 << 22;   // default look-back rounds before giving up
+constexpr int kLookWindow = 4;         // look-back words read per round trip
 // Forward state values per pixel: K ids, K alphas, K list positions, K rgb
 // triples, T, sum alpha, sum alpha rgb (3), prod (1 - alpha).
 __host__ __device__ constexpr int state_values(int K) { return 6 * K + 6; }
@@ -146,7 +149,6 @@ __host__ __device__ constexpr int state_values(int K) { return 6 * K + 6; }
 // left out (-1: none).
 constexpr int kSortedStateValues = 7;
 
-constexpr int kLookWindow = 4;   // look-back words read per round trip
 
 // Fragment counters: kCounterSpread words, each in a 128-byte line of its
 // own, added to by workgroup blockIdx % kCounterSpread and summed when
@@ -159,32 +161,19 @@ __device__ __forceinline__ void count_add(unsigned long long *ctr, unsigned long
   atomicAdd(ctr + (blockIdx.x % kCounterSpread) * kCounterStride, v);
 }
 
-// Status word. ST_SPIN: some cross-workgroup wait gave up, so some prefix
-// is wrong; the stage bit says where (preprocess, or sort pass p), so that
-// a later launch can tell a give-up of an earlier launch (whose outputs it
-// must not trust) from one of its own concurrent workgroups.
-enum StatusBits : uint32_t {
-  ST_OVERFLOW = 1u, ST_SPIN = 2u, ST_SPIN_PRE = 1u << 8, ST_SPIN_SORT0 = 1u << 9,
-  ST_SPIN_DSORT0 = 1u << 16   // depth sort pass p of sorted blending: bit 16 + p
-};
+// Status word. ST_SPIN: the preprocess look-back (the only cross-workgroup
+// wait of the front end) gave up, so some instance positions are wrong;
+// ST_SPIN_PRE says the give-up was the preprocess's, which the sort passes
+// read to leave the unusable lists alone.
+enum StatusBits : uint32_t { ST_OVERFLOW = 1u, ST_SPIN = 2u, ST_SPIN_PRE = 1u << 8 };
 constexpr uint32_t kStatusPublic = ST_OVERFLOW | ST_SPIN;
-constexpr uint32_t kSpinDsortAll = 15u << 16;
-// give-up bits of the stages before sort pass p
-__host__ __device__ constexpr uint32_t spin_bits_before_sort(int p) {
-  return kSpinDsortAll | ST_SPIN_PRE | (((1u << p) - 1u) << 9);
-}
-// give-up bits of the depth-sort passes before pass p
-__host__ __device__ constexpr uint32_t spin_bits_before_dsort(int p) {
-  return ((1u << p) - 1u) << 16;
-}
 // Status words (512 bytes, four 128-byte cache lines). The flags word has a
 // line of its own: every workgroup of the later stages reads it, and when
-// it shared a line with the tickets that each workgroup increments, the
-// reads queued behind the atomics (a sort pass took 30% longer). [0]
-// flags; [32] preprocess ticket, [33..36] sort tickets, [37..40] depth-sort
-// tickets; [64..67] / [68..71] the raster queues.
+// it shared a line with the ticket that each workgroup increments, the
+// reads queued behind the atomics. [0] flags; [32] preprocess ticket;
+// [64..67] / [68..71] the raster queues.
 constexpr int kStatusWords = 128;
-constexpr int kTicketPre = 32, kTicketSort = 33, kDsortTicket = 37;
+constexpr int kTicketPre = 32;
 // outputs of the front end are unusable: overflow or any give-up
 __device__ __forceinline__ bool front_failed(const Ws &w) {
   return (__hip_atomic_load(&w.status[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &

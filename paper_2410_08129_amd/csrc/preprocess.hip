@@ -457,13 +457,11 @@ __global__ void __launch_bounds__(kPreThreads) k_preprocess(GaussPtrs gp, KCfg c
   // Position tid of the workgroup holds Gaussian g: the index itself, or,
   // for sorted blending, the Gaussian at that place of the front-to-back
   // order (so instances are emitted in that order, and the stable tile sort
-  // keeps it inside each tile). A give-up of the depth sort leaves no usable
-  // order: every Gaussian is then treated as culled.
+  // keeps it inside each tile).
   const int64_t pos = blk * kPreThreads + tid;
   int64_t g = pos;
   bool live = pos < cfg.n;
   if (w.perm) {
-    live = live && (ld_acq_u32(&w.status[0]) & kSpinDsortAll) == 0u;
     const uint32_t x = live ? w.perm[pos] : 0xffffffffu;
     live = live && (int64_t)x < cfg.n;
     g = live ? (int64_t)x : pos;

@@ -1,140 +1,290 @@
 // Stable LSD radix sort of the (tile key, Gaussian index) instances and the
 // per-tile ranges (Sec. 4.3: plain tile-id keys, no depth sort). The same
-// pass kernel sorts the Gaussians by the view depth of their means for
-// sorted blending (the 3DGS order that the paper's "w/o per-pixel HT"
+// passes sort the Gaussians by the view depth of their means for sorted
+// blending (the 3DGS order that the paper's "w/o per-pixel HT"
 // configuration blends in, Sec. 4.3, Table splat_eval).
 //
-// One launch per 8-bit digit. Each workgroup takes a chunk of 4096 keys (in
-// ticket order), ranks them stably inside each 64-lane wave with ballots
-// (lanes whose digits match, counted below the lane), combines the four
-// waves in LDS, publishes its digit counts for the decoupled look-back over
-// earlier chunks, and reorders the chunk by digit in LDS. The look-back gives
-// each digit's global offset; the chunk then writes its LDS copy in order,
-// so consecutive lanes store consecutive addresses of one digit's run. The
-// global digit histograms were accumulated by the preprocess launch while it
-// emitted the keys, so a pass reads its keys and values once and writes them
-// once.
+// Three launches per 8-bit digit, none of whose workgroups waits for
+// another. The keys are cut into chunks of 4096 in list order.
+//   count:   each workgroup counts the digits of its chunk (LDS adds) and
+//            stores the 256 counts as the chunk's line of a count table;
+//   scan:    one workgroup per digit turns the digit's chunk counts into the
+//            global start of the digit's run from each chunk (the digit's
+//            base is the sum of the smaller digits' totals, which the
+//            preprocess counted while it emitted the keys);
+//   scatter: each workgroup ranks its chunk again, stably within each wave
+//            by ballots, reorders it by digit in LDS and writes every
+//            digit's run at the start the scan gave it, so consecutive
+//            lanes store consecutive addresses.
+// A pass reads its keys twice and its values once and writes both once.
 #include "common.h"
 
 namespace htgs {
 
 constexpr int kSortWaves = kSortThreads / 64;
+constexpr int kScanItems = 8;   // chunk counts per thread per round of the scan
 
-// What one sort pass works on: the item count (a device word, or a fixed
-// number), the capacity beyond which nothing is sorted, the global digit
-// histograms, look-back words and tickets of its passes, and the status
-// bits that cancel a pass (a give-up of an earlier stage) or that a give-up
-// of this pass sets.
+// What a sort works on: the item count (a device word, or a fixed number),
+// the capacity beyond which nothing is sorted, the global digit histograms,
+// the per-chunk count table and the status bits of earlier stages that
+// leave nothing usable to sort.
 struct SortJob {
   const unsigned long long *count;  // null: n_fixed items
   uint64_t n_fixed;
   int64_t capacity;
   const uint32_t *hist;             // [passes][256]
-  uint32_t *look;                   // [passes][max_chunks][256]
-  uint32_t *tickets;                // one per pass
-  uint32_t *status;
-  int64_t max_chunks;
-  uint32_t cancel[4];               // per pass
-  uint32_t spin[4];                 // per pass
-  int32_t spin_limit;
+  uint32_t *cnt;                    // [passes][stride][256]: digit counts per chunk
+  uint32_t *start;                  // [passes][256][stride]: global start per (digit, chunk)
+  int64_t stride;
+  const uint32_t *status;
+  uint32_t cancel;
 };
 
+// Items to sort, or false when there is nothing usable: on overflow only
+// part of the keys exist while the histograms count all of them, and after
+// a give-up of the preprocess the keys are not the counted ones (the
+// status word reports both).
+__device__ __forceinline__ bool sort_items(const SortJob &job, uint64_t &items) {
+  const unsigned long long tot = job.count ? *job.count : job.n_fixed;
+  if (tot > (unsigned long long)job.capacity) return false;
+  if (job.cancel && (ld_acq_u32(&job.status[0]) & job.cancel)) return false;
+  items = tot;
+  return true;
+}
+
+// Lanes of the wave whose digit equals this lane's, among the lanes of
+// `valid`: one ballot per digit bit (bits at and above nbits are zero in
+// every key), and a lane differs from this one where a ballot bit differs
+// from this lane's own bit.
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t valid, int nbits) {
+  uint32_t xlo = 0u, xhi = 0u;
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    if (b < nbits) {  // uniform
+      const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe((int)d, b, 1);  // all ones where set
+      const uint64_t bal = __ballot((int32_t)m < 0);
+      xlo |= (uint32_t)bal ^ m;
+      xhi |= (uint32_t)(bal >> 32) ^ m;
+    }
+  }
+  return valid & ~(((uint64_t)xhi << 32) | (uint64_t)xlo);
+}
+
+__device__ __forceinline__ uint32_t digit_of(uint32_t key, int shift) { return (key >> shift) & 255u; }
+
+// Inclusive sum over the lanes of a wave by DPP moves (shifts by 1, 2, 4, 8
+// inside each row of 16 lanes, then the row ends broadcast to the rows
+// after them); lanes whose source is outside receive 0.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROW_MASK, 0xf, false);
+}
+__device__ __forceinline__ uint32_t wave_incl_add(uint32_t x) {
+  x += dpp_u32<0x111, 0xf>(x);
+  x += dpp_u32<0x112, 0xf>(x);
+  x += dpp_u32<0x114, 0xf>(x);
+  x += dpp_u32<0x118, 0xf>(x);
+  x += dpp_u32<0x142, 0xa>(x);
+  x += dpp_u32<0x143, 0xc>(x);
+  return x;
+}
+
+// base[i] with a 32-bit byte offset (i * sizeof(T) < 2^32), so that the load
+// takes the base in scalar registers and one 32-bit offset register
+template <typename T>
+__device__ __forceinline__ T load_at(const T *base, uint32_t i) {
+  return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) +
+                                      (uint32_t)(i * (uint32_t)sizeof(T)));
+}
+
 template <typename KeyT>
-__global__ void __launch_bounds__(kSortThreads) k_sort_pass(SortJob job, int pass, int nbits,
-                                                             const KeyT *__restrict__ kin,
-                                                             const uint32_t *__restrict__ vin,
-                                                             KeyT *__restrict__ kout,
-                                                             uint32_t *__restrict__ vout) {
+__global__ void __launch_bounds__(kSortThreads) k_sort_count(SortJob job, int pass, int nbits,
+                                                              const KeyT *__restrict__ kin) {
+  __shared__ uint32_t s_cnt[256];
+  uint64_t I;
+  if (!sort_items(job, I)) return;
+  const uint64_t chunk = blockIdx.x;
+  const uint64_t cbase = chunk * kSortChunk;
+  if (cbase >= I) return;  // uniform over the workgroup
+  const int tid = threadIdx.x, lane = tid & 63;
+  s_cnt[tid] = 0u;
+  const int shift = 8 * pass;
+  uint32_t dg[kSortItems];
+  const bool whole = cbase + kSortChunk <= I;
+  if (whole) {
+    // the order of the keys does not matter here: 16-byte loads
+    constexpr int kPer = 16 / (int)sizeof(KeyT);
+    const uint4 *src = reinterpret_cast<const uint4 *>(kin + cbase);
+#pragma unroll
+    for (int j = 0; j < kSortItems / kPer; ++j) {
+      const uint4 q = src[j * kSortThreads + tid];
+      const uint32_t u[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        if constexpr (sizeof(KeyT) == 2) {
+          dg[j * kPer + 2 * h] = digit_of(u[h] & 0xffffu, shift);
+          dg[j * kPer + 2 * h + 1] = digit_of(u[h] >> 16, shift);
+        } else {
+          dg[j * kPer + h] = digit_of(u[h], shift);
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+      const uint64_t idx = cbase + (uint64_t)i * kSortThreads + tid;
+      dg[i] = idx < I ? digit_of((uint32_t)kin[idx], shift) : 0u;
+    }
+  }
+  __syncthreads();
+  // One LDS add per key; a wave whose keys share one digit adds once.
+#pragma unroll
+  for (int i = 0; i < kSortItems; ++i) {
+    const bool valid = whole || cbase + (uint64_t)i * kSortThreads + tid < I;
+    const uint32_t first = __builtin_amdgcn_readfirstlane(dg[i]);
+    if (whole && __ballot(dg[i] != first) == 0ull) {
+      if (lane == 0) atomicAdd(&s_cnt[first], 64u);
+    } else if (valid) {
+      atomicAdd(&s_cnt[dg[i]], 1u);
+    }
+  }
+  __syncthreads();
+  job.cnt[((size_t)pass * (size_t)job.stride + chunk) * 256 + tid] = s_cnt[tid];
+}
+
+// One workgroup per digit: exclusive scan of the digit's counts over the
+// chunks (a column of the chunk-major count table, so that the count
+// launch writes whole lines), plus the digit's base, written as the digit's
+// row of the start table (read by the scatter launch).
+__global__ void __launch_bounds__(256) k_sort_scan(SortJob job, int pass) {
+  __shared__ uint32_t s_wsum[4];
+  __shared__ uint32_t s_base;
+  uint64_t I;
+  if (!sort_items(job, I)) return;
+  const uint64_t nchunks = (I + kSortChunk - 1) / kSortChunk;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint32_t dg = blockIdx.x;
+  // base: the totals of the digits below this one
+  const uint32_t x = tid < (int)dg ? job.hist[pass * 256 + tid] : 0u;
+  const uint32_t wx = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_add(x), 63);
+  if (lane == 0) s_wsum[wave] = wx;
+  __syncthreads();
+  if (tid == 0) s_base = s_wsum[0] + s_wsum[1] + s_wsum[2] + s_wsum[3];
+  __syncthreads();
+  uint32_t carry = s_base;
+  const uint32_t *col = job.cnt + (size_t)pass * (size_t)job.stride * 256 + dg;
+  uint32_t *row = job.start + ((size_t)pass * 256 + dg) * (size_t)job.stride;
+  for (uint64_t c0 = 0; c0 < nchunks; c0 += 256 * kScanItems) {
+    const uint64_t cb = c0 + (uint64_t)tid * kScanItems;
+    uint32_t v[kScanItems];
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) v[j] = cb + j < nchunks ? col[(cb + j) * 256] : 0u;
+    uint32_t sum = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) sum += v[j];
+    const uint32_t inc = wave_incl_add(sum);
+    __syncthreads();   // the previous round's readers of s_wsum are done
+    if (lane == 63) s_wsum[wave] = inc;
+    __syncthreads();
+    uint32_t run = carry + inc - sum;
+    for (int k = 0; k < wave; ++k) run += s_wsum[k];
+    uint32_t out[kScanItems];
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) { out[j] = run; run += v[j]; }
+    if (cb + kScanItems <= nchunks) {
+      *reinterpret_cast<uint4 *>(row + cb) = make_uint4(out[0], out[1], out[2], out[3]);
+      *reinterpret_cast<uint4 *>(row + cb + 4) = make_uint4(out[4], out[5], out[6], out[7]);
+    } else {
+#pragma unroll
+      for (int j = 0; j < kScanItems; ++j)
+        if (cb + j < nchunks) row[cb + j] = out[j];
+    }
+    carry += s_wsum[0] + s_wsum[1] + s_wsum[2] + s_wsum[3];
+  }
+}
+
+template <typename KeyT>
+__global__ void __launch_bounds__(kSortThreads) k_sort_scatter(SortJob job, int pass, int nbits,
+                                                                const KeyT *__restrict__ kin,
+                                                                const uint32_t *__restrict__ vin,
+                                                                KeyT *__restrict__ kout,
+                                                                uint32_t *__restrict__ vout) {
   static_assert(kSortThreads == 256, "one thread per digit");
   __shared__ uint32_t s_wh[kSortWaves][256];  // per wave and digit: count, then local offset
   __shared__ uint32_t s_off[256];             // global position of local slot 0, per digit
-  __shared__ uint32_t s_wsum[kSortWaves];
   __shared__ uint32_t s_csum[kSortWaves];
-  __shared__ uint32_t s_ticket;
   __shared__ KeyT s_key[kSortChunk];
   __shared__ uint32_t s_val[kSortChunk];
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const unsigned long long tot = job.count ? *job.count : job.n_fixed;
-  // On overflow only part of the keys exist while the histograms count all
-  // of them; after a give-up of the preprocess or an earlier pass the keys
-  // (and their slots) are not the counted ones. Nothing is sorted then, and
-  // the status word reports why. (A give-up inside this pass only moves
-  // positions down within [0, I): every later launch sees its flag.)
-  if (tot > (unsigned long long)job.capacity) return;
-  if (ld_acq_u32(&job.status[0]) & job.cancel[pass]) return;
-  const uint64_t I = tot;
-  const uint64_t nchunks = (I + kSortChunk - 1) / kSortChunk;
-  if (tid == 0) s_ticket = atomicAdd(&job.tickets[pass], 1u);
-  for (int i = tid; i < kSortWaves * 256; i += kSortThreads) (&s_wh[0][0])[i] = 0u;
-
-  // Exclusive scan of the global digit histogram of this pass.
-  const uint32_t hv = job.hist[pass * 256 + tid];
-  uint32_t x = hv;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const uint32_t y = __shfl_up(x, off, 64);
-    if (lane >= off) x += y;
-  }
-  if (lane == 63) s_wsum[wave] = x;
-  __syncthreads();
-  uint32_t woff = 0;
-  for (int k = 0; k < wave; ++k) woff += s_wsum[k];
-  const uint32_t digit_excl = x + woff - hv;
-  const uint64_t chunk = s_ticket;
-  if (chunk >= nchunks) return;  // uniform over the workgroup
-
-  const int shift = 8 * pass;
+  uint64_t I;
+  if (!sort_items(job, I)) return;
+  const uint64_t chunk = blockIdx.x;
   const uint64_t cbase = chunk * kSortChunk;
-  const uint64_t wbase = cbase + (uint64_t)wave * (64 * kSortItems);
-  KeyT key[kSortItems];
+  if (cbase >= I) return;  // uniform over the workgroup
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // global start of this chunk's run of digit tid (from the scan)
+  const uint32_t run_start = job.start[((size_t)pass * 256 + tid) * (size_t)job.stride + chunk];
+  for (int i = tid; i < kSortWaves * 256; i += kSortThreads) (&s_wh[0][0])[i] = 0u;
+  __syncthreads();
+
+  // Items of the chunk: nv; lane l of wave w holds item w 1024 + 64 i + l
+  // as its i-th (out-of-range lanes read the last item and take no part).
+  const uint32_t nv = (I - cbase) < (uint64_t)kSortChunk ? (uint32_t)(I - cbase) : (uint32_t)kSortChunk;
+  const int shift = 8 * pass;
+  const uint32_t obase = (uint32_t)wave * (64 * kSortItems) + (uint32_t)lane;
+  const KeyT *kc = kin + cbase;
+  const uint32_t *vc = vin + cbase;
+  uint32_t kx[kSortItems];   // the keys (widened)
   uint32_t val[kSortItems];
   uint32_t rank[kSortItems];
   const uint64_t lanemask_lt = (1ull << lane) - 1ull;
+  // item i of this lane exists iff 64 i < rem
+  const int rem = (int)nv - (int)obase;
+  if (nv == (uint32_t)kSortChunk) {
+    const KeyT *kp = kc + obase;
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) kx[i] = kp[64 * i];
+  } else {
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) kx[i] = load_at(kc, min(obase + 64u * i, nv - 1u));
+  }
+  // Rank: lanes with the same digit are ranked by lane; the lowest of them
+  // adds their number to the wave's counter of the digit and hands the old
+  // value to the others. One wave's LDS atomics are applied in issue order,
+  // so item i's add is seen by item i + 1's and the ranks follow the list.
+  // (all adds first, then the hand-overs, so that the adds' round trips
+  // overlap)
+  // The leader lane and the rank among the peers (6 bits each) wait in the
+  // upper half of a 16-bit key's register, or in a register of their own.
+  constexpr bool kPack = sizeof(KeyT) == 2;
+  uint32_t lead[kPack ? 1 : kSortItems];
 #pragma unroll
   for (int i = 0; i < kSortItems; ++i) {
-    const uint64_t idx = wbase + (uint64_t)i * 64 + lane;
-    const bool valid = idx < I;
-    key[i] = valid ? kin[idx] : (KeyT)0;
-    val[i] = valid ? vin[idx] : 0u;
+    const bool valid = 64 * i < rem;
+    const uint32_t d = digit_of(kx[i], shift);
+    const uint64_t peers = match_digit(d, __ballot(valid), nbits);
+    const uint32_t lt = (uint32_t)__popcll(peers & lanemask_lt);
+    uint32_t old = 0;
+    if (valid && lt == 0) old = atomicAdd(&s_wh[wave][d], (uint32_t)__popcll(peers));
+    rank[i] = old;
+    const uint32_t ld = (valid ? (uint32_t)__builtin_ctzll(peers) : (uint32_t)lane) | (lt << 6);
+    if constexpr (kPack) kx[i] |= ld << 16;
+    else lead[i] = ld;
   }
 #pragma unroll
   for (int i = 0; i < kSortItems; ++i) {
-    const uint64_t idx = wbase + (uint64_t)i * 64 + lane;
-    const bool valid = idx < I;
-    const uint32_t d = ((uint32_t)key[i] >> shift) & 255u;
-    uint64_t peers = __ballot(valid);
-    for (int b = 0; b < nbits; ++b) {
-      const bool bit = (d >> b) & 1u;
-      const uint64_t bal = __ballot(bit);
-      peers &= bit ? bal : ~bal;
-    }
-    const uint32_t lt = (uint32_t)__popcll(peers & lanemask_lt);
-    uint32_t old = 0;
-    if (valid) old = s_wh[wave][d];
-    rank[i] = old + lt;
-    // Lanes of one wave reach LDS in issue order, so the leader's update is
-    // seen by the next item's reads without a barrier.
-    if (valid && lt == 0) s_wh[wave][d] = old + (uint32_t)__popcll(peers);
-    __builtin_amdgcn_wave_barrier();
+    const uint32_t ld = kPack ? kx[i] >> 16 : lead[kPack ? 0 : i];
+    rank[i] = (uint32_t)__shfl(rank[i], (int)(ld & 63u), 64) + (ld >> 6);
   }
   __syncthreads();
 
-  // Per digit (thread d): counts of the chunk, published at once for the
-  // successors' look-back; the local start of each digit is the exclusive
-  // scan of the counts over digits.
+  // Per digit (thread d): the chunk's count; the local start of each digit
+  // is the exclusive scan of the counts over digits.
   const int d = tid;
   uint32_t cnt = 0;
 #pragma unroll
   for (int k = 0; k < kSortWaves; ++k) cnt += s_wh[k][d];
-  uint32_t *look = job.look + ((size_t)pass * (size_t)job.max_chunks) * 256;
-  st_rel_u32(&look[chunk * 256 + d], (chunk == 0 ? kFlagP32 : kFlagA32) | cnt);
-  uint32_t c = cnt;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const uint32_t y = __shfl_up(c, off, 64);
-    if (lane >= off) c += y;
-  }
+  const uint32_t c = wave_incl_add(cnt);
   if (lane == 63) s_csum[wave] = c;
   __syncthreads();
   uint32_t local_start = c - cnt;
@@ -148,67 +298,65 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_pass(SortJob job, int pas
       run += v;
     }
   }
+  // position of local slot p of digit d: run_start + (p - local_start)
+  s_off[d] = run_start - local_start;
   __syncthreads();
 
-  // Reorder the chunk by digit in LDS.
+  // Reorder the chunk by digit in LDS (the values are loaded only now, which
+  // keeps the ranking's register count down).
+  // (an opaque copy of the keys: otherwise the compiler keeps every item's
+  // LDS address of the ranking live until here)
+  if (nv == (uint32_t)kSortChunk) {
+    const uint32_t *vp = vc + obase;
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) val[i] = vp[64 * i];
+  } else {
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) val[i] = load_at(vc, min(obase + 64u * i, nv - 1u));
+  }
 #pragma unroll
   for (int i = 0; i < kSortItems; ++i) {
-    const uint64_t idx = wbase + (uint64_t)i * 64 + lane;
-    if (idx < I) {
-      const uint32_t dd = ((uint32_t)key[i] >> shift) & 255u;
-      const uint32_t lp = s_wh[wave][dd] + rank[i];
-      s_key[lp] = key[i];
+    if (64 * i < rem) {
+      uint32_t kk = kPack ? (kx[i] & 0xffffu) : kx[i];
+      asm volatile("" : "+v"(kk));
+      const uint32_t lp = s_wh[wave][digit_of(kk, shift)] + rank[i];
+      s_key[lp] = (KeyT)kk;
       s_val[lp] = val[i];
     }
   }
-
-  // Look-back over earlier chunks for this digit's global offset, reading
-  // kLookWindow predecessors per round trip.
-  uint32_t excl = 0;
-  if (chunk > 0) {
-    int64_t j = (int64_t)chunk - 1;
-    int spins = 0;
-    while (true) {
-      if (spins > job.spin_limit) {  // give up (a negative limit: at once)
-        atomicOr(&job.status[0], job.spin[pass]);
-        break;
-      }
-      uint32_t sv[kLookWindow];
-#pragma unroll
-      for (int k = 0; k < kLookWindow; ++k)
-        sv[k] = (j - k >= 0) ? ld_acq_u32(&look[(j - k) * 256 + d]) : 0u;
-      int used = 0;
-      bool done = false;
-#pragma unroll
-      for (int k = 0; k < kLookWindow; ++k) {
-        if (done || used < k) continue;      // stop at the first P or unpublished word
-        const uint32_t f = sv[k] >> 30;
-        if (f == 0) continue;
-        excl += sv[k] & kMask32;
-        used = k + 1;
-        done = (f == 2);
-      }
-      if (done) break;
-      j -= used;
-      if (used == 0) {
-        ++spins;
-        __builtin_amdgcn_s_sleep(1);
-      }
-    }
-    st_rel_u32(&look[chunk * 256 + d], kFlagP32 | (excl + cnt));
-  }
-  // position of local slot p of digit d: digit_excl + excl + (p - local_start)
-  s_off[d] = digit_excl + excl - local_start;
   __syncthreads();
 
-  const uint64_t left = I - cbase;
-  const int n_local = left < (uint64_t)kSortChunk ? (int)left : kSortChunk;
-  for (int p = tid; p < n_local; p += kSortThreads) {
+  for (int p = tid; p < (int)nv; p += kSortThreads) {
     const KeyT k = s_key[p];
-    const uint32_t pos = s_off[((uint32_t)k >> shift) & 255u] + (uint32_t)p;
-    kout[pos] = k;
-    vout[pos] = s_val[p];
+    const uint32_t pos = s_off[digit_of((uint32_t)k, shift)] + (uint32_t)p;
+    if (pos < I) {  // always, when the counts match the emitted keys
+      kout[pos] = k;
+      vout[pos] = s_val[p];
+    }
   }
+}
+
+// The three launches of each pass; blocks: the largest chunk count the
+// item count can reach.
+template <typename KeyT>
+static hipError_t sort_passes(const SortJob &job, int passes, int key_bits, int64_t blocks,
+                              void *const *keys, uint32_t *const *vals, hipStream_t s) {
+  if (blocks < 1) blocks = 1;
+  for (int p = 0; p < passes; ++p) {
+    const int nbits = (key_bits - 8 * p) < 8 ? (key_bits - 8 * p) : 8;
+    const KeyT *kin = reinterpret_cast<const KeyT *>(keys[p & 1]);
+    KeyT *kout = reinterpret_cast<KeyT *>(keys[(p + 1) & 1]);
+    hipLaunchKernelGGL(k_sort_count<KeyT>, dim3((uint32_t)blocks), dim3(kSortThreads), 0, s, job, p,
+                       nbits, kin);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sort_scan, dim3(256), dim3(256), 0, s, job, p);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sort_scatter<KeyT>, dim3((uint32_t)blocks), dim3(kSortThreads), 0, s, job,
+                       p, nbits, kin, vals[p & 1], kout, vals[(p + 1) & 1]);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // Per-tile [start, end): each thread takes 8 consecutive sorted keys (one
@@ -320,26 +468,13 @@ static hipError_t sort_impl(const Ws &w, hipStream_t s) {
   job.count = w.total;
   job.capacity = w.capacity;
   job.hist = w.hist;
-  job.look = w.sort_look;
-  job.tickets = w.status + kTicketSort;
+  job.cnt = w.sort_cnt;
+  job.start = w.sort_start;
+  job.stride = w.chunk_stride;
   job.status = w.status;
-  job.max_chunks = w.max_chunks;
-  job.spin_limit = w.spin_limit;
-  for (int p = 0; p < 4; ++p) {
-    job.cancel[p] = spin_bits_before_sort(p);
-    job.spin[p] = (uint32_t)ST_SPIN | ((uint32_t)ST_SPIN_SORT0 << p);
-  }
-  const int blocks = (int)(w.max_chunks > 0 ? w.max_chunks : 1);
-  for (int p = 0; p < w.passes; ++p) {
-    const int nbits = (w.key_bits - 8 * p) < 8 ? (w.key_bits - 8 * p) : 8;
-    const KeyT *kin = reinterpret_cast<const KeyT *>(w.keys[p & 1]);
-    KeyT *kout = reinterpret_cast<KeyT *>(w.keys[(p + 1) & 1]);
-    hipLaunchKernelGGL(k_sort_pass<KeyT>, dim3(blocks), dim3(kSortThreads), 0, s, job, p, nbits,
-                       kin, w.vals[p & 1], kout, w.vals[(p + 1) & 1]);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
+  job.cancel = ST_SPIN_PRE;
+  return sort_passes<KeyT>(job, w.passes, w.key_bits, (w.capacity + kSortChunk - 1) / kSortChunk,
+                           w.keys, w.vals, s);
 }
 
 // Sort key of sorted blending: the view depth of the mean, the third row of
@@ -392,24 +527,13 @@ hipError_t launch_depth_sort(const Ws &w, const float *means, int64_t n, const f
   job.n_fixed = (uint64_t)n;
   job.capacity = n;
   job.hist = w.dhist;
-  job.look = w.dlook;
-  job.tickets = w.status + kDsortTicket;
+  job.cnt = w.dcnt;
+  job.start = w.dstart;
+  job.stride = w.dchunk_stride;
   job.status = w.status;
-  job.max_chunks = w.dmax_chunks;
-  job.spin_limit = w.spin_limit;
-  for (int p = 0; p < 4; ++p) {
-    job.cancel[p] = spin_bits_before_dsort(p);
-    job.spin[p] = (uint32_t)ST_SPIN | ((uint32_t)ST_SPIN_DSORT0 << p);
-  }
-  const int sblocks = (int)((n + kSortChunk - 1) / kSortChunk);
-  for (int p = 0; p < 4; ++p) {
-    hipLaunchKernelGGL(k_sort_pass<uint32_t>, dim3(sblocks), dim3(kSortThreads), 0, s, job, p, 8,
-                       w.dkeys[p & 1], w.dvals[p & 1], w.dkeys[(p + 1) & 1],
-                       w.dvals[(p + 1) & 1]);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
+  job.cancel = 0u;
+  void *keys[2] = {w.dkeys[0], w.dkeys[1]};
+  return sort_passes<uint32_t>(job, 4, 32, (n + kSortChunk - 1) / kSortChunk, keys, w.dvals, s);
 }
 
 template <typename KeyT>
