@@ -45,8 +45,7 @@ enum {
 
 /* Status flags reported by htgs_read_status(). */
 enum {
-  HTGS_STATUS_OVERFLOW = 1u,      /* instance count exceeded the capacity; outputs invalid */
-  HTGS_STATUS_SPIN_TIMEOUT = 2u   /* a cross-workgroup wait gave up; outputs invalid */
+  HTGS_STATUS_OVERFLOW = 1u       /* instance count exceeded the capacity; outputs invalid */
 };
 
 #define HTGS_MAX_VIEWS 16
@@ -332,24 +331,17 @@ int htgs_debug_export_bins(const htgs_gaussians *g, const htgs_camera *cams, int
 int htgs_opacity_decay(float *opacity_logits, int64_t n, double lambda, void *stream);
 
 /* Debugging and testing.
- * htgs_debug_set_spin_limit: look-back rounds (each one memory round trip
- *   and a short sleep) after which a workgroup waiting for its
- *   predecessors' prefix gives up, default 4,194,304; a negative value makes
- *   every wait give up at once. A give-up sets HTGS_STATUS_SPIN_TIMEOUT:
- *   every later stage of the call then treats the lists as empty (the image
- *   is the background, gradients are zero) and no kernel reads or writes
- *   out of bounds. Host-side setting for later calls; not thread-safe.
  * htgs_debug_fragment_counts: fragments (pixel-Gaussian pairs with
  *   rho^2 <= rho_c) counted by the last forward raster on ws and by the
  *   backward rasters since that forward. SYNCHRONISES the stream. */
-int htgs_debug_set_spin_limit(int32_t limit);
 int htgs_debug_fragment_counts(const void *ws, int64_t ws_bytes, int64_t *forward_out,
                                int64_t *backward_out, void *stream);
 
 /* Static description of an error code. */
 const char *htgs_strerror(int code);
 
-/* ABI version, currently 3 (htgs_config gained tau_T). */
+/* ABI version, currently 4 (htgs_debug_set_spin_limit removed: no launch
+ * waits across workgroups any more). */
 int htgs_version(void);
 
 #ifdef __cplusplus

@@ -28,15 +28,12 @@ hipError_t launch_raster_bwd(const Ws &w, const ViewSet &vs, const KCfg &cfg, co
 namespace {
 
 constexpr int64_t kAlign = 256;
-// Look-back rounds before a cross-workgroup wait gives up (a debug entry
-// point lowers it; negative: give up at once).
-int32_t g_spin_limit = kSpinLimit;
 constexpr int64_t kMaxCapacity = (1ll << 30) - 1;
 
 int64_t align_up(int64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  int64_t status, total, frags, pp_look, hist, ranges, order_hist, dhist, zero_end;
+  int64_t status, total, frags, pp_total, hist, ranges, order_hist, dhist, zero_end;
   int64_t sort_cnt, sort_start, dcnt, dstart, records, rects, tslots, refpix, cflags, order, keys0, keys1, vals0, vals1;
   int64_t partials, dkeys0, dkeys1, dvals0, dvals1, bytes;
   int64_t capacity, chunk_stride, dchunk_stride;
@@ -68,11 +65,11 @@ Layout make_layout(int64_t n, int n_views, int64_t total_tiles, int64_t capacity
   L.status = o; o = align_up(o + 4 * kStatusWords);
   L.total = o; o = align_up(o + 8);   // instance count
   L.frags = o; o = align_up(o + 2 * 8 * kCounterSpread * kCounterStride);  // fragment counters
-  L.pp_look = o; o = align_up(o + 8 * ((n + kPreThreads - 1) / kPreThreads));
-  L.hist = o; o = align_up(o + 4 * 256 * 4);
+  L.pp_total = o; o = align_up(o + 8 * ((n + kPreThreads - 1) / kPreThreads));
+  L.hist = o; o = align_up(o + kHistCopies * 4 * 256 * 4);
   L.ranges = o; o = align_up(o + 8 * total_tiles);
   L.order_hist = o; o = align_up(o + 2 * 32 * 4);
-  L.dhist = o; o = align_up(o + (sorted ? 4 * 256 * 4 : 0));
+  L.dhist = o; o = align_up(o + (sorted ? kHistCopies * 4 * 256 * 4 : 0));
   L.zero_end = o;
   L.sort_cnt = o; o = align_up(o + (int64_t)L.passes * 256 * L.chunk_stride * 4);
   L.sort_start = o; o = align_up(o + (int64_t)L.passes * 256 * L.chunk_stride * 4);
@@ -119,7 +116,7 @@ Ws make_ws(void *base, const Layout &L) {
   w.total = reinterpret_cast<unsigned long long *>(b + L.total);
   w.frags = reinterpret_cast<unsigned long long *>(b + L.frags);
   w.frags_bwd = w.frags + kCounterSpread * kCounterStride;
-  w.pp_look = reinterpret_cast<unsigned long long *>(b + L.pp_look);
+  w.pp_total = reinterpret_cast<unsigned long long *>(b + L.pp_total);
   w.hist = reinterpret_cast<uint32_t *>(b + L.hist);
   w.sort_cnt = reinterpret_cast<uint32_t *>(b + L.sort_cnt);
   w.sort_start = reinterpret_cast<uint32_t *>(b + L.sort_start);
@@ -153,7 +150,6 @@ Ws make_ws(void *base, const Layout &L) {
   w.passes = L.passes;
   w.key16 = L.key16;
   w.final_buf = L.passes & 1;
-  w.spin_limit = g_spin_limit;
   return w;
 }
 
@@ -502,7 +498,7 @@ using namespace htgs;
 
 extern "C" {
 
-int htgs_version(void) { return 3; }
+int htgs_version(void) { return 4; }
 
 const char *htgs_strerror(int code) {
   switch (code) {
@@ -628,7 +624,7 @@ int htgs_read_status(const void *ws, int64_t ws_bytes, uint32_t *flags_out,
                      int64_t *instances_out, int64_t *fragments_out, void *stream) {
   // status and counters sit at fixed offsets at the start of every layout
   const Layout L = make_layout(0, 1, 1, 0);
-  if (!ws || !flags_out || ws_bytes < L.pp_look) return HTGS_E_INVAL;
+  if (!ws || !flags_out || ws_bytes < L.pp_total) return HTGS_E_INVAL;
   hipStream_t s = static_cast<hipStream_t>(stream);
   uint32_t flags = 0;
   unsigned long long total = 0;
@@ -654,15 +650,10 @@ int htgs_opacity_decay(float *opacity_logits, int64_t n, double lambda, void *st
   return HTGS_OK;
 }
 
-int htgs_debug_set_spin_limit(int32_t limit) {
-  g_spin_limit = limit;
-  return HTGS_OK;
-}
-
 int htgs_debug_fragment_counts(const void *ws, int64_t ws_bytes, int64_t *forward_out,
                                int64_t *backward_out, void *stream) {
   const Layout L = make_layout(0, 1, 1, 0);
-  if (!ws || !forward_out || !backward_out || ws_bytes < L.pp_look) return HTGS_E_INVAL;
+  if (!ws || !forward_out || !backward_out || ws_bytes < L.pp_total) return HTGS_E_INVAL;
   return read_counters(ws, L, forward_out, backward_out, static_cast<hipStream_t>(stream));
 }
 

@@ -97,12 +97,12 @@ constexpr uint32_t kCflagVisible = 8u;
 
 // Device addresses inside the caller's workspace.
 struct Ws {
-  uint32_t *status;            // [kStatusWords]: flags, tickets, raster queues (see below)
+  uint32_t *status;            // [kStatusWords]: flags, raster queues (see below)
   unsigned long long *total;   // instance count (64-bit)
   unsigned long long *frags;   // fragments counted by the forward raster (spread, below)
   unsigned long long *frags_bwd;  // fragments counted by the backward raster (spread)
-  unsigned long long *pp_look; // preprocess look-back words, one per block
-  uint32_t *hist;              // [4][256] digit histograms
+  unsigned long long *pp_total;  // per preprocess workgroup: its instance total, then its first slot
+  uint32_t *hist;              // [kHistCopies][4][256] digit histograms (summed when read)
   uint32_t *sort_cnt;          // [passes][chunk_stride][256]: digit counts per chunk
   uint32_t *sort_start;        // [passes][256][chunk_stride]: global start of each
                                // (digit, chunk) run
@@ -123,7 +123,7 @@ struct Ws {
   // preprocess walks), its digit histograms and per-chunk counts.
   uint32_t *dkeys[2];
   uint32_t *dvals[2];
-  uint32_t *dhist;             // [4][256]
+  uint32_t *dhist;             // [kHistCopies][4][256]
   uint32_t *dcnt;              // [4][dchunk_stride][256]
   uint32_t *dstart;            // [4][256][dchunk_stride]
   const uint32_t *perm;        // Gaussians front to back (null: index order)
@@ -132,14 +132,8 @@ struct Ws {
   int64_t chunk_stride;        // words per digit row of sort_cnt (>= chunks of capacity)
   int32_t key_bits, passes, key16;
   int32_t final_buf;           // which of keys/vals holds the sorted lists
-  int32_t spin_limit;          // look-back rounds before a wait gives up (< 0: at once)
 };
 
-// Look-back words: 2 flag bits on top of the value.
-constexpr unsigned long long kFlagA64 = 1ull << 62, kFlagP64 = 2ull << 62,
-                             kMask64 = (1ull << 62) - 1ull;
-constexpr int kSpinLimit = 1 << 22;   // default look-back rounds before giving up
-constexpr int kLookWindow = 4;         // look-back words read per round trip
 // Forward state values per pixel: K ids, K alphas, K list positions, K rgb
 // triples, T, sum alpha, sum alpha rgb (3), prod (1 - alpha).
 __host__ __device__ constexpr int state_values(int K) { return 6 * K + 6; }
@@ -149,6 +143,14 @@ __host__ __device__ constexpr int state_values(int K) { return 6 * K + 6; }
 // left out (-1: none).
 constexpr int kSortedStateValues = 7;
 
+// Digit histograms: kHistCopies copies, added to by workgroup
+// blockIdx % kHistCopies and summed by the sort's scan. With one copy the
+// emit launch's end-of-workgroup adds (one per non-empty digit, ~24 per
+// workgroup) queued on 16 cache lines and set its length (87 us at 1080p).
+constexpr int kHistCopies = 64;
+__device__ __forceinline__ uint32_t *hist_copy(uint32_t *hist) {
+  return hist + (blockIdx.x % kHistCopies) * (4 * 256);
+}
 
 // Fragment counters: kCounterSpread words, each in a 128-byte line of its
 // own, added to by workgroup blockIdx % kCounterSpread and summed when
@@ -161,40 +163,22 @@ __device__ __forceinline__ void count_add(unsigned long long *ctr, unsigned long
   atomicAdd(ctr + (blockIdx.x % kCounterSpread) * kCounterStride, v);
 }
 
-// Status word. ST_SPIN: the preprocess look-back (the only cross-workgroup
-// wait of the front end) gave up, so some instance positions are wrong;
-// ST_SPIN_PRE says the give-up was the preprocess's, which the sort passes
-// read to leave the unusable lists alone.
-enum StatusBits : uint32_t { ST_OVERFLOW = 1u, ST_SPIN = 2u, ST_SPIN_PRE = 1u << 8 };
-constexpr uint32_t kStatusPublic = ST_OVERFLOW | ST_SPIN;
+// Status word: ST_OVERFLOW, more instances than the workspace holds (no
+// workgroup of any launch waits for another, so nothing else can fail).
+enum StatusBits : uint32_t { ST_OVERFLOW = 1u };
+constexpr uint32_t kStatusPublic = ST_OVERFLOW;
 // Status words (512 bytes, four 128-byte cache lines). The flags word has a
-// line of its own: every workgroup of the later stages reads it, and when
-// it shared a line with the ticket that each workgroup increments, the
-// reads queued behind the atomics. [0] flags; [32] preprocess ticket;
+// line of its own: every workgroup of the later stages reads it. [0] flags;
 // [64..67] / [68..71] the raster queues.
 constexpr int kStatusWords = 128;
-constexpr int kTicketPre = 32;
-// outputs of the front end are unusable: overflow or any give-up
+// outputs of the front end are unusable: overflow
 __device__ __forceinline__ bool front_failed(const Ws &w) {
   return (__hip_atomic_load(&w.status[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
-          (ST_OVERFLOW | ST_SPIN)) != 0u;
+          ST_OVERFLOW) != 0u;
 }
 // status words of the persistent raster queues (16-byte aligned, cleared
 // before each raster launch)
 constexpr int kQueueFwd = 64, kQueueBwd = 68;
-
-__device__ __forceinline__ uint32_t ld_acq_u32(const uint32_t *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_rel_u32(uint32_t *p, uint32_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ unsigned long long ld_acq_u64(const unsigned long long *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_rel_u64(unsigned long long *p, unsigned long long v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 

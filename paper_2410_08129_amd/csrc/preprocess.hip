@@ -8,10 +8,10 @@
 //    Sec. 3.2 (s, f, p_i, h_i), all in float64 so that the tile lists are
 //    exact; pixel-centre rect -> tile rect -> instance count;
 //  * the affine Pluecker record for the rasterizer and the SH colour.
-// The same launch then scans the counts across workgroups (decoupled
-// look-back over workgroup tickets), emits the (tile key, Gaussian index)
-// instances with a load-balanced loop and adds the radix-sort digit
-// histograms of those keys.
+// A one-workgroup launch then scans the workgroups' instance totals, and an
+// emit launch writes the (tile key, Gaussian index) instances with a
+// load-balanced loop and adds the radix-sort digit histograms of those
+// keys. No workgroup waits for another.
 //
 // Backward: a slot-parallel segmented reduction sums the per-instance
 // partials of each (Gaussian, view); then one lane per Gaussian applies the
@@ -103,8 +103,9 @@ __device__ inline void activate(const GaussPtrs &gp, const KCfg &cfg, int64_t g,
     qq += a.q[k] * a.q[k];
   }
   a.qnorm = cfg.baked ? 1.0 : sqrt(qq);
+  const double iq = 1.0 / a.qnorm;
   double qn[4];
-  for (int k = 0; k < 4; ++k) qn[k] = a.q[k] / a.qnorm;
+  for (int k = 0; k < 4; ++k) qn[k] = a.q[k] * iq;
   quat_to_rot(qn, a.R);
   a.o = raw_opacity(gp, cfg, g);
   if (gp.filter_var) {
@@ -244,12 +245,14 @@ __device__ inline unsigned long long cull_mask(const Conic &c, int4 rect, int tw
   const double det = c.Dpp * c.Fqq - c.Epq * c.Epq;
   *valid = c.Dpp > 0.0 && c.Fqq > 0.0 && det > 1e-9 * c.Dpp * c.Fqq;
   if (!*valid) return 0ull;
-  const double ps = (c.Epq * c.C - c.Fqq * c.B) / det, qs = (c.Epq * c.B - c.Dpp * c.C) / det;
+  const double idet = 1.0 / det;
+  const double ps = (c.Epq * c.C - c.Fqq * c.B) * idet, qs = (c.Epq * c.B - c.Dpp * c.C) * idet;
   const double Q0 = conic_at(c, ps, qs);
   if (!(Q0 < 0.0)) return 0ull;  // empty ellipse: no fragment anywhere
-  const double hp = sqrt(-Q0 * c.Fqq / det), hq = sqrt(-Q0 * c.Dpp / det);
+  const double hp = sqrt(-Q0 * c.Fqq * idet), hq = sqrt(-Q0 * c.Dpp * idet);
   const double qmin = qs - hq, qmax = qs + hq;
-  const double qL = qs + c.Epq * hp / c.Fqq, qR = qs - c.Epq * hp / c.Fqq;
+  const double eh = c.Epq * hp / c.Fqq;
+  const double qL = qs + eh, qR = qs - eh;
   const double idp = 1.0 / c.Dpp;
   // p extent of the ellipse on the line q: pc(q) +- sqrt(disc(q)) / Dpp
   auto side = [&](double q, double sgn) {
@@ -332,45 +335,49 @@ __device__ inline uint32_t preprocess_view(const GaussPtrs &gp, const KCfg &cfg,
   }
 
   // Reference point: the centre of the covered pixel nearest the box centre.
+  // (Divisions by the focal lengths are products with their reciprocals:
+  // a float64 division is a sequence of about ten instructions at the
+  // float64 rate, and these values are rounded to float32 or only decide
+  // a conservative tile test.)
   const double ixd = fmin(fmax(floor(p1), x0), x1);
   const double iyd = fmin(fmax(floor(p2), y0), y1);
-  const double uc = (ixd + 0.5 - cx) / fx, vc = (iyd + 0.5 - cy) / fy;
-  double D0[3], Du[3], Dv[3];
-  cross3(Rv[0], Rv[1], D0);
-  cross3(Rv[1], Rv[2], Du);
-  cross3(Rv[2], Rv[0], Dv);
-  // Tile culling works on the float64 conic of the footprint; the tiles are
-  // tested after the record is written, when few other values are live.
-  const bool cull = CULL && count >= 2u && count <= 64u;
-  Conic conic{};
-  if (cull) {
-    double Dc[3], Dx[3], Dy[3], Mc[3], Mx[3], My[3];
+  const double ifx = 1.0 / fx, ify = 1.0 / fy;
+  const double uc = (ixd + 0.5 - cx) * ifx, vc = (iyd + 0.5 - cy) * ify;
+  // Pluecker vectors affine in the pixel offset: d = Dc + p Dx + q Dy,
+  // m = Mc + p Mx + q My.
+  double Dc[3], Dx[3], Dy[3], Mc[3], Mx[3], My[3];
+  {
+    double D0[3], Du[3], Dv[3];
+    cross3(Rv[0], Rv[1], D0);
+    cross3(Rv[1], Rv[2], Du);
+    cross3(Rv[2], Rv[0], Dv);
     for (int k = 0; k < 3; ++k) {
       const double M0 = mv[0] * Rv[1][k] - mv[1] * Rv[0][k];
       const double Mu = mv[1] * Rv[2][k] - mv[2] * Rv[1][k];
       const double Mv = mv[2] * Rv[0][k] - mv[0] * Rv[2][k];
       Dc[k] = D0[k] + uc * Du[k] + vc * Dv[k];
-      Dx[k] = Du[k] / fx;
-      Dy[k] = Dv[k] / fy;
+      Dx[k] = Du[k] * ifx;
+      Dy[k] = Dv[k] * ify;
       Mc[k] = M0 + uc * Mu + vc * Mv;
-      Mx[k] = Mu / fx;
-      My[k] = Mv / fy;
+      Mx[k] = Mu * ifx;
+      My[k] = Mv * ify;
     }
-    conic = make_conic(Dc, Dx, Dy, Mc, Mx, My, rc);
   }
+  // Tile culling works on the float64 conic of the footprint; the tiles are
+  // tested after the record is written, when few other values are live.
+  const bool cull = CULL && count >= 2u && count <= 64u;
+  Conic conic{};
+  if (cull) conic = make_conic(Dc, Dx, Dy, Mc, Mx, My, rc);
   // The geometric part of the record is stored first so that its registers
   // are free before the colour is evaluated.
   float rec[24];
   for (int k = 0; k < 3; ++k) {
-    const double M0 = mv[0] * Rv[1][k] - mv[1] * Rv[0][k];
-    const double Mu = mv[1] * Rv[2][k] - mv[2] * Rv[1][k];
-    const double Mv = mv[2] * Rv[0][k] - mv[0] * Rv[2][k];
-    rec[R_D0 + k] = (float)(D0[k] + uc * Du[k] + vc * Dv[k]);
-    rec[R_DU + k] = (float)(Du[k] / fx);
-    rec[R_DV + k] = (float)(Dv[k] / fy);
-    rec[R_M0 + k] = (float)(M0 + uc * Mu + vc * Mv);
-    rec[R_MU + k] = (float)(Mu / fx);
-    rec[R_MV + k] = (float)(Mv / fy);
+    rec[R_D0 + k] = (float)Dc[k];
+    rec[R_DU + k] = (float)Dx[k];
+    rec[R_DV + k] = (float)Dy[k];
+    rec[R_M0 + k] = (float)Mc[k];
+    rec[R_MU + k] = (float)Mx[k];
+    rec[R_MV + k] = (float)My[k];
     rec[R_R3 + k] = (float)Rv[2][k];
   }
   rec[R_MUZ] = (float)mv[2];
@@ -387,10 +394,10 @@ __device__ inline uint32_t preprocess_view(const GaussPtrs &gp, const KCfg &cfg,
 
   // View-dependent colour (Sec. 3.1; 3DGS convention).
   double dv[3] = {a.mu[0] - V.cam_pos[0], a.mu[1] - V.cam_pos[1], a.mu[2] - V.cam_pos[2]};
-  const double dn = sqrt(dot3(dv, dv));
+  const double idn = 1.0 / sqrt(dot3(dv, dv));
   constexpr int NB = (DEG + 1) * (DEG + 1), NF = 3 * NB;
   float Y[16];
-  sh_basis<float>((float)(dv[0] / dn), (float)(dv[1] / dn), (float)(dv[2] / dn), DEG, Y);
+  sh_basis<float>((float)(dv[0] * idn), (float)(dv[1] * idn), (float)(dv[2] * idn), DEG, Y);
   float coef[NF];
   load_row<NF>(gp.sh + g * NF, coef);
   uint32_t flags = 0;
@@ -431,51 +438,37 @@ __global__ void __launch_bounds__(256) k_fill_zero(uint4 *p, int64_t n16) {
     p[i] = make_uint4(0u, 0u, 0u, 0u);
 }
 
-// MV: more than one view (a single view keeps far fewer values live);
-// CULL: tile culling of small boxes.
+// Position pos of the list the front end walks holds Gaussian g: the index
+// itself, or, for sorted blending, the Gaussian at that place of the
+// front-to-back order (so instances are emitted in that order, and the
+// stable tile sort keeps it inside each tile). False past the end.
+__device__ __forceinline__ bool gaussian_at(const Ws &w, const KCfg &cfg, int64_t pos,
+                                            int64_t &g) {
+  g = pos;
+  if (pos >= cfg.n) return false;
+  if (w.perm) {
+    const uint32_t x = w.perm[pos];
+    if ((int64_t)x >= cfg.n) return false;
+    g = (int64_t)x;
+  }
+  return true;
+}
+
+// Per Gaussian and view (MV: more than one view, which keeps more values
+// live; CULL: tile culling of small boxes): the record, the rect, the
+// colour flags and a tile-slot descriptor whose first word holds the
+// instance count for now (the emit launch replaces it by the first slot);
+// per workgroup the instance total, for the scan of the totals.
 template <int DEG, bool MV, bool CULL>
 __global__ void __launch_bounds__(kPreThreads) k_preprocess(GaussPtrs gp, KCfg cfg, ViewSet vs,
                                                              Ws w) {
-  __shared__ uint32_t s_ticket;
-  constexpr int NVL = MV ? kMaxViews : 1;
-  // instances formed before the look-back (single view: the batched form's
-  // per-view tables already fill most of the LDS)
-  constexpr int NSTAGE = MV ? 0 : 3072;
-  __shared__ uint32_t s_ekey[NSTAGE > 0 ? NSTAGE : 1], s_egid[NSTAGE > 0 ? NSTAGE : 1];
-  __shared__ uint32_t s_start[NVL * kPreThreads + 1];
-  __shared__ uint32_t s_vrect[NVL][kPreThreads];
-  __shared__ unsigned long long s_vmask[NVL][kPreThreads];
-  __shared__ uint32_t s_hist[4][256];
-  __shared__ uint32_t s_wsum[kPreThreads / 64];
-  __shared__ unsigned long long s_base;
-
-  const int tid = threadIdx.x;
-  if (tid == 0) s_ticket = atomicAdd(&w.status[kTicketPre], 1u);
-  for (int i = tid; i < 4 * 256; i += kPreThreads) (&s_hist[0][0])[i] = 0u;
-  __syncthreads();
-  const int64_t blk = s_ticket;
-  // Position tid of the workgroup holds Gaussian g: the index itself, or,
-  // for sorted blending, the Gaussian at that place of the front-to-back
-  // order (so instances are emitted in that order, and the stable tile sort
-  // keeps it inside each tile).
-  const int64_t pos = blk * kPreThreads + tid;
-  int64_t g = pos;
-  bool live = pos < cfg.n;
-  if (w.perm) {
-    const uint32_t x = live ? w.perm[pos] : 0xffffffffu;
-    live = live && (int64_t)x < cfg.n;
-    g = live ? (int64_t)x : pos;
-  }
-  __shared__ uint32_t s_gidx[kPreThreads];
-  s_gidx[tid] = (uint32_t)g;
+  __shared__ unsigned long long s_wsum[kPreThreads / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t blk = blockIdx.x;
+  int64_t g;
+  const bool live = gaussian_at(w, cfg, blk * kPreThreads + tid, g);
   const int nviews = MV ? vs.n : 1;
-
-  // Slot layout: the workgroup's 64-Gaussian groups (one per wave) in
-  // order; inside a group view by view, inside a view Gaussian by Gaussian,
-  // inside a (view, Gaussian) tile by tile. s_start holds the workgroup-
-  // relative first slot of every (group, view, lane), in slot order, plus
-  // the workgroup total at the end; it first holds the counts.
-  const int lane = tid & 63, wave = tid >> 6;
+  unsigned long long total = 0;
   if (live) {
     Activated a;
     activate(gp, cfg, g, a);
@@ -483,12 +476,93 @@ __global__ void __launch_bounds__(kPreThreads) k_preprocess(GaussPtrs gp, KCfg c
       uint32_t packed = 0;
       unsigned long long mk = 0ull;
       const uint32_t c = preprocess_view<DEG, CULL>(gp, cfg, vs.v[v], w, v, g, a, &packed, &mk);
-      s_start[(wave * nviews + v) * 64 + lane] = c;
-      s_vrect[v][tid] = packed;
-      s_vmask[v][tid] = c ? mk : 0ull;
+      w.tslots[(int64_t)v * cfg.n + g] =
+          c ? make_uint4(c, packed, (uint32_t)mk, (uint32_t)(mk >> 32)) : make_uint4(0u, 0u, 0u, 0u);
+      total += c;
     }
-  } else {
-    for (int v = 0; v < nviews; ++v) s_start[(wave * nviews + v) * 64 + lane] = 0u;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) total += __shfl_xor(total, off, 64);
+  if (lane == 0) s_wsum[wave] = total;
+  __syncthreads();
+  if (tid == 0) {
+    unsigned long long t = 0;
+#pragma unroll
+    for (int k = 0; k < kPreThreads / 64; ++k) t += s_wsum[k];
+    w.pp_total[blk] = t;
+  }
+}
+
+// Exclusive scan of the workgroup totals, in place, by one workgroup; the
+// sum is the instance count, which raises the overflow flag when it
+// exceeds the capacity.
+constexpr int kTotScanThreads = 1024, kTotScanItems = 4;
+__global__ void __launch_bounds__(kTotScanThreads) k_preprocess_scan(Ws w, int64_t nblk) {
+  __shared__ unsigned long long s_wsum[kTotScanThreads / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  unsigned long long carry = 0;
+  for (int64_t b0 = 0; b0 < nblk; b0 += (int64_t)kTotScanThreads * kTotScanItems) {
+    const int64_t bb = b0 + (int64_t)tid * kTotScanItems;
+    unsigned long long v[kTotScanItems], sum = 0;
+#pragma unroll
+    for (int j = 0; j < kTotScanItems; ++j) {
+      v[j] = bb + j < nblk ? w.pp_total[bb + j] : 0ull;
+      sum += v[j];
+    }
+    unsigned long long inc = sum;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const unsigned long long y = __shfl_up(inc, off, 64);
+      if (lane >= off) inc += y;
+    }
+    __syncthreads();   // the previous round's readers of s_wsum are done
+    if (lane == 63) s_wsum[wave] = inc;
+    __syncthreads();
+    unsigned long long run = carry + inc - sum;
+    for (int k = 0; k < wave; ++k) run += s_wsum[k];
+#pragma unroll
+    for (int j = 0; j < kTotScanItems; ++j) {
+      if (bb + j < nblk) w.pp_total[bb + j] = run;
+      run += v[j];
+    }
+    for (int k = 0; k < kTotScanThreads / 64; ++k) carry += s_wsum[k];
+  }
+  if (tid == 0) {
+    *w.total = carry;
+    if (carry > (unsigned long long)w.capacity) atomicOr(&w.status[0], (uint32_t)ST_OVERFLOW);
+  }
+}
+
+// The instances of the workgroup's Gaussians (the same 256 positions as the
+// preprocess launch), written from its first slot on, and the radix-sort
+// digit histograms of their keys. Slot layout: the workgroup's 64-Gaussian
+// groups (one per wave) in order; inside a group view by view, inside a
+// view Gaussian by Gaussian, inside a (view, Gaussian) tile by tile.
+// s_start holds the workgroup-relative first slot of every (group, view,
+// lane), in slot order, plus the workgroup total at the end; it first holds
+// the counts. The tile-slot descriptors get their first slots here.
+template <bool MV>
+__global__ void __launch_bounds__(kPreThreads) k_emit(KCfg cfg, ViewSet vs, Ws w) {
+  constexpr int NVL = MV ? kMaxViews : 1;
+  __shared__ uint32_t s_start[NVL * kPreThreads + 1];
+  __shared__ uint32_t s_vrect[NVL][kPreThreads];
+  __shared__ unsigned long long s_vmask[NVL][kPreThreads];
+  __shared__ uint32_t s_hist[4][256];
+  __shared__ uint32_t s_wsum[kPreThreads / 64];
+  __shared__ uint32_t s_gidx[kPreThreads];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t blk = blockIdx.x;
+  for (int i = tid; i < 4 * 256; i += kPreThreads) (&s_hist[0][0])[i] = 0u;
+  int64_t g;
+  const bool live = gaussian_at(w, cfg, blk * kPreThreads + tid, g);
+  s_gidx[tid] = (uint32_t)g;
+  const int nviews = MV ? vs.n : 1;
+  for (int v = 0; v < nviews; ++v) {
+    const uint4 ts = live ? w.tslots[(int64_t)v * cfg.n + g] : make_uint4(0u, 0u, 0u, 0u);
+    s_start[(wave * nviews + v) * 64 + lane] = ts.x;
+    s_vrect[v][tid] = ts.y;
+    s_vmask[v][tid] = (unsigned long long)ts.z | ((unsigned long long)ts.w << 32);
   }
 
   // Group-relative starts: a wave scan per view, the views one after
@@ -518,20 +592,26 @@ __global__ void __launch_bounds__(kPreThreads) k_preprocess(GaussPtrs gp, KCfg c
   const int nent = kPreThreads * nviews;
   if (tid == 0) s_start[nent] = block_total;
   __syncthreads();
+  const unsigned long long base = w.pp_total[blk];
 
-  // The workgroup's count is published first. When the workgroup's
-  // instances fit, they are formed into LDS before the look-back, so the
-  // wait for the predecessors' prefixes overlaps that work; otherwise they
-  // are formed after it, straight to memory.
-  if (tid == 0) {
-    if (blk == 0) st_rel_u64(&w.pp_look[0], kFlagP64 | block_total);
-    else st_rel_u64(&w.pp_look[blk], kFlagA64 | block_total);
+  if (live) {
+    // First slot of each (view, Gaussian), clamped at 2^31 so that base +
+    // rank cannot wrap (slots at or past the capacity are never written).
+    for (int v = 0; v < nviews; ++v) {
+      const int f = (wave * nviews + v) * 64 + lane;
+      const unsigned long long m = s_vmask[v][tid];
+      w.tslots[(int64_t)v * cfg.n + g] =
+          make_uint4((uint32_t)min(base + s_start[f], 0x80000000ull), s_vrect[v][tid],
+                     (uint32_t)m, (uint32_t)(m >> 32));
+    }
   }
-  const bool staged = block_total <= (uint32_t)NSTAGE;
 
-  // Instance e of the workgroup: its tile key and Gaussian index.
-  auto make_instance = [&](uint32_t e, uint32_t &key, uint32_t &gid) {
-    // the last (group, view, lane) entry starting at or before e owns it
+  // Instances to memory, one per loop iteration, balanced over the
+  // workgroup: instance e belongs to the last (group, view, lane) entry
+  // starting at or before it.
+  uint16_t *k16 = reinterpret_cast<uint16_t *>(w.keys[0]);
+  uint32_t *k32 = reinterpret_cast<uint32_t *>(w.keys[0]);
+  for (uint32_t e = tid; e < block_total; e += kPreThreads) {
     int lo = 0, hi = nent;
     while (hi - lo > 1) {
       const int mid = (lo + hi) >> 1;
@@ -541,7 +621,7 @@ __global__ void __launch_bounds__(kPreThreads) k_preprocess(GaussPtrs gp, KCfg c
     const int grp = lo / (64 * nviews);
     const int v = MV ? (lo >> 6) - grp * nviews : 0;
     const int owner = grp * 64 + (lo & 63);
-    gid = w.perm ? s_gidx[owner] : (uint32_t)(blk * kPreThreads + owner);
+    const uint32_t gid = s_gidx[owner];
     const uint32_t pr = s_vrect[v][owner];
     const uint32_t rw = pr >> 20;
     // With a tile mask, the rank-th surviving tile is the rank-th set bit.
@@ -568,94 +648,8 @@ __global__ void __launch_bounds__(kPreThreads) k_preprocess(GaussPtrs gp, KCfg c
     if (rx >= (int)rw) { ++qy; rx -= (int)rw; }
     const uint32_t ty = ((pr >> 10) & 1023u) + (uint32_t)qy;
     const uint32_t tx = (pr & 1023u) + (uint32_t)rx;
-    key = (uint32_t)vs.v[v].tile_base + ty * (uint32_t)vs.v[v].tiles_x + tx;
+    const uint32_t key = (uint32_t)vs.v[v].tile_base + ty * (uint32_t)vs.v[v].tiles_x + tx;
     for (int p = 0; p < w.passes; ++p) atomicAdd(&s_hist[p][(key >> (8 * p)) & 255u], 1u);
-  };
-  if constexpr (NSTAGE > 0) {
-    if (staged) {
-      for (uint32_t e = tid; e < block_total; e += kPreThreads) {
-        uint32_t key, gid;
-        make_instance(e, key, gid);
-        s_ekey[e] = key;
-        s_egid[e] = gid;
-      }
-    }
-  }
-
-  // Decoupled look-back across workgroups (in ticket order).
-  if (tid == 0) {
-    unsigned long long excl = 0;
-    if (blk > 0) {
-      int64_t j = blk - 1;
-      int spins = 0;
-      while (true) {
-        // A wait that gives up (w.spin_limit rounds without progress; a
-        // negative limit gives up at once) flags the status word and goes
-        // on with a prefix that is too small: slots stay below the true
-        // ones, and every later stage sees the flag.
-        if (spins > w.spin_limit) {
-          atomicOr(&w.status[0], (uint32_t)(ST_SPIN | ST_SPIN_PRE));
-          break;
-        }
-        // kLookWindow predecessors per round trip; stop at the first
-        // inclusive (P) or unpublished word.
-        unsigned long long sv[kLookWindow];
-#pragma unroll
-        for (int k = 0; k < kLookWindow; ++k) sv[k] = (j - k >= 0) ? ld_acq_u64(&w.pp_look[j - k]) : 0ull;
-        int used = 0;
-        bool done = false;
-#pragma unroll
-        for (int k = 0; k < kLookWindow; ++k) {
-          if (done || used < k) continue;
-          const unsigned f = (unsigned)(sv[k] >> 62);
-          if (f == 0) continue;
-          excl += sv[k] & kMask64;
-          used = k + 1;
-          done = (f == 2);
-        }
-        if (done) break;
-        j -= used;
-        if (used == 0) {
-          ++spins;
-          __builtin_amdgcn_s_sleep(1);
-        }
-      }
-      st_rel_u64(&w.pp_look[blk], kFlagP64 | (excl + block_total));
-    }
-    s_base = excl;
-    if (blk == (int64_t)gridDim.x - 1) {
-      const unsigned long long tot = excl + block_total;
-      *w.total = tot;
-      if (tot > (unsigned long long)w.capacity) atomicOr(&w.status[0], (uint32_t)ST_OVERFLOW);
-    }
-  }
-  __syncthreads();
-  const unsigned long long base = s_base;
-  if (live) {
-    // Tile-slot descriptors: first slot of each (view, Gaussian), clamped
-    // at 2^31 so that base + rank cannot wrap (slots at or past the
-    // capacity are never written).
-    for (int v = 0; v < nviews; ++v) {
-      const int f = (wave * nviews + v) * 64 + lane;
-      const uint32_t c = s_start[f + 1] - s_start[f];
-      const unsigned long long m = s_vmask[v][tid];
-      w.tslots[(int64_t)v * cfg.n + g] =
-          make_uint4((uint32_t)min(base + s_start[f], 0x80000000ull), c ? s_vrect[v][tid] : 0u,
-                     (uint32_t)m, (uint32_t)(m >> 32));
-    }
-  }
-
-  // Instances to memory, one per loop iteration, balanced over the workgroup.
-  uint16_t *k16 = reinterpret_cast<uint16_t *>(w.keys[0]);
-  uint32_t *k32 = reinterpret_cast<uint32_t *>(w.keys[0]);
-  for (uint32_t e = tid; e < block_total; e += kPreThreads) {
-    uint32_t key, gid;
-    if (NSTAGE > 0 && staged) {
-      key = s_ekey[e];
-      gid = s_egid[e];
-    } else {
-      make_instance(e, key, gid);
-    }
     const unsigned long long pos = base + e;
     if (pos < (unsigned long long)w.capacity) {
       if (w.key16) k16[pos] = (uint16_t)key; else k32[pos] = key;
@@ -663,9 +657,10 @@ __global__ void __launch_bounds__(kPreThreads) k_preprocess(GaussPtrs gp, KCfg c
     }
   }
   __syncthreads();
+  uint32_t *hist = hist_copy(w.hist);
   for (int p = 0; p < w.passes; ++p) {
     const uint32_t c = s_hist[p][tid];
-    if (c) atomicAdd(&w.hist[p * 256 + tid], c);
+    if (c) atomicAdd(&hist[p * 256 + tid], c);
   }
 }
 
@@ -837,8 +832,8 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(GaussPtrs gp, GradPtrs g
   if (pos0 >= cfg.n) return;  // uniform over the wave
   const int nviews = MV ? vs.n : 1;
   const unsigned long long I = *w.total;
-  // An overflowed forward, or one whose look-back gave up (both reported
-  // by the status word), leaves no usable partials: zero gradient.
+  // An overflowed forward (reported by the status word) leaves no usable
+  // partials: zero gradient.
   const bool ok = I <= (unsigned long long)w.capacity && !front_failed(w);
   // Sorted blending emitted the instances in the depth order of its
   // Gaussians (position p holds Gaussian perm[p]), so a group of 64
@@ -1099,8 +1094,9 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(GaussPtrs gp, GradPtrs g
     for (int k = 0; k < 3; ++k) gl[k] = gs[k] * a.s[k];
     glogit = (double)go * a.o * (1.0 - a.o);
   }
+  const double iq = 1.0 / a.qnorm;
   double qn[4];
-  for (int k = 0; k < 4; ++k) qn[k] = a.q[k] / a.qnorm;
+  for (int k = 0; k < 4; ++k) qn[k] = a.q[k] * iq;
   double gqn[4];
   rot_grad_to_quat(qn, gRot, gqn);
   const double proj = qn[0] * gqn[0] + qn[1] * gqn[1] + qn[2] * gqn[2] + qn[3] * gqn[3];
@@ -1110,7 +1106,7 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(GaussPtrs gp, GradPtrs g
     fmu[k] = (float)gmu[k];
     fls[k] = (float)gl[k];
   }
-  for (int k = 0; k < 4; ++k) fq[k] = (float)((gqn[k] - qn[k] * proj) / a.qnorm);
+  for (int k = 0; k < 4; ++k) fq[k] = (float)((gqn[k] - qn[k] * proj) * iq);
   emit_grads<NB>(gr, g, fmu, fls, fq, (float)glogit, gsh, cfg.grad_overwrite != 0);
 }
 
@@ -1170,6 +1166,14 @@ hipError_t launch_preprocess(const GaussPtrs &gp, const KCfg &cfg, const ViewSet
   }
 #undef HTGS_PRE
 #undef HTGS_PRE3
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_preprocess_scan, dim3(1), dim3(kTotScanThreads), 0, s, w, (int64_t)blocks);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (vs.n > 1)
+    hipLaunchKernelGGL(k_emit<true>, dim3(blocks), dim3(kPreThreads), 0, s, cfg, vs, w);
+  else
+    hipLaunchKernelGGL(k_emit<false>, dim3(blocks), dim3(kPreThreads), 0, s, cfg, vs, w);
   return hipGetLastError();
 }
 

@@ -310,7 +310,7 @@ __device__ __forceinline__ void fwd_tile(const TileInfo &ti, const Ws &w, const 
   const int px0 = ti.tx * TW, py0 = ti.ty * TH;
   const int px = px0 + lx, py = py0 + ly;
   const bool inside = (px < V.width) && (py < V.height);
-  // a failed front end (overflow, a look-back that gave up) leaves every
+  // a failed front end (overflow) leaves every
   // tile empty: background, and no list or record is read
   const uint2 rg = front_failed(w) ? make_uint2(0u, 0u) : w.ranges[ti.t];
   PixQ u;

@@ -25,29 +25,23 @@ constexpr int kSortWaves = kSortThreads / 64;
 constexpr int kScanItems = 8;   // chunk counts per thread per round of the scan
 
 // What a sort works on: the item count (a device word, or a fixed number),
-// the capacity beyond which nothing is sorted, the global digit histograms,
-// the per-chunk count table and the status bits of earlier stages that
-// leave nothing usable to sort.
+// the capacity beyond which nothing is sorted, the global digit histograms
+// and the per-chunk count and start tables.
 struct SortJob {
   const unsigned long long *count;  // null: n_fixed items
   uint64_t n_fixed;
   int64_t capacity;
-  const uint32_t *hist;             // [passes][256]
+  const uint32_t *hist;             // [kHistCopies][4][256]
   uint32_t *cnt;                    // [passes][stride][256]: digit counts per chunk
   uint32_t *start;                  // [passes][256][stride]: global start per (digit, chunk)
   int64_t stride;
-  const uint32_t *status;
-  uint32_t cancel;
 };
 
-// Items to sort, or false when there is nothing usable: on overflow only
-// part of the keys exist while the histograms count all of them, and after
-// a give-up of the preprocess the keys are not the counted ones (the
-// status word reports both).
+// Items to sort, or false on overflow, when only part of the keys exist
+// while the histograms count all of them (the status word reports it).
 __device__ __forceinline__ bool sort_items(const SortJob &job, uint64_t &items) {
   const unsigned long long tot = job.count ? *job.count : job.n_fixed;
   if (tot > (unsigned long long)job.capacity) return false;
-  if (job.cancel && (ld_acq_u32(&job.status[0]) & job.cancel)) return false;
   items = tot;
   return true;
 }
@@ -165,7 +159,9 @@ __global__ void __launch_bounds__(256) k_sort_scan(SortJob job, int pass) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint32_t dg = blockIdx.x;
   // base: the totals of the digits below this one
-  const uint32_t x = tid < (int)dg ? job.hist[pass * 256 + tid] : 0u;
+  uint32_t x = 0u;
+  if (tid < (int)dg)
+    for (int c = 0; c < kHistCopies; ++c) x += job.hist[(c * 4 + pass) * 256 + tid];
   const uint32_t wx = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_add(x), 63);
   if (lane == 0) s_wsum[wave] = wx;
   __syncthreads();
@@ -365,7 +361,7 @@ template <typename KeyT>
 __global__ void __launch_bounds__(256) k_ranges(Ws w, const KeyT *__restrict__ keys,
                                                  uint32_t total_tiles) {
   const unsigned long long tot = *w.total;
-  // overflow or a give-up: the keys are not a sorted list, every tile stays empty
+  // overflow: the keys are not a sorted list, every tile stays empty
   if (tot > (unsigned long long)w.capacity || front_failed(w)) return;
   const uint64_t I = tot;
   const uint64_t ngroups = (I + 7) / 8;
@@ -471,8 +467,6 @@ static hipError_t sort_impl(const Ws &w, hipStream_t s) {
   job.cnt = w.sort_cnt;
   job.start = w.sort_start;
   job.stride = w.chunk_stride;
-  job.status = w.status;
-  job.cancel = ST_SPIN_PRE;
   return sort_passes<KeyT>(job, w.passes, w.key_bits, (w.capacity + kSortChunk - 1) / kSortChunk,
                            w.keys, w.vals, s);
 }
@@ -504,9 +498,10 @@ __global__ void __launch_bounds__(256) k_depth_keys(const float *__restrict__ me
     for (int p = 0; p < 4; ++p) atomicAdd(&s_hist[p][(key >> (8 * p)) & 255u], 1u);
   }
   __syncthreads();
+  uint32_t *hc = hist_copy(hist);
   for (int i = threadIdx.x; i < 4 * 256; i += blockDim.x) {
     const uint32_t c = (&s_hist[0][0])[i];
-    if (c) atomicAdd(&hist[i], c);
+    if (c) atomicAdd(&hc[i], c);
   }
 }
 
@@ -530,8 +525,6 @@ hipError_t launch_depth_sort(const Ws &w, const float *means, int64_t n, const f
   job.cnt = w.dcnt;
   job.start = w.dstart;
   job.stride = w.dchunk_stride;
-  job.status = w.status;
-  job.cancel = 0u;
   void *keys[2] = {w.dkeys[0], w.dkeys[1]};
   return sort_passes<uint32_t>(job, 4, 32, (n + kSortChunk - 1) / kSortChunk, keys, w.dvals, s);
 }

@@ -17,7 +17,6 @@ LIB_PATH = os.path.join(_HERE, "libhtgs.so")
 
 HTGS_OK = 0
 HTGS_STATUS_OVERFLOW = 1
-HTGS_STATUS_SPIN_TIMEOUT = 2
 HTGS_FLAG_COST_ORDER = 1
 HTGS_FLAG_GRAD_OVERWRITE = 2
 HTGS_FLAG_TILE_CULL = 4
@@ -32,7 +31,7 @@ EXPORTED = (
     "htgs_render_forward", "htgs_render_backward", "htgs_render_forward_batched",
     "htgs_render_backward_batched", "htgs_read_status", "htgs_debug_export_bins",
     "htgs_strerror", "htgs_version", "htgs_profile_enable", "htgs_profile_read",
-    "htgs_debug_set_spin_limit", "htgs_debug_fragment_counts", "htgs_opacity_decay",
+    "htgs_debug_fragment_counts", "htgs_opacity_decay",
     "htgs_render_forward_noalloc",
 )
 STAGES = ("fill", "preprocess", "sort", "ranges", "raster_fwd", "raster_bwd", "reduce",
@@ -102,7 +101,6 @@ def lib():
     L.htgs_profile_read.argtypes = [P(ctypes.c_double), P(i64), i32]
     L.htgs_debug_export_bins.argtypes = [P(Gaussians), P(Camera), i32, P(Config), vp, i64, vp, vp,
                                          i64, vp, P(i64), vp]
-    L.htgs_debug_set_spin_limit.argtypes = [i32]
     L.htgs_opacity_decay.argtypes = [vp, i64, ctypes.c_double, vp]
     L.htgs_debug_fragment_counts.argtypes = [vp, i64, P(i64), P(i64), vp]
     L.htgs_strerror.argtypes = [ctypes.c_int]
@@ -263,14 +261,6 @@ def fragment_counts(ws: torch.Tensor, stream=None):
                                            ctypes.byref(f), ctypes.byref(b),
                                            stream_handle(stream)), "fragment_counts")
     return f.value, b.value
-
-
-def set_spin_limit(limit: int):
-    """Look-back rounds before a wait gives up (negative: at once); testing."""
-    check(lib().htgs_debug_set_spin_limit(int(limit)), "set_spin_limit")
-
-
-DEFAULT_SPIN_LIMIT = 1 << 22
 
 
 def profile_enable(on: bool):

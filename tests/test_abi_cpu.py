@@ -24,7 +24,7 @@ def test_library_exports_every_declared_entry_point():
     for n in names:
         assert hasattr(L, n), n
     assert set(htgs.EXPORTED) == set(names)
-    assert L.htgs_version() == 3
+    assert L.htgs_version() == 4
 
 
 def test_strerror_codes():

@@ -157,33 +157,3 @@ def test_forward_and_backward_count_the_same_fragments(tile):
     fwd, bwd = htgs.fragment_counts(frame.ws)
     log(f"1080p tile {tile}: forward {fwd} fragments, backward {bwd}")
     assert fwd > 1e8 and fwd == bwd
-
-
-def test_forced_lookback_give_up_is_flagged_and_safe():
-    """With a spin limit below zero every look-back gives up at once: the
-    status word reports it, the later stages treat the lists as empty (the
-    image is the background, the gradients zero) and every kernel exits
-    normally; a normal call afterwards is unaffected."""
-    sc, cams, st = scenes.workload_small()
-    st = scenes.RenderSettings(K=4, tile_w=8, tile_h=8, bg=(0.2, 0.4, 0.6), cost_order=True)
-    params = to_dev(sc)
-    ref = htgs.forward(params, sc.sh_degree, cams, st)
-    torch.cuda.synchronize()
-    ref_img = ref.images[0].clone()
-    try:
-        htgs.set_spin_limit(-1)
-        frame = htgs.forward(params, sc.sh_degree, cams, st, ws=ref.ws)
-        grads = htgs.backward(params, frame, [torch.ones_like(frame.images[0])])
-        torch.cuda.synchronize()
-        flags, _ = htgs.read_status(frame.ws)
-    finally:
-        htgs.set_spin_limit(htgs.DEFAULT_SPIN_LIMIT)
-    log(f"  forced give-up: status flags {flags}")
-    assert flags & htgs.HTGS_STATUS_SPIN_TIMEOUT
-    bg = torch.tensor(st.bg, device="cuda")[:, None, None].expand_as(frame.images[0])
-    assert torch.equal(frame.images[0], bg)
-    assert all(not torch.any(g) for g in grads)
-    again = htgs.forward(params, sc.sh_degree, cams, st, ws=ref.ws)
-    torch.cuda.synchronize()
-    assert htgs.read_status(again.ws)[0] == 0
-    assert torch.equal(again.images[0], ref_img)
