@@ -302,7 +302,8 @@ def run_variants(args, params, sc, cam, st0, target, steps=10, warmup=3):
     """Other blending modes on the same frame and schedule: hybrid
     transparency with K = 8, 16, 32 (fwd+bwd and forward only), inference
     without the tail (forward), and sorted alpha blending with the early
-    stop (forward); each with its own workspace, timed over `steps`."""
+    stop (forward, and fwd+bwd); each with its own workspace, timed over
+    `steps`."""
     import torch
 
     from paper_2410_08129_amd import htgs
@@ -353,6 +354,7 @@ def run_variants(args, params, sc, cam, st0, target, steps=10, warmup=3):
         one(f"ht_K{K}_fwd", st, False)
     one("no_tail_K8_fwd", dataclasses.replace(st0, K=8, no_tail=True, grad_overwrite=False), False)
     one("sorted_fwd", dataclasses.replace(st0, sorted_blend=True, grad_overwrite=False), False)
+    one("sorted_fwd_bwd", dataclasses.replace(st0, sorted_blend=True), True)
     for v in out.values():
         v["pass"] = v.pop("pass_")
     return out

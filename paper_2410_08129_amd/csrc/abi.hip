@@ -34,7 +34,7 @@ int64_t align_up(int64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
   int64_t status, total, frags, pp_total, hist, ranges, order_hist, dhist, zero_end;
-  int64_t sort_cnt, sort_start, dcnt, dstart, records, rects, tslots, refpix, cflags, order, keys0, keys1, vals0, vals1;
+  int64_t sort_cnt, dcnt, records, rects, tslots, refpix, cflags, order, keys0, keys1, vals0, vals1;
   int64_t partials, dkeys0, dkeys1, dvals0, dvals1, bytes;
   int64_t capacity, chunk_stride, dchunk_stride;
   int32_t key_bits, passes, key16, sorted;
@@ -72,9 +72,7 @@ Layout make_layout(int64_t n, int n_views, int64_t total_tiles, int64_t capacity
   L.dhist = o; o = align_up(o + (sorted ? kHistCopies * 4 * 256 * 4 : 0));
   L.zero_end = o;
   L.sort_cnt = o; o = align_up(o + (int64_t)L.passes * 256 * L.chunk_stride * 4);
-  L.sort_start = o; o = align_up(o + (int64_t)L.passes * 256 * L.chunk_stride * 4);
   L.dcnt = o; o = align_up(o + 4 * 256 * L.dchunk_stride * 4);
-  L.dstart = o; o = align_up(o + 4 * 256 * L.dchunk_stride * 4);
   L.records = o; o = align_up(o + (int64_t)n_views * n * kRecFloats * 4);
   L.rects = o; o = align_up(o + (int64_t)n_views * n * 16);
   L.refpix = o; o = align_up(o + (int64_t)n_views * n * 4);
@@ -119,7 +117,6 @@ Ws make_ws(void *base, const Layout &L) {
   w.pp_total = reinterpret_cast<unsigned long long *>(b + L.pp_total);
   w.hist = reinterpret_cast<uint32_t *>(b + L.hist);
   w.sort_cnt = reinterpret_cast<uint32_t *>(b + L.sort_cnt);
-  w.sort_start = reinterpret_cast<uint32_t *>(b + L.sort_start);
   w.ranges = reinterpret_cast<uint2 *>(b + L.ranges);
   w.order_hist = reinterpret_cast<uint32_t *>(b + L.order_hist);
   w.order = reinterpret_cast<uint32_t *>(b + L.order);
@@ -140,7 +137,6 @@ Ws make_ws(void *base, const Layout &L) {
     w.dvals[1] = reinterpret_cast<uint32_t *>(b + L.dvals1);
     w.dhist = reinterpret_cast<uint32_t *>(b + L.dhist);
     w.dcnt = reinterpret_cast<uint32_t *>(b + L.dcnt);
-    w.dstart = reinterpret_cast<uint32_t *>(b + L.dstart);
     w.perm = w.dvals[0];   // after the four depth-sort passes
     w.dchunk_stride = L.dchunk_stride;
   }

@@ -103,9 +103,8 @@ struct Ws {
   unsigned long long *frags_bwd;  // fragments counted by the backward raster (spread)
   unsigned long long *pp_total;  // per preprocess workgroup: its instance total, then its first slot
   uint32_t *hist;              // [kHistCopies][4][256] digit histograms (summed when read)
-  uint32_t *sort_cnt;          // [passes][chunk_stride][256]: digit counts per chunk
-  uint32_t *sort_start;        // [passes][256][chunk_stride]: global start of each
-                               // (digit, chunk) run
+  uint32_t *sort_cnt;          // [passes][256][chunk_stride]: per-chunk digit counts, then
+                               // the global start of each (digit, chunk) run
   uint2 *ranges;               // [total_tiles] (start, end)
   uint32_t *order_hist;        // [2][32] cost-bucket counts and cursors
   uint32_t *order;             // [total_tiles] tiles by descending instance count
@@ -124,8 +123,7 @@ struct Ws {
   uint32_t *dkeys[2];
   uint32_t *dvals[2];
   uint32_t *dhist;             // [kHistCopies][4][256]
-  uint32_t *dcnt;              // [4][dchunk_stride][256]
-  uint32_t *dstart;            // [4][256][dchunk_stride]
+  uint32_t *dcnt;              // [4][256][dchunk_stride]
   const uint32_t *perm;        // Gaussians front to back (null: index order)
   int64_t dchunk_stride;
   int64_t capacity;

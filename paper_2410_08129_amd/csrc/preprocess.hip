@@ -420,7 +420,12 @@ __device__ inline uint32_t preprocess_view(const GaussPtrs &gp, const KCfg &cfg,
   if (cull) {
     bool valid = false;
     mask = cull_mask(conic, rect, cfg.tile_w, cfg.tile_h, x0, x1, y0, y1, ixd, iyd, &valid);
-    if (valid) count = (uint32_t)__popcll(mask);
+    if (valid) {
+      const uint32_t kept = (uint32_t)__popcll(mask);
+      // every tile kept: no mask (the emit then skips the set-bit search)
+      if (kept == count) mask = 0ull;
+      count = kept;
+    }
   }
   if (count == 0) rect = make_int4(1, 1, 0, 0);
   w.rects[vg] = rect;
@@ -533,6 +538,23 @@ __global__ void __launch_bounds__(kTotScanThreads) k_preprocess_scan(Ws w, int64
   }
 }
 
+// Inclusive maximum over the lanes of a wave by DPP moves (shifts by 1, 2,
+// 4, 8 inside each row of 16 lanes, then the row ends broadcast to the rows
+// after them); lanes whose source is outside receive 0.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint32_t dpp_max_step(uint32_t x) {
+  return max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROW_MASK, 0xf, false));
+}
+__device__ __forceinline__ uint32_t wave_incl_max(uint32_t x) {
+  x = dpp_max_step<0x111, 0xf>(x);
+  x = dpp_max_step<0x112, 0xf>(x);
+  x = dpp_max_step<0x114, 0xf>(x);
+  x = dpp_max_step<0x118, 0xf>(x);
+  x = dpp_max_step<0x142, 0xa>(x);
+  x = dpp_max_step<0x143, 0xc>(x);
+  return x;
+}
+
 // The instances of the workgroup's Gaussians (the same 256 positions as the
 // preprocess launch), written from its first slot on, and the radix-sort
 // digit histograms of their keys. Slot layout: the workgroup's 64-Gaussian
@@ -550,6 +572,7 @@ __global__ void __launch_bounds__(kPreThreads) k_emit(KCfg cfg, ViewSet vs, Ws w
   __shared__ uint32_t s_hist[4][256];
   __shared__ uint32_t s_wsum[kPreThreads / 64];
   __shared__ uint32_t s_gidx[kPreThreads];
+  __shared__ uint32_t s_mark[kPreThreads / 64][64];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t blk = blockIdx.x;
@@ -606,32 +629,61 @@ __global__ void __launch_bounds__(kPreThreads) k_emit(KCfg cfg, ViewSet vs, Ws w
     }
   }
 
-  // Instances to memory, one per loop iteration, balanced over the
-  // workgroup: instance e belongs to the last (group, view, lane) entry
-  // starting at or before it.
+  // Instances to memory in windows of 64 consecutive instances, each wave
+  // taking every fourth window. Instance e belongs to the last (group,
+  // view, lane) entry starting at or before it. The owner of a window's
+  // first instance comes from a 64-way search (two rounds of one LDS read
+  // per lane and a ballot); every later entry that starts inside the window
+  // marks the lane of its first instance with its distance from that owner,
+  // and an inclusive max-scan of the marks gives each lane its owner.
   uint16_t *k16 = reinterpret_cast<uint16_t *>(w.keys[0]);
   uint32_t *k32 = reinterpret_cast<uint32_t *>(w.keys[0]);
-  for (uint32_t e = tid; e < block_total; e += kPreThreads) {
-    int lo = 0, hi = nent;
+  // instances e < room fit below the capacity
+  const unsigned long long cap = (unsigned long long)w.capacity;
+  const uint32_t room =
+      base >= cap ? 0u : (uint32_t)min(cap - base, (unsigned long long)0xffffffffu);
+  for (uint32_t e0 = (uint32_t)wave * 64u; e0 < block_total; e0 += kPreThreads) {
+    int lo = 0, hi = nent;   // s_start[lo] <= e0 < s_start[hi]
     while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (s_start[mid] <= e) lo = mid; else hi = mid;
+      const int step = (hi - lo + 63) >> 6;
+      const int idx = lo + lane * step;
+      const bool t = idx < hi && s_start[idx] <= e0;
+      const uint64_t bal = __ballot(t);
+      const int last = 63 - (int)__builtin_clzll(bal);   // lane 0 always holds
+      lo += last * step;
+      hi = min(lo + step, hi);
     }
-    uint32_t rank = e - s_start[lo];
-    const int grp = lo / (64 * nviews);
-    const int v = MV ? (lo >> 6) - grp * nviews : 0;
-    const int owner = grp * 64 + (lo & 63);
+    s_mark[wave][lane] = 0u;
+    __builtin_amdgcn_wave_barrier();
+    for (int jb = lo + 1; jb < nent; jb += 64) {
+      const int j = jb + lane;
+      const uint32_t st = j < nent ? s_start[j] : 0xffffffffu;
+      if (st < e0 + 64u) atomicMax(&s_mark[wave][st - e0], (uint32_t)(j - lo));
+      if (__ballot(st >= e0 + 64u)) break;   // later entries start later still
+    }
+    __builtin_amdgcn_wave_barrier();
+    const int ent = lo + (int)wave_incl_max(s_mark[wave][lane]);
+    const uint32_t e = e0 + (uint32_t)lane;
+    if (e >= block_total) continue;
+    uint32_t rank = e - s_start[ent];
+    const int grp = ent / (64 * nviews);
+    const int v = MV ? (ent >> 6) - grp * nviews : 0;
+    const int owner = grp * 64 + (ent & 63);
     const uint32_t gid = s_gidx[owner];
     const uint32_t pr = s_vrect[v][owner];
     const uint32_t rw = pr >> 20;
-    // With a tile mask, the rank-th surviving tile is the rank-th set bit.
+    // With a tile mask, the rank-th surviving tile is the rank-th set bit:
+    // the half that holds it, then halving widths.
     const unsigned long long mk = s_vmask[v][owner];
     if (mk) {
-      unsigned long long m = mk;
-      uint32_t pos = 0, k = rank;
+      const uint32_t mlo = (uint32_t)mk, plo = (uint32_t)__popc(mlo);
+      const bool in_lo = rank < plo;
+      uint32_t m = in_lo ? mlo : (uint32_t)(mk >> 32);
+      uint32_t k = in_lo ? rank : rank - plo;
+      uint32_t pos = in_lo ? 0u : 32u;
 #pragma unroll
-      for (int wd = 32; wd >= 1; wd >>= 1) {
-        const uint32_t c = (uint32_t)__popcll(m & ((1ull << wd) - 1ull));
+      for (int wd = 16; wd >= 1; wd >>= 1) {
+        const uint32_t c = (uint32_t)__popc(m & ((1u << wd) - 1u));
         if (k >= c) {
           k -= c;
           m >>= wd;
@@ -650,10 +702,9 @@ __global__ void __launch_bounds__(kPreThreads) k_emit(KCfg cfg, ViewSet vs, Ws w
     const uint32_t tx = (pr & 1023u) + (uint32_t)rx;
     const uint32_t key = (uint32_t)vs.v[v].tile_base + ty * (uint32_t)vs.v[v].tiles_x + tx;
     for (int p = 0; p < w.passes; ++p) atomicAdd(&s_hist[p][(key >> (8 * p)) & 255u], 1u);
-    const unsigned long long pos = base + e;
-    if (pos < (unsigned long long)w.capacity) {
-      if (w.key16) k16[pos] = (uint16_t)key; else k32[pos] = key;
-      w.vals[0][pos] = gid;
+    if (e < room) {
+      if (w.key16) k16[base + e] = (uint16_t)key; else k32[base + e] = key;
+      w.vals[0][base + e] = gid;
     }
   }
   __syncthreads();
@@ -821,7 +872,7 @@ __device__ __forceinline__ void sh_backward(const float *wsv, const double dir[3
 // Gaussian's summed moments for the view into gradients of the Pluecker
 // coefficients (float64) and those into parameter gradients.
 template <int DEG, bool MV>
-__global__ void __launch_bounds__(256) k_preprocess_bwd(GaussPtrs gp, GradPtrs gr, KCfg cfg,
+__global__ void __launch_bounds__(256, MV ? 2 : 1) k_preprocess_bwd(GaussPtrs gp, GradPtrs gr, KCfg cfg,
                                                          ViewSet vs, Ws w) {
   constexpr int NB = (DEG + 1) * (DEG + 1);
   __shared__ float s_acc[4][kPartialFloats][64];

@@ -7,8 +7,8 @@
 // Three launches per 8-bit digit, none of whose workgroups waits for
 // another. The keys are cut into chunks of 4096 in list order.
 //   count:   each workgroup counts the digits of its chunk (LDS adds) and
-//            stores the 256 counts as the chunk's line of a count table;
-//   scan:    one workgroup per digit turns the digit's chunk counts into the
+//            stores the 256 counts into a digit-major table;
+//   scan:    one workgroup per digit turns its row of chunk counts into the
 //            global start of the digit's run from each chunk (the digit's
 //            base is the sum of the smaller digits' totals, which the
 //            preprocess counted while it emitted the keys);
@@ -17,6 +17,10 @@
 //            digit's run at the start the scan gave it, so consecutive
 //            lanes store consecutive addresses.
 // A pass reads its keys twice and its values once and writes both once.
+// The chunks are dealt to the eight XCDs (workgroups go round-robin over
+// them) in contiguous ranges, so that the 32 chunks of a 128-byte line of a
+// digit row are counted, and read back, on one XCD, and adjacent digit runs
+// are written from one L2.
 #include "common.h"
 
 namespace htgs {
@@ -26,14 +30,14 @@ constexpr int kScanItems = 8;   // chunk counts per thread per round of the scan
 
 // What a sort works on: the item count (a device word, or a fixed number),
 // the capacity beyond which nothing is sorted, the global digit histograms
-// and the per-chunk count and start tables.
+// and the per-chunk count table (counts, then run starts).
 struct SortJob {
   const unsigned long long *count;  // null: n_fixed items
   uint64_t n_fixed;
   int64_t capacity;
   const uint32_t *hist;             // [kHistCopies][4][256]
-  uint32_t *cnt;                    // [passes][stride][256]: digit counts per chunk
-  uint32_t *start;                  // [passes][256][stride]: global start per (digit, chunk)
+  uint32_t *cnt;                    // [passes][256][stride]: digit counts per chunk, then
+                                    // the global start of each (digit, chunk) run
   int64_t stride;
 };
 
@@ -44,6 +48,13 @@ __device__ __forceinline__ bool sort_items(const SortJob &job, uint64_t &items) 
   if (tot > (unsigned long long)job.capacity) return false;
   items = tot;
   return true;
+}
+
+// Chunk of workgroup b < nchunks: XCD b mod 8 takes a contiguous range of
+// the chunks (the first nchunks mod 8 XCDs one more).
+__device__ __forceinline__ uint64_t chunk_of(uint64_t b, uint64_t nchunks) {
+  const uint64_t q = nchunks >> 3, r = nchunks & 7, x = b & 7, i = b >> 3;
+  return x * q + (x < r ? x : r) + i;
 }
 
 // Lanes of the wave whose digit equals this lane's, among the lanes of
@@ -97,9 +108,10 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_count(SortJob job, int pa
   __shared__ uint32_t s_cnt[256];
   uint64_t I;
   if (!sort_items(job, I)) return;
-  const uint64_t chunk = blockIdx.x;
+  const uint64_t nchunks = (I + kSortChunk - 1) / kSortChunk;
+  if (blockIdx.x >= nchunks) return;  // uniform over the workgroup
+  const uint64_t chunk = chunk_of(blockIdx.x, nchunks);
   const uint64_t cbase = chunk * kSortChunk;
-  if (cbase >= I) return;  // uniform over the workgroup
   const int tid = threadIdx.x, lane = tid & 63;
   s_cnt[tid] = 0u;
   const int shift = 8 * pass;
@@ -143,13 +155,11 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_count(SortJob job, int pa
     }
   }
   __syncthreads();
-  job.cnt[((size_t)pass * (size_t)job.stride + chunk) * 256 + tid] = s_cnt[tid];
+  job.cnt[((size_t)pass * 256 + tid) * (size_t)job.stride + chunk] = s_cnt[tid];
 }
 
-// One workgroup per digit: exclusive scan of the digit's counts over the
-// chunks (a column of the chunk-major count table, so that the count
-// launch writes whole lines), plus the digit's base, written as the digit's
-// row of the start table (read by the scatter launch).
+// One workgroup per digit: exclusive scan of its row of chunk counts, plus
+// the digit's base, in place.
 __global__ void __launch_bounds__(256) k_sort_scan(SortJob job, int pass) {
   __shared__ uint32_t s_wsum[4];
   __shared__ uint32_t s_base;
@@ -168,13 +178,18 @@ __global__ void __launch_bounds__(256) k_sort_scan(SortJob job, int pass) {
   if (tid == 0) s_base = s_wsum[0] + s_wsum[1] + s_wsum[2] + s_wsum[3];
   __syncthreads();
   uint32_t carry = s_base;
-  const uint32_t *col = job.cnt + (size_t)pass * (size_t)job.stride * 256 + dg;
-  uint32_t *row = job.start + ((size_t)pass * 256 + dg) * (size_t)job.stride;
+  uint32_t *row = job.cnt + ((size_t)pass * 256 + dg) * (size_t)job.stride;
   for (uint64_t c0 = 0; c0 < nchunks; c0 += 256 * kScanItems) {
     const uint64_t cb = c0 + (uint64_t)tid * kScanItems;
     uint32_t v[kScanItems];
+    if (cb + kScanItems <= nchunks) {
+      const uint4 a = *reinterpret_cast<const uint4 *>(row + cb);
+      const uint4 b = *reinterpret_cast<const uint4 *>(row + cb + 4);
+      v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+    } else {
 #pragma unroll
-    for (int j = 0; j < kScanItems; ++j) v[j] = cb + j < nchunks ? col[(cb + j) * 256] : 0u;
+      for (int j = 0; j < kScanItems; ++j) v[j] = cb + j < nchunks ? row[cb + j] : 0u;
+    }
     uint32_t sum = 0;
 #pragma unroll
     for (int j = 0; j < kScanItems; ++j) sum += v[j];
@@ -214,12 +229,13 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_scatter(SortJob job, int 
 
   uint64_t I;
   if (!sort_items(job, I)) return;
-  const uint64_t chunk = blockIdx.x;
+  const uint64_t nchunks = (I + kSortChunk - 1) / kSortChunk;
+  if (blockIdx.x >= nchunks) return;  // uniform over the workgroup
+  const uint64_t chunk = chunk_of(blockIdx.x, nchunks);
   const uint64_t cbase = chunk * kSortChunk;
-  if (cbase >= I) return;  // uniform over the workgroup
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   // global start of this chunk's run of digit tid (from the scan)
-  const uint32_t run_start = job.start[((size_t)pass * 256 + tid) * (size_t)job.stride + chunk];
+  const uint32_t run_start = job.cnt[((size_t)pass * 256 + tid) * (size_t)job.stride + chunk];
   for (int i = tid; i < kSortWaves * 256; i += kSortThreads) (&s_wh[0][0])[i] = 0u;
   __syncthreads();
 
@@ -465,7 +481,6 @@ static hipError_t sort_impl(const Ws &w, hipStream_t s) {
   job.capacity = w.capacity;
   job.hist = w.hist;
   job.cnt = w.sort_cnt;
-  job.start = w.sort_start;
   job.stride = w.chunk_stride;
   return sort_passes<KeyT>(job, w.passes, w.key_bits, (w.capacity + kSortChunk - 1) / kSortChunk,
                            w.keys, w.vals, s);
@@ -523,7 +538,6 @@ hipError_t launch_depth_sort(const Ws &w, const float *means, int64_t n, const f
   job.capacity = n;
   job.hist = w.dhist;
   job.cnt = w.dcnt;
-  job.start = w.dstart;
   job.stride = w.dchunk_stride;
   void *keys[2] = {w.dkeys[0], w.dkeys[1]};
   return sort_passes<uint32_t>(job, 4, 32, (n + kSortChunk - 1) / kSortChunk, keys, w.dvals, s);
