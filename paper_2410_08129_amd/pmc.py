@@ -40,8 +40,14 @@ KERNEL_SOURCES = {
     "k_raster_bwd": ("raster.hip", "common.h"),
     "k_preprocess": ("preprocess.hip", "common.h"),
     "k_preprocess_bwd": ("preprocess.hip", "common.h"),
-    "k_sort_pass": ("sort.hip", "common.h"),
+    "k_preprocess_scan": ("preprocess.hip", "common.h"),
+    "k_emit": ("preprocess.hip", "common.h"),
+    "k_sort_count": ("sort.hip", "common.h"),
+    "k_sort_scan": ("sort.hip", "common.h"),
+    "k_sort_scatter": ("sort.hip", "common.h"),
     "k_ranges": ("sort.hip", "common.h"),
+    "k_tile_order_count": ("sort.hip", "common.h"),
+    "k_tile_order_place": ("sort.hip", "common.h"),
     "k_fill_zero": ("preprocess.hip", "common.h"),
 }
 
