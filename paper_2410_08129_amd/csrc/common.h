@@ -150,6 +150,51 @@ __device__ __forceinline__ uint32_t *hist_copy(uint32_t *hist) {
   return hist + (blockIdx.x % kHistCopies) * (4 * 256);
 }
 
+// LDS digit histogram of one wave's keys, in C copies of kHistPadWords
+// words (copy c at c * kHistPadWords, so that the copies of a digit lie in
+// different banks): when every valid lane holds one digit, one add of
+// their number; for digits of at most two bits, one ballot per digit value
+// and one add each; otherwise one add per lane into copy lane % C. Lanes of
+// one wave that add to one address are served one after another, and tile
+// keys often share their high digits across a wave (one add per lane on
+// one copy made the high passes' counting many times slower). Called by
+// all lanes of the wave.
+constexpr int kHistLaneCopies = 4, kHistPadWords = 257;
+constexpr int kHistWords = kHistLaneCopies * kHistPadWords;
+template <int C = kHistLaneCopies>
+__device__ __forceinline__ void wave_hist_add(uint32_t *h, uint32_t d, bool valid, int nbits) {
+  const uint64_t vm = __ballot(valid);
+  if (vm == 0ull) return;
+  const int lane = __lane_id();
+  const int lead = (int)__builtin_ctzll(vm);
+  const uint32_t d0 = (uint32_t)__builtin_amdgcn_readlane((int)d, lead);
+  if (__ballot(valid && d != d0) == 0ull) {
+    if (lane == lead) atomicAdd(&h[d0], (uint32_t)__popcll(vm));
+    return;
+  }
+  if (nbits <= 2) {
+    for (uint32_t v = 0; v < (1u << nbits); ++v) {
+      const uint32_t c = (uint32_t)__popcll(__ballot(valid && d == v));
+      if (lane == lead && c) atomicAdd(&h[v], c);
+    }
+    return;
+  }
+  if (valid) atomicAdd(&h[(lane % C) * kHistPadWords + d], 1u);
+}
+// Digit d of a histogram written by wave_hist_add<C>.
+template <int C = kHistLaneCopies>
+__device__ __forceinline__ uint32_t hist_total(const uint32_t *h, int d) {
+  uint32_t t = 0;
+#pragma unroll
+  for (int c = 0; c < C; ++c) t += h[c * kHistPadWords + d];
+  return t;
+}
+// Width of sort pass p's digit for keys of key_bits bits.
+__host__ __device__ __forceinline__ int pass_bits(int key_bits, int p) {
+  const int r = key_bits - 8 * p;
+  return r < 8 ? r : 8;
+}
+
 // Fragment counters: kCounterSpread words, each in a 128-byte line of its
 // own, added to by workgroup blockIdx % kCounterSpread and summed when
 // read. With one word, the raster's tens of thousands of workgroups queued

@@ -569,14 +569,16 @@ __global__ void __launch_bounds__(kPreThreads) k_emit(KCfg cfg, ViewSet vs, Ws w
   __shared__ uint32_t s_start[NVL * kPreThreads + 1];
   __shared__ uint32_t s_vrect[NVL][kPreThreads];
   __shared__ unsigned long long s_vmask[NVL][kPreThreads];
-  __shared__ uint32_t s_hist[4][256];
+  // (the batched form's per-view tables leave room for one copy)
+  constexpr int HC = MV ? 1 : kHistLaneCopies;
+  __shared__ uint32_t s_hist[4][HC * kHistPadWords];
   __shared__ uint32_t s_wsum[kPreThreads / 64];
   __shared__ uint32_t s_gidx[kPreThreads];
   __shared__ uint32_t s_mark[kPreThreads / 64][64];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t blk = blockIdx.x;
-  for (int i = tid; i < 4 * 256; i += kPreThreads) (&s_hist[0][0])[i] = 0u;
+  for (int i = tid; i < 4 * HC * kHistPadWords; i += kPreThreads) (&s_hist[0][0])[i] = 0u;
   int64_t g;
   const bool live = gaussian_at(w, cfg, blk * kPreThreads + tid, g);
   s_gidx[tid] = (uint32_t)g;
@@ -664,8 +666,8 @@ __global__ void __launch_bounds__(kPreThreads) k_emit(KCfg cfg, ViewSet vs, Ws w
     __builtin_amdgcn_wave_barrier();
     const int ent = lo + (int)wave_incl_max(s_mark[wave][lane]);
     const uint32_t e = e0 + (uint32_t)lane;
-    if (e >= block_total) continue;
-    uint32_t rank = e - s_start[ent];
+    const bool valid = e < block_total;
+    uint32_t rank = valid ? e - s_start[ent] : 0u;
     const int grp = ent / (64 * nviews);
     const int v = MV ? (ent >> 6) - grp * nviews : 0;
     const int owner = grp * 64 + (ent & 63);
@@ -701,8 +703,12 @@ __global__ void __launch_bounds__(kPreThreads) k_emit(KCfg cfg, ViewSet vs, Ws w
     const uint32_t ty = ((pr >> 10) & 1023u) + (uint32_t)qy;
     const uint32_t tx = (pr & 1023u) + (uint32_t)rx;
     const uint32_t key = (uint32_t)vs.v[v].tile_base + ty * (uint32_t)vs.v[v].tiles_x + tx;
-    for (int p = 0; p < w.passes; ++p) atomicAdd(&s_hist[p][(key >> (8 * p)) & 255u], 1u);
-    if (e < room) {
+    // (one add per lane, spread over HC copies: the wave-level paths of
+    // wave_hist_add cost the emit more than the conflicts they avoid)
+    if (valid)
+      for (int p = 0; p < w.passes; ++p)
+        atomicAdd(&s_hist[p][(lane % HC) * kHistPadWords + ((key >> (8 * p)) & 255u)], 1u);
+    if (valid && e < room) {
       if (w.key16) k16[base + e] = (uint16_t)key; else k32[base + e] = key;
       w.vals[0][base + e] = gid;
     }
@@ -710,7 +716,7 @@ __global__ void __launch_bounds__(kPreThreads) k_emit(KCfg cfg, ViewSet vs, Ws w
   __syncthreads();
   uint32_t *hist = hist_copy(w.hist);
   for (int p = 0; p < w.passes; ++p) {
-    const uint32_t c = s_hist[p][tid];
+    const uint32_t c = hist_total<HC>(s_hist[p], tid);
     if (c) atomicAdd(&hist[p * 256 + tid], c);
   }
 }

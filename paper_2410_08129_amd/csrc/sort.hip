@@ -105,15 +105,15 @@ __device__ __forceinline__ T load_at(const T *base, uint32_t i) {
 template <typename KeyT>
 __global__ void __launch_bounds__(kSortThreads) k_sort_count(SortJob job, int pass, int nbits,
                                                               const KeyT *__restrict__ kin) {
-  __shared__ uint32_t s_cnt[256];
+  __shared__ uint32_t s_cnt[kHistWords];
   uint64_t I;
   if (!sort_items(job, I)) return;
   const uint64_t nchunks = (I + kSortChunk - 1) / kSortChunk;
   if (blockIdx.x >= nchunks) return;  // uniform over the workgroup
   const uint64_t chunk = chunk_of(blockIdx.x, nchunks);
   const uint64_t cbase = chunk * kSortChunk;
-  const int tid = threadIdx.x, lane = tid & 63;
-  s_cnt[tid] = 0u;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < kHistWords; i += kSortThreads) s_cnt[i] = 0u;
   const int shift = 8 * pass;
   uint32_t dg[kSortItems];
   const bool whole = cbase + kSortChunk <= I;
@@ -143,19 +143,11 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_count(SortJob job, int pa
     }
   }
   __syncthreads();
-  // One LDS add per key; a wave whose keys share one digit adds once.
 #pragma unroll
-  for (int i = 0; i < kSortItems; ++i) {
-    const bool valid = whole || cbase + (uint64_t)i * kSortThreads + tid < I;
-    const uint32_t first = __builtin_amdgcn_readfirstlane(dg[i]);
-    if (whole && __ballot(dg[i] != first) == 0ull) {
-      if (lane == 0) atomicAdd(&s_cnt[first], 64u);
-    } else if (valid) {
-      atomicAdd(&s_cnt[dg[i]], 1u);
-    }
-  }
+  for (int i = 0; i < kSortItems; ++i)
+    wave_hist_add(s_cnt, dg[i], whole || cbase + (uint64_t)i * kSortThreads + tid < I, nbits);
   __syncthreads();
-  job.cnt[((size_t)pass * 256 + tid) * (size_t)job.stride + chunk] = s_cnt[tid];
+  job.cnt[((size_t)pass * 256 + tid) * (size_t)job.stride + chunk] = hist_total(s_cnt, tid);
 }
 
 // One workgroup per digit: exclusive scan of its row of chunk counts, plus
@@ -496,26 +488,33 @@ __global__ void __launch_bounds__(256) k_depth_keys(const float *__restrict__ me
                                                      uint32_t *__restrict__ keys,
                                                      uint32_t *__restrict__ idx,
                                                      uint32_t *__restrict__ hist) {
-  __shared__ uint32_t s_hist[4][256];
-  for (int i = threadIdx.x; i < 4 * 256; i += blockDim.x) (&s_hist[0][0])[i] = 0u;
+  __shared__ uint32_t s_hist[4][kHistWords];
+  for (int i = threadIdx.x; i < 4 * kHistWords; i += blockDim.x) (&s_hist[0][0])[i] = 0u;
   __syncthreads();
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n; g += stride) {
-    const double z = (((double)r0 * (double)means[3 * g] + (double)r1 * (double)means[3 * g + 1]) +
-                      (double)r2 * (double)means[3 * g + 2]) + (double)t;
-    float zf = (float)z;
-    if (zf == 0.0f) zf = 0.0f;
-    const uint32_t u = __float_as_uint(zf);
-    const uint32_t key = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-    keys[g] = key;
-    idx[g] = (uint32_t)g;
+  // (the trip count is uniform over the workgroup: the histogram adds are
+  // made by whole waves)
+  for (int64_t b = (int64_t)blockIdx.x * blockDim.x; b < n; b += stride) {
+    const int64_t g = b + threadIdx.x;
+    const bool valid = g < n;
+    uint32_t key = 0u;
+    if (valid) {
+      const double z = (((double)r0 * (double)means[3 * g] + (double)r1 * (double)means[3 * g + 1]) +
+                        (double)r2 * (double)means[3 * g + 2]) + (double)t;
+      float zf = (float)z;
+      if (zf == 0.0f) zf = 0.0f;
+      const uint32_t u = __float_as_uint(zf);
+      key = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+      keys[g] = key;
+      idx[g] = (uint32_t)g;
+    }
 #pragma unroll
-    for (int p = 0; p < 4; ++p) atomicAdd(&s_hist[p][(key >> (8 * p)) & 255u], 1u);
+    for (int p = 0; p < 4; ++p) wave_hist_add(s_hist[p], (key >> (8 * p)) & 255u, valid, 8);
   }
   __syncthreads();
   uint32_t *hc = hist_copy(hist);
   for (int i = threadIdx.x; i < 4 * 256; i += blockDim.x) {
-    const uint32_t c = (&s_hist[0][0])[i];
+    const uint32_t c = hist_total(s_hist[i >> 8], i & 255);
     if (c) atomicAdd(&hc[i], c);
   }
 }
