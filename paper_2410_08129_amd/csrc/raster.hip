@@ -715,13 +715,15 @@ __global__ void __launch_bounds__(TW * TH)
 // ---------------------------------------------------------------------------
 // Backward
 // ---------------------------------------------------------------------------
+// Per-pixel adjoint factors of the hybrid backward in LDS (the core's list
+// positions are read from the forward state when a chunk's core table is
+// built, which keeps the row at 24 floats for K = 8).
 template <int KMAX>
 struct PixLayout {
-  // G(3), w1, q1, q2, pad(2), dL/dalpha_i[KMAX], T_i[KMAX], list position_i[KMAX]
+  // G(3), w1, q1, q2, pad(2), dL/dalpha_i[KMAX], T_i[KMAX]
   static constexpr int kCoef = 8;
   static constexpr int kT = 8 + KMAX;
-  static constexpr int kPos = 8 + 2 * KMAX;
-  static constexpr int kStride = ((8 + 3 * KMAX) + 3) / 4 * 4;
+  static constexpr int kStride = ((8 + 2 * KMAX) + 3) / 4 * 4;
 };
 
 // Gradient contribution of one fragment (lane's splat at pixel Pp, column c
@@ -845,7 +847,19 @@ __device__ __forceinline__ void bwd_tile(const TileInfo &ti, const Ws &w, const 
   // core. The byte swizzle swz(q) = ((q >> 1) & 15) << 2 spreads the fill
   // (each lane writes its own pixel's 64-byte row) over the banks; the
   // reads (one row, one byte per lane) stay conflict-free.
-  __shared__ uint8_t s_slot[BW][64][64];
+  // With a core of at most 8 entries the table holds core index + 1 in
+  // nibbles (two lanes per byte; a pixel's row is 32 bytes): half the LDS of
+  // byte rows, 10 KiB in all for an 8x8 tile, which made the 8x8 backward
+  // ~4% faster. Paired waves keep byte rows, which double as the buffer
+  // through which they hand over their sums.
+  constexpr bool NIB = KMAX <= 8 && !(NB == 2 && BW == 4);
+  constexpr int SB = NIB ? 32 : 64;
+  __shared__ uint8_t s_slot[BW][64][SB];
+  // core index (or -1) of table row entry idx
+  auto core_of = [](const uint8_t *row, int idx) -> int {
+    if constexpr (NIB) return (int)((row[idx >> 1] >> ((idx & 1) * 4)) & 15u) - 1;
+    else return (int)row[idx] - 1;
+  };
 
   const ViewParams &V = vs.v[ti.v];
   const int tid = threadIdx.x;
@@ -930,7 +944,6 @@ __device__ __forceinline__ void bwd_tile(const TileInfo &ti, const Ws &w, const 
     for (int i = 0; i < KMAX; ++i) {
       Pp[L::kCoef + i] = coef[i];
       Pp[L::kT + i] = Ti[i];
-      Pp[L::kPos + i] = __int_as_float(pos[i]);
     }
   }
   __syncthreads();
@@ -1000,20 +1013,30 @@ __device__ __forceinline__ void bwd_tile(const TileInfo &ti, const Ws &w, const 
       if (__ballot(hitb) == 0ull) continue;
       // Core table of this block for this chunk: lane = block pixel.
       {
-        const int p = (by + (lane >> 3)) * TW + bx + (lane & 7);
-        const float *Pp = sp_all + p * L::kStride;
+        // list positions of the pixel's core from the forward state
+        const float *tst = tstate + blk * 64 + lane;
+        int cps[KMAX];
+#pragma unroll
+        for (int i = 0; i < KMAX; ++i) cps[i] = i < K ? __float_as_int(tst[(int64_t)(2 * K + i) * NT]) : -1;
         // cleared with consecutive lanes on consecutive words (no bank
         // conflicts), then each lane fills its own pixel's row
         uint32_t *tab = reinterpret_cast<uint32_t *>(&s_slot[wave][0][0]);
 #pragma unroll
-        for (int k = 0; k < 16; ++k) tab[k * 64 + lane] = 0u;
+        for (int k = 0; k < SB / 4; ++k) tab[k * 64 + lane] = 0u;
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int i = 0; i < KMAX; ++i) {
           if (i < K) {
-            const int ps = __float_as_int(Pp[L::kPos + i]);
+            const int ps = cps[i];
             const uint32_t dl = (uint32_t)(ps - (int)(c * 64u));
-            if (ps >= 0 && dl < 64u) s_slot[wave][lane][dl ^ slot_swz(lane)] = (uint8_t)(i + 1);
+            if (ps >= 0 && dl < 64u) {
+              if constexpr (NIB) {
+                uint8_t *b = &s_slot[wave][lane][(dl ^ slot_swz(lane)) >> 1];
+                *b = (uint8_t)(*b | ((i + 1) << ((dl & 1u) * 4u)));
+              } else {
+                s_slot[wave][lane][dl ^ slot_swz(lane)] = (uint8_t)(i + 1);
+              }
+            }
           }
         }
         __builtin_amdgcn_wave_barrier();
@@ -1051,13 +1074,13 @@ __device__ __forceinline__ void bwd_tile(const TileInfo &ti, const Ws &w, const 
           const float *P0 = sp_all + ((by + row) * TW + bx + col) * L::kStride;
           if (f0) {
             ++nfr;
-            bwd_fragment<KMAX>(op, rgb, P0, col, dd0, mm0, (int)s_slot[wave][q][lane ^ slot_swz(q)] - 1, amax,
+            bwd_fragment<KMAX>(op, rgb, P0, col, dd0, mm0, core_of(s_slot[wave][q], lane ^ slot_swz(q)), amax,
                                rs, acc);
           }
           if (f1) {
             ++nfr;
             bwd_fragment<KMAX>(op, rgb, P0 + L::kStride, col + 1, dd1, mm1,
-                               (int)s_slot[wave][q + 1][lane ^ slot_swz(q + 1)] - 1, amax, rs, acc);
+                               core_of(s_slot[wave][q + 1], lane ^ slot_swz(q + 1)), amax, rs, acc);
           }
         }
         if constexpr (BX > 1) {
