@@ -152,13 +152,13 @@ __device__ __forceinline__ uint32_t *hist_copy(uint32_t *hist) {
 
 // LDS digit histogram of one wave's keys, in C copies of kHistPadWords
 // words (copy c at c * kHistPadWords, so that the copies of a digit lie in
-// different banks): when every valid lane holds one digit, one add of
-// their number; for digits of at most two bits, one ballot per digit value
-// and one add each; otherwise one add per lane into copy lane % C. Lanes of
-// one wave that add to one address are served one after another, and tile
-// keys often share their high digits across a wave (one add per lane on
-// one copy made the high passes' counting many times slower). Called by
-// all lanes of the wave.
+// different banks): for digits of at most two bits, one ballot per digit
+// value and one add each; otherwise one add per lane into copy lane % C.
+// Lanes of one wave that add to one address are served one after another,
+// and tile keys often share their high digits across a wave (one add per
+// lane on one copy made the high passes' counting many times slower; a
+// test for a wave whose keys all share one digit cost more than it saved).
+// Called by all lanes of the wave.
 constexpr int kHistLaneCopies = 4, kHistPadWords = 257;
 constexpr int kHistWords = kHistLaneCopies * kHistPadWords;
 template <int C = kHistLaneCopies>
@@ -167,11 +167,6 @@ __device__ __forceinline__ void wave_hist_add(uint32_t *h, uint32_t d, bool vali
   if (vm == 0ull) return;
   const int lane = __lane_id();
   const int lead = (int)__builtin_ctzll(vm);
-  const uint32_t d0 = (uint32_t)__builtin_amdgcn_readlane((int)d, lead);
-  if (__ballot(valid && d != d0) == 0ull) {
-    if (lane == lead) atomicAdd(&h[d0], (uint32_t)__popcll(vm));
-    return;
-  }
   if (nbits <= 2) {
     for (uint32_t v = 0; v < (1u << nbits); ++v) {
       const uint32_t c = (uint32_t)__popcll(__ballot(valid && d == v));
