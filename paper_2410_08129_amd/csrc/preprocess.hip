@@ -197,6 +197,45 @@ __device__ __forceinline__ void add_row(float *dst, const float *v) {
   }
 }
 
+// Inclusive maximum and sum over the lanes of a wave by DPP moves (shifts
+// by 1, 2, 4, 8 inside each row of 16 lanes, then the row ends broadcast
+// to the rows after them); lanes whose source is outside receive 0. Every
+// lane of the wave must be active.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint32_t dpp_move_u32(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROW_MASK, 0xf, false);
+}
+__device__ __forceinline__ uint32_t wave_incl_max(uint32_t x) {
+  x = max(x, dpp_move_u32<0x111, 0xf>(x));
+  x = max(x, dpp_move_u32<0x112, 0xf>(x));
+  x = max(x, dpp_move_u32<0x114, 0xf>(x));
+  x = max(x, dpp_move_u32<0x118, 0xf>(x));
+  x = max(x, dpp_move_u32<0x142, 0xa>(x));
+  x = max(x, dpp_move_u32<0x143, 0xc>(x));
+  return x;
+}
+__device__ __forceinline__ uint32_t wave_incl_sum(uint32_t x) {
+  x += dpp_move_u32<0x111, 0xf>(x);
+  x += dpp_move_u32<0x112, 0xf>(x);
+  x += dpp_move_u32<0x114, 0xf>(x);
+  x += dpp_move_u32<0x118, 0xf>(x);
+  x += dpp_move_u32<0x142, 0xa>(x);
+  x += dpp_move_u32<0x143, 0xc>(x);
+  return x;
+}
+
+// x / d for 0 <= x < 2^16 and 1 <= d <= 1024 (pixel index by tile size):
+// x and d are exact in float32 and the product with the reciprocal is off
+// by at most one, which one remainder test corrects (an integer division
+// by a value not known at compile time is a sequence of ~15 instructions).
+__device__ __forceinline__ int div_px(int x, int d) {
+  int q = (int)((float)x * __builtin_amdgcn_rcpf((float)d));
+  const int r = x - q * d;
+  if (r < 0) --q;
+  else if (r >= d) ++q;
+  return q;
+}
+
 // Tiles of a screen box that the splat's rho_c-ellipse reaches. With the
 // Pluecker vectors affine in the pixel offset (p, q) from the reference
 // pixel, d = Dc + p Dx + q Dy and m = Mc + p Mx + q My, a pixel is a fragment
@@ -237,55 +276,143 @@ __device__ __forceinline__ double conic_at(const Conic &c, double p, double q) {
 // to its right boundary's maximum; the left boundary is convex in q, so its
 // minimum over the band is at the band point nearest the ellipse's
 // leftmost point (likewise on the right). The pixel-centre columns in that
-// span give the row's tiles. *valid is false when the quadratic part is not
-// clearly positive definite (then every tile stays).
-__device__ inline unsigned long long cull_mask(const Conic &c, int4 rect, int tw, int th,
-                                               double x0, double x1, double y0, double y1,
-                                               double ixd, double iyd, bool *valid) {
+// span give the row's tiles. The conic is unusable (every tile stays) when
+// its quadratic part is not clearly positive definite.
+//
+// The rows of a wave's Gaussians are tested by the whole wave: each lane
+// puts its Gaussian's ellipse extent in LDS (cull_setup), then the (lane,
+// tile row) pairs are dealt to the lanes in windows of 64 (wave_cull_rows).
+// One row per lane and Gaussian left most lanes idle: a wave's Gaussians
+// have ~2 tile rows on average and ~8 at most.
+struct CullExt {                  // one lane's ellipse extent (96 bytes)
+  double A, B, C, Dpp, Epq, Fqq;  // the conic
+  double idp;                     // 1 / Dpp
+  double qmin, qmax;              // q extent of the ellipse
+  double qL, qR;                  // q of its leftmost and rightmost points
+  uint32_t xs, ys;                // covered pixel rect: x0 | x1 << 16, y0 | y1 << 16
+  uint32_t ref;                   // reference pixel ix | iy << 16
+  uint32_t trect;                 // first tile column | first tile row << 16
+};
+struct CullLds {
+  CullExt ext[64];
+  unsigned long long mask[64];    // kept tiles
+  uint32_t mark[64];              // see wave_cull_rows
+};
+
+// This lane's part of the cull: whether the conic is usable (*valid) and,
+// if the ellipse is not empty, its extent in s; returns the number of tile
+// rows to test (0: none; with a usable conic and an empty ellipse no tile
+// is kept).
+__device__ inline uint32_t cull_setup(const Conic &c, int4 rect, double x0, double x1,
+                                      double y0, double y1, double ixd, double iyd, CullLds &s,
+                                      int lane, bool *valid) {
   const double det = c.Dpp * c.Fqq - c.Epq * c.Epq;
   *valid = c.Dpp > 0.0 && c.Fqq > 0.0 && det > 1e-9 * c.Dpp * c.Fqq;
-  if (!*valid) return 0ull;
+  if (!*valid) return 0u;
   const double idet = 1.0 / det;
   const double ps = (c.Epq * c.C - c.Fqq * c.B) * idet, qs = (c.Epq * c.B - c.Dpp * c.C) * idet;
   const double Q0 = conic_at(c, ps, qs);
-  if (!(Q0 < 0.0)) return 0ull;  // empty ellipse: no fragment anywhere
+  if (!(Q0 < 0.0)) return 0u;  // empty ellipse: no fragment anywhere
   const double hp = sqrt(-Q0 * c.Fqq * idet), hq = sqrt(-Q0 * c.Dpp * idet);
-  const double qmin = qs - hq, qmax = qs + hq;
   const double eh = c.Epq * hp / c.Fqq;
-  const double qL = qs + eh, qR = qs - eh;
-  const double idp = 1.0 / c.Dpp;
-  // p extent of the ellipse on the line q: pc(q) +- sqrt(disc(q)) / Dpp
-  auto side = [&](double q, double sgn) {
-    const double b = c.B + c.Epq * q;
-    const double disc = b * b - c.Dpp * (c.A + 2.0 * c.C * q + c.Fqq * q * q);
-    return (-b + sgn * sqrt(fmax(disc, 0.0))) * idp;
-  };
-  const int w = rect.z - rect.x + 1;
-  unsigned long long mask = 0ull;
-  for (int ty = rect.y; ty <= rect.w; ++ty) {
-    const double a = fmax(fmax((double)(ty * th), y0) - iyd, qmin);
-    const double b = fmin(fmin((double)(ty * th + th - 1), y1) - iyd, qmax);
-    if (a > b) continue;
-    const double pl = side(fmin(fmax(qL, a), b), -1.0);
-    const double pr = side(fmin(fmax(qR, a), b), 1.0);
-    const double xlo = fmax(ceil(pl + ixd), x0), xhi = fmin(floor(pr + ixd), x1);
-    if (xlo > xhi) continue;
-    const int t0 = (int)xlo / tw - rect.x, t1 = (int)xhi / tw - rect.x;
-    const unsigned long long run = ((2ull << (t1 - t0)) - 1ull) << t0;
-    mask |= run << ((ty - rect.y) * w);
-  }
-  return mask;
+  CullExt e;
+  e.A = c.A; e.B = c.B; e.C = c.C; e.Dpp = c.Dpp; e.Epq = c.Epq; e.Fqq = c.Fqq;
+  e.idp = 1.0 / c.Dpp;
+  e.qmin = qs - hq;
+  e.qmax = qs + hq;
+  e.qL = qs + eh;
+  e.qR = qs - eh;
+  // (the covered rect and reference pixel are integers below 2^16)
+  e.xs = (uint32_t)x0 | ((uint32_t)x1 << 16);
+  e.ys = (uint32_t)y0 | ((uint32_t)y1 << 16);
+  e.ref = (uint32_t)ixd | ((uint32_t)iyd << 16);
+  e.trect = (uint32_t)rect.x | ((uint32_t)rect.y << 16);
+  s.ext[lane] = e;
+  return (uint32_t)(rect.w - rect.y + 1);
 }
 
-// One Gaussian in one view: cull, box, rect, record. Returns the instance
-// count and writes the tile rect (and the record if the count is non-zero);
-// *packed receives tx0 | ty0 << 10 | width << 20 of a non-empty rect and
-// *mask the surviving tiles of the rect (0 = all).
+// Tile row k of a rect with extent e, w tiles wide: its kept tiles at
+// their bits of the rect's mask.
+__device__ inline unsigned long long cull_row(const CullExt &e, int k, int w, int tw, int th) {
+  const double x0 = (double)(e.xs & 0xffffu), x1 = (double)(e.xs >> 16);
+  const double y0 = (double)(e.ys & 0xffffu), y1 = (double)(e.ys >> 16);
+  const double ixd = (double)(e.ref & 0xffffu), iyd = (double)(e.ref >> 16);
+  const int rx = (int)(e.trect & 0xffffu), ty = (int)(e.trect >> 16) + k;
+  const double a = fmax(fmax((double)(ty * th), y0) - iyd, e.qmin);
+  const double b = fmin(fmin((double)(ty * th + th - 1), y1) - iyd, e.qmax);
+  if (a > b) return 0ull;
+  // p extent of the ellipse on the line q: pc(q) +- sqrt(disc(q)) / Dpp
+  auto side = [&](double q, double sgn) {
+    const double bq = e.B + e.Epq * q;
+    const double disc = bq * bq - e.Dpp * (e.A + 2.0 * e.C * q + e.Fqq * q * q);
+    return (-bq + sgn * sqrt(fmax(disc, 0.0))) * e.idp;
+  };
+  const double pl = side(fmin(fmax(e.qL, a), b), -1.0);
+  const double pr = side(fmin(fmax(e.qR, a), b), 1.0);
+  const double xlo = fmax(ceil(pl + ixd), x0), xhi = fmin(floor(pr + ixd), x1);
+  if (xlo > xhi) return 0ull;
+  const int t0 = div_px((int)xlo, tw) - rx, t1 = div_px((int)xhi, tw) - rx;
+  const unsigned long long run = ((2ull << (t1 - t0)) - 1ull) << t0;
+  return run << (k * w);
+}
+
+// The kept-tile mask of every lane's rect (rows: tile rows to test, 0 for
+// lanes without a cull; w: the rect's width in tiles). All 64 lanes of the
+// wave take part. Pair e of the wave (pairs in lane order, rows in order
+// inside a lane) goes to lane e mod 64 of window e / 64. Its owner is the
+// last lane whose first pair is at or before e: each lane whose first pair
+// lies in the window marks that place with (first pair, width, lane + 1),
+// and a max-scan over the window, seeded with the previous window's last
+// owner, spreads the marks (the first pairs grow with the lane).
+__device__ inline unsigned long long wave_cull_rows(CullLds &s, uint32_t rows, uint32_t w,
+                                                   int tw, int th, int lane) {
+  const uint32_t incl = wave_incl_sum(rows);
+  const uint32_t first = incl - rows;   // < 4096
+  const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+  s.mask[lane] = 0ull;
+  const uint32_t tag = (first << 14) | (w << 7) | ((uint32_t)lane + 1u);
+  uint32_t carry = 0u;   // the previous window's last owner tag
+  for (uint32_t e0 = 0; e0 < total; e0 += 64u) {
+    s.mark[lane] = 0u;
+    __builtin_amdgcn_wave_barrier();
+    if (rows && first >= e0 && first < e0 + 64u) s.mark[first - e0] = tag;
+    __builtin_amdgcn_wave_barrier();
+    uint32_t m = s.mark[lane];
+    if (lane == 0) m = max(m, carry);
+    const uint32_t own = wave_incl_max(m);
+    carry = (uint32_t)__builtin_amdgcn_readlane((int)own, 63);
+    const uint32_t e = e0 + (uint32_t)lane;
+    if (e < total && (own & 127u) != 0u) {
+      const int o = (int)(own & 127u) - 1;
+      const int k = (int)(e - (own >> 14));
+      const unsigned long long bits = cull_row(s.ext[o], k, (int)((own >> 7) & 127u), tw, th);
+      if (bits) atomicOr(&s.mask[o], bits);
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  return s.mask[lane];
+}
+
+// State of one (view, Gaussian) between its own work and the wave's cull.
+struct ViewPending {
+  int4 rect;        // tile rect
+  uint32_t count;   // its tiles
+  bool finish;      // visible: the rect, descriptor and count are still to be written
+  bool cull;        // tiles to be culled with the wave's masks
+  bool valid;       // the cull's conic is usable
+  uint32_t rows;    // tile rows for the wave to test
+  uint32_t width;   // the rect's width in tiles
+};
+
+// One Gaussian in one view: cull, box, rect, record, colour, and the
+// lane's part of the tile cull (in cl). A Gaussian that is not visible
+// gets its empty rect here (finish false); the others are finished by
+// preprocess_view_end once the wave's cull masks are known.
 template <int DEG, bool CULL>
-__device__ inline uint32_t preprocess_view(const GaussPtrs &gp, const KCfg &cfg,
-                                           const ViewParams &V, const Ws &w, int v,
-                                           int64_t g, const Activated &a, uint32_t *packed,
-                                           unsigned long long *mask_out) {
+__device__ inline ViewPending preprocess_view(const GaussPtrs &gp, const KCfg &cfg,
+                                              const ViewParams &V, const Ws &w, int v,
+                                              int64_t g, const Activated &a, CullLds &cl,
+                                              int lane) {
   double Rv[3][3], mv[3];
   view_rows(V, a, Rv, mv);
   const double fx = V.fx, fy = V.fy, cx = V.cx, cy = V.cy;
@@ -319,19 +446,19 @@ __device__ inline uint32_t preprocess_view(const GaussPtrs &gp, const KCfg &cfg,
     y0 = fmax(ceil(p2 - h2 - 0.5), 0.0);
     y1 = fmin(floor(p2 + h2 - 0.5), (double)(V.height - 1));
     if (x0 <= x1 && y0 <= y1) {
-      rect.x = (int)x0 / cfg.tile_w;
-      rect.y = (int)y0 / cfg.tile_h;
-      rect.z = (int)x1 / cfg.tile_w;
-      rect.w = (int)y1 / cfg.tile_h;
+      rect.x = div_px((int)x0, cfg.tile_w);
+      rect.y = div_px((int)y0, cfg.tile_h);
+      rect.z = div_px((int)x1, cfg.tile_w);
+      rect.w = div_px((int)y1, cfg.tile_h);
       count = (uint32_t)((rect.z - rect.x + 1) * (rect.w - rect.y + 1));
     }
   }
   const int64_t vg = (int64_t)v * cfg.n + g;
+  ViewPending pv{rect, count, false, false, false, 0u, (uint32_t)(rect.z - rect.x + 1)};
   if (count == 0) {
     w.rects[vg] = rect;
     w.cflags[vg] = 0u;   // not visible in this view
-    *mask_out = 0ull;
-    return 0;
+    return pv;
   }
 
   // Reference point: the centre of the covered pixel nearest the box centre.
@@ -416,16 +543,28 @@ __device__ inline uint32_t preprocess_view(const GaussPtrs &gp, const KCfg &cfg,
   dst[R_RGB / 4] = make_float4(col[0], col[1], col[2], __uint_as_float(flags));
   w.cflags[(int64_t)v * cfg.n + g] = (uint8_t)(flags | kCflagVisible);
 
+  pv.finish = true;
+  pv.cull = cull;
+  if (cull) pv.rows = cull_setup(conic, rect, x0, x1, y0, y1, ixd, iyd, cl, lane, &pv.valid);
+  return pv;
+}
+
+// The rest of a visible (view, Gaussian) once the wave's cull masks are
+// known (cmask: this lane's): returns the instance count and writes the
+// tile rect; *packed receives tx0 | ty0 << 10 | width << 20 of a non-empty
+// rect and *mask_out the surviving tiles of the rect (0 = all).
+__device__ inline uint32_t preprocess_view_end(const Ws &w, int64_t vg, const ViewPending &pv,
+                                               unsigned long long cmask, uint32_t *packed,
+                                               unsigned long long *mask_out) {
+  uint32_t count = pv.count;
+  int4 rect = pv.rect;
   unsigned long long mask = 0ull;
-  if (cull) {
-    bool valid = false;
-    mask = cull_mask(conic, rect, cfg.tile_w, cfg.tile_h, x0, x1, y0, y1, ixd, iyd, &valid);
-    if (valid) {
-      const uint32_t kept = (uint32_t)__popcll(mask);
-      // every tile kept: no mask (the emit then skips the set-bit search)
-      if (kept == count) mask = 0ull;
-      count = kept;
-    }
+  if (pv.cull && pv.valid) {
+    mask = cmask;
+    const uint32_t kept = (uint32_t)__popcll(mask);
+    // every tile kept: no mask (the emit then skips the set-bit search)
+    if (kept == count) mask = 0ull;
+    count = kept;
   }
   if (count == 0) rect = make_int4(1, 1, 0, 0);
   w.rects[vg] = rect;
@@ -468,19 +607,27 @@ template <int DEG, bool MV, bool CULL>
 __global__ void __launch_bounds__(kPreThreads) k_preprocess(GaussPtrs gp, KCfg cfg, ViewSet vs,
                                                              Ws w) {
   __shared__ unsigned long long s_wsum[kPreThreads / 64];
+  __shared__ CullLds s_cull[CULL ? kPreThreads / 64 : 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t blk = blockIdx.x;
   int64_t g;
   const bool live = gaussian_at(w, cfg, blk * kPreThreads + tid, g);
   const int nviews = MV ? vs.n : 1;
   unsigned long long total = 0;
-  if (live) {
-    Activated a;
-    activate(gp, cfg, g, a);
-    for (int v = 0; v < nviews; ++v) {
-      uint32_t packed = 0;
+  Activated a;
+  if (live) activate(gp, cfg, g, a);
+  CullLds &cl = s_cull[CULL ? wave : 0];
+  for (int v = 0; v < nviews; ++v) {
+    ViewPending pv{make_int4(1, 1, 0, 0), 0u, false, false, false, 0u, 0u};
+    if (live) pv = preprocess_view<DEG, CULL>(gp, cfg, vs.v[v], w, v, g, a, cl, lane);
+    // (every lane of the wave takes part in the cull, live or not)
+    unsigned long long cmask = 0ull;
+    if constexpr (CULL)
+      cmask = wave_cull_rows(cl, pv.rows, pv.width, cfg.tile_w, cfg.tile_h, lane);
+    if (live) {
+      uint32_t c = 0, packed = 0;
       unsigned long long mk = 0ull;
-      const uint32_t c = preprocess_view<DEG, CULL>(gp, cfg, vs.v[v], w, v, g, a, &packed, &mk);
+      if (pv.finish) c = preprocess_view_end(w, (int64_t)v * cfg.n + g, pv, cmask, &packed, &mk);
       w.tslots[(int64_t)v * cfg.n + g] =
           c ? make_uint4(c, packed, (uint32_t)mk, (uint32_t)(mk >> 32)) : make_uint4(0u, 0u, 0u, 0u);
       total += c;
@@ -536,23 +683,6 @@ __global__ void __launch_bounds__(kTotScanThreads) k_preprocess_scan(Ws w, int64
     *w.total = carry;
     if (carry > (unsigned long long)w.capacity) atomicOr(&w.status[0], (uint32_t)ST_OVERFLOW);
   }
-}
-
-// Inclusive maximum over the lanes of a wave by DPP moves (shifts by 1, 2,
-// 4, 8 inside each row of 16 lanes, then the row ends broadcast to the rows
-// after them); lanes whose source is outside receive 0.
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ uint32_t dpp_max_step(uint32_t x) {
-  return max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROW_MASK, 0xf, false));
-}
-__device__ __forceinline__ uint32_t wave_incl_max(uint32_t x) {
-  x = dpp_max_step<0x111, 0xf>(x);
-  x = dpp_max_step<0x112, 0xf>(x);
-  x = dpp_max_step<0x114, 0xf>(x);
-  x = dpp_max_step<0x118, 0xf>(x);
-  x = dpp_max_step<0x142, 0xa>(x);
-  x = dpp_max_step<0x143, 0xc>(x);
-  return x;
 }
 
 // The instances of the workgroup's Gaussians (the same 256 positions as the
