@@ -282,9 +282,9 @@ __device__ __forceinline__ double conic_at(const Conic &c, double p, double q) {
 // The rows of a wave's Gaussians are tested by the whole wave: each lane
 // puts its Gaussian's ellipse extent in LDS (cull_setup), then the (lane,
 // tile row) pairs are dealt to the lanes in windows of 64 (wave_cull_rows).
-// One row per lane and Gaussian left most lanes idle: a wave's Gaussians
-// have ~2 tile rows on average and ~8 at most.
-struct CullExt {                  // one lane's ellipse extent (96 bytes)
+// With each lane looping over its own rows, most lanes sat idle: in a 1080p
+// frame a wave's Gaussians have ~2 tile rows on average and ~8 at most.
+struct CullExt {                  // one lane's ellipse extent (104 bytes)
   double A, B, C, Dpp, Epq, Fqq;  // the conic
   double idp;                     // 1 / Dpp
   double qmin, qmax;              // q extent of the ellipse
