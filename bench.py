@@ -277,6 +277,7 @@ def run_single(args):
         "candidate_pairs": pairs,
         "gaussian_pixels_per_s": sc.n * cam.width * cam.height / (ms_step * 1e-3),
         "candidate_pairs_per_s": pairs / (ms_step * 1e-3),
+        "passes": pass_split(stages, sc.n * cam.width * cam.height, pairs),
         "autotune": tune_rep,
     }
     if args.workload != "1080p" or args.forward_only:
@@ -296,6 +297,21 @@ def run_single(args):
     del params
     torch.cuda.empty_cache()
     return out, (sc, cam, st)
+
+
+def pass_split(stages, gauss_px, pairs):
+    """Forward and backward apart: the summed HIP-event times of their
+    stages per step (no loss kernels, no gaps between launches) and the
+    Gaussian x pixel and candidate-pair rates over them."""
+    split = {}
+    for name, ks in (("fwd", ("fill", "preprocess", "sort", "ranges", "raster_fwd")),
+                     ("bwd", ("raster_bwd", "preprocess_bwd"))):
+        t = sum(stages[k]["ms_per_step"] for k in ks if k in stages)
+        if t > 0:
+            split[name] = dict(ms=round(t, 4), stages=list(ks),
+                               gaussian_pixels_per_s=gauss_px / (t * 1e-3),
+                               candidate_pairs_per_s=pairs / (t * 1e-3))
+    return split
 
 
 def run_variants(args, params, sc, cam, st0, target, steps=10, warmup=3):
